@@ -1,0 +1,169 @@
+"""CPU FP64 oracle for the per-cell chemistry path -- TEST INFRASTRUCTURE.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never links or calls it, and it
+shares no code with the GPU path: the chemistry is a plain C program
+(``chem_oracle.c``) that interprets the ``.mech`` table at run time, and the
+surrogate oracle (``mlp_oracle.py``) is plain numpy.
+
+``build()`` compiles the C oracle into ``liboracle.so`` beside this file.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "chem_oracle.c")
+
+STATUS_OK, STATUS_MAXSTEPS, STATUS_NONFINITE, STATUS_H_UNDERFLOW = 0, 1, 2, 3
+
+
+def build() -> str:
+    """Compile the oracle (portable x86-64 code, no FP contraction)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", LIB_PATH + ".tmp", SRC_PATH, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P, D, I = C.c_void_p, C.c_double, C.c_int
+        L.or_mech_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+        L.or_mech_load.restype = I
+        L.or_mech_free.argtypes = [P]
+        L.or_mech_dims.argtypes = [P, C.POINTER(I), C.POINTER(I), C.POINTER(I)]
+        L.or_mech_species.argtypes = [P, P, P]
+        L.or_mech_stoich.argtypes = [P, P]
+        L.or_thermo.argtypes = [P, D, P, P, P]
+        L.or_rates.argtypes = [P, D, P, P, P, P, P]
+        L.or_rhs.argtypes = [P, D, P, P]
+        L.or_lsrk_coeffs.argtypes = [P, P, P]
+        L.or_integrate_cell.argtypes = [P, D, P, D, D, D, I, I, C.POINTER(D), C.POINTER(I),
+                                        C.POINTER(I), P, I, C.POINTER(I)]
+        L.or_integrate_cell.restype = I
+        L.or_integrate.argtypes = [P, P, C.c_int64, C.c_int64, D, D, D, I, I, I, P, P]
+        L.or_integrate.restype = I
+        L.or_integrate_linear.argtypes = [I, P, P, D, D, D, I, I, C.POINTER(D), C.POINTER(I),
+                                          C.POINTER(I), P, I, C.POINTER(I)]
+        L.or_integrate_linear.restype = I
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def lsrk_coeffs():
+    a, b, bh = np.zeros(4), np.zeros(5), np.zeros(5)
+    lib().or_lsrk_coeffs(_ptr(a), _ptr(b), _ptr(bh))
+    return a, b, bh
+
+
+class Mech:
+    """A parsed mechanism (table form) on the CPU."""
+
+    def __init__(self, path: str):
+        h = C.c_void_p()
+        rc = lib().or_mech_load(path.encode(), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"oracle: cannot parse {path} (line {rc})")
+        self._h = h
+        ne, ns, nr = C.c_int(), C.c_int(), C.c_int()
+        lib().or_mech_dims(h, C.byref(ne), C.byref(ns), C.byref(nr))
+        self.ne, self.ns, self.nr = ne.value, ns.value, nr.value
+        self.W = np.zeros(self.ns)
+        self.comp = np.zeros((self.ns, self.ne), dtype=np.int32)
+        lib().or_mech_species(h, _ptr(self.W), _ptr(self.comp))
+        self.nu = np.zeros((self.nr, self.ns))
+        lib().or_mech_stoich(h, _ptr(self.nu))
+
+    def __del__(self):
+        try:
+            lib().or_mech_free(self._h)
+        except Exception:
+            pass
+
+    def thermo(self, T: float):
+        cp, h, s = np.zeros(self.ns), np.zeros(self.ns), np.zeros(self.ns)
+        lib().or_thermo(self._h, float(T), _ptr(cp), _ptr(h), _ptr(s))
+        return cp, h, s
+
+    def rates(self, rho: float, u: np.ndarray):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        kf, kr, q, w = (np.zeros(self.nr), np.zeros(self.nr), np.zeros(self.nr),
+                        np.zeros(self.ns))
+        lib().or_rates(self._h, float(rho), _ptr(u), _ptr(kf), _ptr(kr), _ptr(q), _ptr(w))
+        return kf, kr, q, w
+
+    def rhs(self, rho: float, u: np.ndarray) -> np.ndarray:
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        f = np.zeros(self.ns + 1)
+        lib().or_rhs(self._h, float(rho), _ptr(u), _ptr(f))
+        return f
+
+    def integrate_cell(self, rho, u, dt, rtol=1e-8, atol=1e-10, max_steps=100000,
+                       fixed_steps=0, h0=0.0, trace_cap=0):
+        u = np.array(u, dtype=np.float64)
+        h = C.c_double(h0)
+        na, nr, tl = C.c_int(), C.c_int(), C.c_int()
+        tr = np.zeros(4 * max(trace_cap, 1)) if trace_cap else None
+        st = lib().or_integrate_cell(self._h, float(rho), _ptr(u), float(dt), float(rtol),
+                                     float(atol), int(max_steps), int(fixed_steps), C.byref(h),
+                                     C.byref(na), C.byref(nr),
+                                     _ptr(tr) if tr is not None else None, int(trace_cap),
+                                     C.byref(tl))
+        out = dict(u=u, status=st, h=h.value, nacc=na.value, nrej=nr.value)
+        if tr is not None:
+            out["trace"] = tr[: 4 * tl.value].reshape(-1, 4)
+        return out
+
+    def integrate(self, state: np.ndarray, dt: float, rtol=1e-8, atol=1e-10,
+                  max_steps=100000, fixed_steps=0, nthreads=None):
+        """In-place on an SoA block state[(N+3), n] (rows T, Y.., rho, h).
+
+        Returns (status[n], counts[2, n]) with counts = (n_acc, n_rej)."""
+        assert state.dtype == np.float64 and state.flags.c_contiguous
+        assert state.shape[0] == self.ns + 3
+        n = state.shape[1]
+        status = np.zeros(n, dtype=np.int32)
+        counts = np.zeros((2, n), dtype=np.int32)
+        if nthreads is None:
+            nthreads = os.cpu_count() or 1
+        lib().or_integrate(self._h, _ptr(state), n, n, float(dt), float(rtol), float(atol),
+                           int(max_steps), int(fixed_steps), int(nthreads), _ptr(status),
+                           _ptr(counts))
+        return status, counts
+
+
+def integrate_linear(A, u0, dt, rtol=1e-8, atol=1e-10, max_steps=100000, fixed_steps=0,
+                     h0=0.0, trace_cap=0):
+    """u' = A u through the oracle's own step/controller/driver."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    u = np.array(u0, dtype=np.float64)
+    h = C.c_double(h0)
+    na, nr, tl = C.c_int(), C.c_int(), C.c_int()
+    tr = np.zeros(4 * max(trace_cap, 1)) if trace_cap else None
+    st = lib().or_integrate_linear(n, _ptr(A), _ptr(u), float(dt), float(rtol), float(atol),
+                                   int(max_steps), int(fixed_steps), C.byref(h), C.byref(na),
+                                   C.byref(nr), _ptr(tr) if tr is not None else None,
+                                   int(trace_cap), C.byref(tl))
+    out = dict(u=u, status=st, h=h.value, nacc=na.value, nrej=nr.value)
+    if tr is not None:
+        out["trace"] = tr[: 4 * tl.value].reshape(-1, 4)
+    return out

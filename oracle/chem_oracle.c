@@ -1,0 +1,514 @@
+/*
+ * chem_oracle.c -- plain, slow, table-driven FP64 CPU oracle for per-cell
+ * chemistry integration.  TEST INFRASTRUCTURE ONLY: it exists so that the GPU
+ * path can be checked against something written directly from the paper.  It
+ * shares no code, header or table with the GPU library and must never be
+ * linked into it.
+ *
+ * What it computes (paper: Sec. 2.1.2 and Sec. 2.2.3):
+ *   - NASA 7-coefficient thermodynamics per species (Eq. 10's h_i, c_pi);
+ *   - mass-action molar production rates (Eq. 15-16), forward rate in
+ *     Arrhenius form, reverse rate from the equilibrium constant, and a
+ *     third-body concentration multiplying both directions when a reaction
+ *     lists collision efficiencies;
+ *   - the chemistry ODE of Eq. 20 with the species source of Eq. 14, written
+ *     for u = (T, Y_1..Y_N) at constant density and internal energy
+ *     (constant-volume adiabatic closure for dT/dt);
+ *   - one step of the two-register low-storage RK (Eq. 21) with the embedded
+ *     error register, and the WRMS step-size controller of Eq. 22;
+ *   - a per-cell driver over one flow time step.
+ *
+ * Readings where the paper is silent or garbled (each also listed in the
+ * design notes of the repository):
+ *   - scheme coefficients: Kennedy-Carpenter-Lewis RK4(3)5[2R+]C (the paper's
+ *     "fourth-order, five-stage, low-storage embedded" scheme, its ref. [37]);
+ *   - Eq. 22's h_min/h_max clamp is applied to the step factor: [0.2, 5];
+ *     exponent 1/4; the WRMS weights use |u| at the start of the step; the
+ *     mean runs over all N+1 components;
+ *   - accept iff err <= 1; NaN error => reject with factor 0.2; err == 0 =>
+ *     factor 5; the final step is clipped to end exactly at dt;
+ *   - NASA-7 range: T < Tmid uses the low range; no clamping outside the fit;
+ *   - the equilibrium constant uses the standard pressure given in the
+ *     mechanism file (1 atm) and R in cgs units.
+ *
+ * Units: cgs (mol/cm^3, g/cm^3, s); activation energy in J/mol.
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared -o liboracle.so chem_oracle.c -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_R_J 8.31446261815324       /* J/(mol K) */
+#define OR_R_CGS 8.31446261815324e7   /* erg/(mol K) */
+
+enum { OR_OK = 0, OR_MAXSTEPS = 1, OR_NONFINITE = 2, OR_H_UNDERFLOW = 3 };
+
+typedef struct {
+    int n_reac, n_prod;
+    int reac_sp[8], reac_nu[8];
+    int prod_sp[8], prod_nu[8];
+    double A, b, Ea;
+    int third_body;
+    double *eff; /* [ns] */
+} or_reaction;
+
+typedef struct {
+    int ne, ns, nr;
+    double pstd;
+    char (*sp_name)[32];
+    double *W;       /* [ns] */
+    int *comp;       /* [ns*ne] */
+    double *Tmid;    /* [ns] */
+    double *lo;      /* [ns*7] */
+    double *hi;      /* [ns*7] */
+    or_reaction *rx; /* [nr] */
+} or_mech;
+
+/* ------------------------------------------------------------------ parser */
+static char *next_tok(char **p) {
+    char *s = *p;
+    while (*s == ' ' || *s == '\t') s++;
+    if (*s == 0 || *s == '\n') { *p = s; return NULL; }
+    char *t = s;
+    while (*s && *s != ' ' && *s != '\t' && *s != '\n') s++;
+    if (*s) { *s = 0; s++; }
+    *p = s;
+    return t;
+}
+
+static int read_line(FILE *f, char *buf, int len) {
+    for (;;) {
+        if (!fgets(buf, len, f)) return 0;
+        char *s = buf;
+        while (*s == ' ' || *s == '\t') s++;
+        if (*s == '#' || *s == '\n' || *s == 0) continue;
+        return 1;
+    }
+}
+
+static int species_index(const or_mech *m, const char *name) {
+    for (int k = 0; k < m->ns; k++)
+        if (strcmp(m->sp_name[k], name) == 0) return k;
+    return -1;
+}
+
+void or_mech_free(or_mech *m) {
+    if (!m) return;
+    if (m->rx)
+        for (int j = 0; j < m->nr; j++) free(m->rx[j].eff);
+    free(m->rx); free(m->sp_name); free(m->W); free(m->comp);
+    free(m->Tmid); free(m->lo); free(m->hi); free(m);
+}
+
+/* Returns 0 on success, else the (1-based) offending line-count; *out set on success. */
+int or_mech_load(const char *path, or_mech **out) {
+    FILE *f = fopen(path, "r");
+    if (!f) return -1;
+    char buf[65536];
+    int line = 0;
+    or_mech *m = calloc(1, sizeof(or_mech));
+#define FAIL() do { fclose(f); or_mech_free(m); return line > 0 ? line : 1; } while (0)
+    char *p, *t;
+    if (!read_line(f, buf, sizeof buf) || strncmp(buf, "MECH 1", 6) != 0) FAIL();
+    line++;
+    for (;;) {
+        if (!read_line(f, buf, sizeof buf)) FAIL();
+        line++;
+        p = buf;
+        t = next_tok(&p);
+        if (!t) FAIL();
+        if (strcmp(t, "name") == 0) continue;
+        if (strcmp(t, "pstd") == 0) { m->pstd = strtod(next_tok(&p), NULL); continue; }
+        if (strcmp(t, "elements") == 0) {
+            m->ne = atoi(next_tok(&p));
+            for (int e = 0; e < m->ne; e++) { if (!read_line(f, buf, sizeof buf)) FAIL(); line++; }
+            continue;
+        }
+        if (strcmp(t, "species") == 0) {
+            m->ns = atoi(next_tok(&p));
+            int ns = m->ns;
+            m->sp_name = calloc(ns, 32);
+            m->W = calloc(ns, sizeof(double));
+            m->comp = calloc((size_t)ns * (m->ne > 0 ? m->ne : 1), sizeof(int));
+            m->Tmid = calloc(ns, sizeof(double));
+            m->lo = calloc((size_t)ns * 7, sizeof(double));
+            m->hi = calloc((size_t)ns * 7, sizeof(double));
+            for (int k = 0; k < ns; k++) {
+                if (!read_line(f, buf, sizeof buf)) FAIL();
+                line++;
+                p = buf;
+                t = next_tok(&p); if (!t) FAIL();
+                strncpy(m->sp_name[k], t, 31);
+                t = next_tok(&p); if (!t) FAIL(); m->W[k] = strtod(t, NULL);
+                for (int e = 0; e < m->ne; e++) { t = next_tok(&p); if (!t) FAIL(); m->comp[k * m->ne + e] = atoi(t); }
+                t = next_tok(&p); if (!t) FAIL();                         /* Tlow */
+                t = next_tok(&p); if (!t) FAIL(); m->Tmid[k] = strtod(t, NULL);
+                t = next_tok(&p); if (!t) FAIL();                         /* Thigh */
+                for (int i = 0; i < 7; i++) { t = next_tok(&p); if (!t) FAIL(); m->lo[k * 7 + i] = strtod(t, NULL); }
+                for (int i = 0; i < 7; i++) { t = next_tok(&p); if (!t) FAIL(); m->hi[k * 7 + i] = strtod(t, NULL); }
+            }
+            continue;
+        }
+        if (strcmp(t, "reactions") == 0) {
+            m->nr = atoi(next_tok(&p));
+            m->rx = calloc(m->nr, sizeof(or_reaction));
+            for (int j = 0; j < m->nr; j++) {
+                or_reaction *r = &m->rx[j];
+                if (!read_line(f, buf, sizeof buf)) FAIL();
+                line++;
+                p = buf;
+                t = next_tok(&p); if (!t || strcmp(t, "reaction") != 0) FAIL();
+                r->A = strtod(next_tok(&p), NULL);
+                r->b = strtod(next_tok(&p), NULL);
+                r->Ea = strtod(next_tok(&p), NULL);
+                r->third_body = atoi(next_tok(&p));
+                for (int side = 0; side < 2; side++) {
+                    if (!read_line(f, buf, sizeof buf)) FAIL();
+                    line++;
+                    p = buf;
+                    t = next_tok(&p);
+                    if (!t || strcmp(t, side == 0 ? "reactants" : "products") != 0) FAIL();
+                    int n = atoi(next_tok(&p));
+                    if (n < 1 || n > 8) FAIL();
+                    for (int i = 0; i < n; i++) {
+                        char *nm = next_tok(&p);
+                        char *nu = next_tok(&p);
+                        if (!nm || !nu) FAIL();
+                        int k = species_index(m, nm);
+                        if (k < 0) FAIL();
+                        if (side == 0) { r->reac_sp[i] = k; r->reac_nu[i] = atoi(nu); }
+                        else { r->prod_sp[i] = k; r->prod_nu[i] = atoi(nu); }
+                    }
+                    if (side == 0) r->n_reac = n; else r->n_prod = n;
+                }
+                if (r->third_body) {
+                    if (!read_line(f, buf, sizeof buf)) FAIL();
+                    line++;
+                    p = buf;
+                    t = next_tok(&p); if (!t || strcmp(t, "efficiencies") != 0) FAIL();
+                    r->eff = calloc(m->ns, sizeof(double));
+                    for (int k = 0; k < m->ns; k++) { t = next_tok(&p); if (!t) FAIL(); r->eff[k] = strtod(t, NULL); }
+                }
+            }
+            continue;
+        }
+        if (strcmp(t, "end") == 0) break;
+        FAIL();
+    }
+#undef FAIL
+    fclose(f);
+    *out = m;
+    return 0;
+}
+
+void or_mech_dims(const or_mech *m, int *ne, int *ns, int *nr) {
+    *ne = m->ne; *ns = m->ns; *nr = m->nr;
+}
+
+void or_mech_species(const or_mech *m, double *W, int *comp) {
+    for (int k = 0; k < m->ns; k++) {
+        W[k] = m->W[k];
+        for (int e = 0; e < m->ne; e++) comp[k * m->ne + e] = m->comp[k * m->ne + e];
+    }
+}
+
+/* Net stoichiometric matrix nu[j*ns + k] = nu''_jk - nu'_jk. */
+void or_mech_stoich(const or_mech *m, double *nu) {
+    memset(nu, 0, sizeof(double) * (size_t)m->nr * m->ns);
+    for (int j = 0; j < m->nr; j++) {
+        const or_reaction *r = &m->rx[j];
+        for (int i = 0; i < r->n_reac; i++) nu[j * m->ns + r->reac_sp[i]] -= r->reac_nu[i];
+        for (int i = 0; i < r->n_prod; i++) nu[j * m->ns + r->prod_sp[i]] += r->prod_nu[i];
+    }
+}
+
+/* ------------------------------------------------------------------ thermo */
+/* NASA-7 (Eq. 10's fits): cp/R, h/(RT), s/R for every species at T. */
+void or_thermo(const or_mech *m, double T, double *cp_R, double *h_RT, double *s_R) {
+    for (int k = 0; k < m->ns; k++) {
+        const double *a = (T < m->Tmid[k]) ? &m->lo[k * 7] : &m->hi[k * 7];
+        cp_R[k] = a[0] + a[1] * T + a[2] * T * T + a[3] * T * T * T + a[4] * T * T * T * T;
+        h_RT[k] = a[0] + a[1] * T / 2.0 + a[2] * T * T / 3.0 + a[3] * T * T * T / 4.0
+                + a[4] * T * T * T * T / 5.0 + a[5] / T;
+        s_R[k] = a[0] * log(T) + a[1] * T + a[2] * T * T / 2.0 + a[3] * T * T * T / 3.0
+               + a[4] * T * T * T * T / 4.0 + a[6];
+    }
+}
+
+/* ------------------------------------------------------------------- rates */
+/* Eq. 16 and the Arrhenius / equilibrium-constant rates.  u = (T, Y_1..Y_N).
+ * Outputs per reaction (kf, kr, q) and per species wdot [mol/(cm^3 s)]; any
+ * output pointer may be NULL. */
+void or_rates(const or_mech *m, double rho, const double *u,
+              double *kf_out, double *kr_out, double *q_out, double *wdot) {
+    int ns = m->ns;
+    double T = u[0];
+    double *cp = malloc(sizeof(double) * ns), *h = malloc(sizeof(double) * ns);
+    double *s = malloc(sizeof(double) * ns), *c = malloc(sizeof(double) * ns);
+    or_thermo(m, T, cp, h, s);
+    for (int k = 0; k < ns; k++) c[k] = rho * u[1 + k] / m->W[k];
+    if (wdot) for (int k = 0; k < ns; k++) wdot[k] = 0.0;
+    for (int j = 0; j < m->nr; j++) {
+        const or_reaction *r = &m->rx[j];
+        double kf = r->A * pow(T, r->b) * exp(-r->Ea / (OR_R_J * T));
+        /* Kc = exp(-sum_k nu_jk g_k/RT) * (pstd/(R T))^(sum_k nu_jk) */
+        double dG = 0.0;
+        int dnu = 0;
+        for (int i = 0; i < r->n_prod; i++) {
+            int k = r->prod_sp[i];
+            dG += r->prod_nu[i] * (h[k] - s[k]);
+            dnu += r->prod_nu[i];
+        }
+        for (int i = 0; i < r->n_reac; i++) {
+            int k = r->reac_sp[i];
+            dG -= r->reac_nu[i] * (h[k] - s[k]);
+            dnu -= r->reac_nu[i];
+        }
+        double Kc = exp(-dG) * pow(m->pstd / (OR_R_CGS * T), (double)dnu);
+        double kr = kf / Kc;
+        double fwd = kf, rev = kr;
+        for (int i = 0; i < r->n_reac; i++)
+            for (int n = 0; n < r->reac_nu[i]; n++) fwd *= c[r->reac_sp[i]];
+        for (int i = 0; i < r->n_prod; i++)
+            for (int n = 0; n < r->prod_nu[i]; n++) rev *= c[r->prod_sp[i]];
+        double M = 1.0;
+        if (r->third_body) {
+            M = 0.0;
+            for (int k = 0; k < ns; k++) M += r->eff[k] * c[k];
+        }
+        double q = M * (fwd - rev);
+        if (kf_out) kf_out[j] = kf;
+        if (kr_out) kr_out[j] = kr;
+        if (q_out) q_out[j] = q;
+        if (wdot) {
+            for (int i = 0; i < r->n_reac; i++) wdot[r->reac_sp[i]] -= r->reac_nu[i] * q;
+            for (int i = 0; i < r->n_prod; i++) wdot[r->prod_sp[i]] += r->prod_nu[i] * q;
+        }
+    }
+    free(cp); free(h); free(s); free(c);
+}
+
+/* Right-hand side f(u) of the chemistry ODE (Eq. 14, Eq. 20) for u = (T, Y):
+ *   dY_k/dt = W_k wdot_k / rho
+ *   dT/dt   = -T * sum_k (h_k/RT - 1) wdot_k / sum_k c_k (cp_k/R - 1)
+ * (constant density, constant internal energy). */
+void or_rhs(const or_mech *m, double rho, const double *u, double *f) {
+    int ns = m->ns;
+    double T = u[0];
+    double *cp = malloc(sizeof(double) * ns), *h = malloc(sizeof(double) * ns);
+    double *s = malloc(sizeof(double) * ns), *w = malloc(sizeof(double) * ns);
+    or_thermo(m, T, cp, h, s);
+    or_rates(m, rho, u, NULL, NULL, NULL, w);
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < ns; k++) {
+        double c = rho * u[1 + k] / m->W[k];
+        num += (h[k] - 1.0) * w[k];
+        den += c * (cp[k] - 1.0);
+        f[1 + k] = m->W[k] * w[k] / rho;
+    }
+    f[0] = -T * num / den;
+    free(cp); free(h); free(s); free(w);
+}
+
+/* -------------------------------------------------------- LSRK coefficients */
+/* Kennedy, Carpenter & Lewis (2000) RK4(3)5[2R+]C: subdiagonal a_{i+1,i},
+ * weights b_i and embedded weights bhat_i, as exact rationals. */
+static const double LS_A_NUM[4] = {970286171893.0, 6584761158862.0, 2251764453980.0, 26877169314380.0};
+static const double LS_A_DEN[4] = {4311952581923.0, 12103376702013.0, 15575788980749.0, 34165994151039.0};
+static const double LS_B_NUM[5] = {1153189308089.0, 1772645290293.0, -1672844663538.0, 2114624349019.0, 5198255086312.0};
+static const double LS_B_DEN[5] = {22510343858157.0, 4653164025191.0, 4480602732383.0, 3568978502595.0, 14908931495163.0};
+static const double LS_BH_NUM[5] = {1016888040809.0, 11231460423587.0, -1563879915014.0, 606302364029.0, 1097981568119.0};
+static const double LS_BH_DEN[5] = {7410784769900.0, 58533540763752.0, 6823010717585.0, 971179775848.0, 3980877426909.0};
+
+void or_lsrk_coeffs(double *a, double *b, double *bh) {
+    for (int i = 0; i < 4; i++) a[i] = LS_A_NUM[i] / LS_A_DEN[i];
+    for (int i = 0; i < 5; i++) { b[i] = LS_B_NUM[i] / LS_B_DEN[i]; bh[i] = LS_BH_NUM[i] / LS_BH_DEN[i]; }
+}
+
+/* ----------------------------------------------------------- generic core */
+typedef void (*or_rhs_fn)(const void *ctx, const double *u, double *f);
+
+/* One step of Eq. 21 (two registers U, X) plus the error register E:
+ *   U <- X + a_{i+1,i} h F_i ;  X <- U + (b_i - a_{i+1,i}) h F_i ;  E += (b_i - bhat_i) h F_i
+ * with F_i = f(U), for i = 1..5 (the last stage adds b_5 h F_5 to X). */
+static void lsrk_step(or_rhs_fn f, const void *ctx, int n, double h, const double *un,
+                      double *unew, double *err_vec, double *U, double *F) {
+    double a[4], b[5], bh[5];
+    or_lsrk_coeffs(a, b, bh);
+    double *X = unew;
+    for (int i = 0; i < n; i++) { X[i] = un[i]; U[i] = un[i]; err_vec[i] = 0.0; }
+    for (int s = 0; s < 5; s++) {
+        f(ctx, U, F);
+        for (int i = 0; i < n; i++) err_vec[i] += (b[s] - bh[s]) * h * F[i];
+        if (s < 4) {
+            for (int i = 0; i < n; i++) {
+                U[i] = X[i] + a[s] * h * F[i];
+                X[i] = U[i] + (b[s] - a[s]) * h * F[i];
+            }
+        } else {
+            for (int i = 0; i < n; i++) X[i] = X[i] + b[s] * h * F[i];
+        }
+    }
+}
+
+/* Eq. 22: WRMS norm of the error with weights from the state at step start. */
+static double wrms(int n, const double *e, const double *un, double rtol, double atol) {
+    double sum = 0.0;
+    for (int i = 0; i < n; i++) {
+        double w = e[i] / (rtol * fabs(un[i]) + atol);
+        sum += w * w;
+    }
+    return sqrt(sum / n);
+}
+
+/* Eq. 22's step factor with the [1/5, 5] clamp and beta = 0.9. */
+static double step_factor(double err) {
+    if (err != err) return 0.2;
+    if (err == 0.0) return 5.0;
+    double fac = 0.9 * pow(err, -0.25);
+    if (fac < 0.2) fac = 0.2;
+    if (fac > 5.0) fac = 5.0;
+    return fac;
+}
+
+typedef struct { double t, h, err; int accepted; } or_trace;
+
+/* Integrate u over [0, dt]; returns a status code.  h_inout: initial step
+ * hint (<= 0 => dt) and, on return, the proposed next step. */
+static int drive(or_rhs_fn f, const void *ctx, int n, double *u, double dt, double rtol,
+                 double atol, int max_steps, int fixed_steps, double *h_inout, int *nacc,
+                 int *nrej, or_trace *trace, int trace_cap, int *trace_len) {
+    double *unew = malloc(sizeof(double) * n), *e = malloc(sizeof(double) * n);
+    double *U = malloc(sizeof(double) * n), *F = malloc(sizeof(double) * n);
+    int status = OR_OK;
+    *nacc = 0; *nrej = 0;
+    if (trace_len) *trace_len = 0;
+    if (fixed_steps > 0) {
+        double h = dt / fixed_steps;
+        for (int s = 0; s < fixed_steps; s++) {
+            lsrk_step(f, ctx, n, h, u, unew, e, U, F);
+            for (int i = 0; i < n; i++) u[i] = unew[i];
+            (*nacc)++;
+        }
+        *h_inout = h;
+        free(unew); free(e); free(U); free(F);
+        return OR_OK;
+    }
+    double t = 0.0;
+    double h = (*h_inout > 0.0 && *h_inout < dt) ? *h_inout : dt;
+    for (;;) {
+        int last = 0;
+        if (h >= dt - t) { h = dt - t; last = 1; }
+        lsrk_step(f, ctx, n, h, u, unew, e, U, F);
+        double err = wrms(n, e, u, rtol, atol);
+        double fac = step_factor(err);
+        int ok = (err <= 1.0);
+        if (trace && *trace_len < trace_cap) {
+            trace[*trace_len].t = t; trace[*trace_len].h = h;
+            trace[*trace_len].err = err; trace[*trace_len].accepted = ok;
+            (*trace_len)++;
+        }
+        if (ok) {
+            for (int i = 0; i < n; i++) u[i] = unew[i];
+            (*nacc)++;
+            if (last) { h = h * fac; break; }
+            t = t + h;
+        } else {
+            (*nrej)++;
+        }
+        h = h * fac;
+        if (*nacc + *nrej >= max_steps) { status = OR_MAXSTEPS; break; }
+        if (h < 1e-14 * dt) { status = OR_H_UNDERFLOW; break; }
+    }
+    *h_inout = h;
+    free(unew); free(e); free(U); free(F);
+    return status;
+}
+
+/* ------------------------------------------------------ chemistry driver */
+typedef struct { const or_mech *m; double rho; } chem_ctx;
+
+static void chem_rhs_cb(const void *ctx, const double *u, double *f) {
+    const chem_ctx *c = ctx;
+    or_rhs(c->m, c->rho, u, f);
+}
+
+/* One cell: u (N+1) in/out.  Returns status. */
+int or_integrate_cell(const or_mech *m, double rho, double *u, double dt, double rtol,
+                      double atol, int max_steps, int fixed_steps, double *h_inout,
+                      int *nacc, int *nrej, double *trace_out, int trace_cap, int *trace_len) {
+    int n = m->ns + 1;
+    for (int i = 0; i < n; i++) if (!isfinite(u[i])) { *nacc = *nrej = 0; return OR_NONFINITE; }
+    if (!isfinite(rho)) { *nacc = *nrej = 0; return OR_NONFINITE; }
+    chem_ctx ctx = {m, rho};
+    or_trace *tr = trace_out ? malloc(sizeof(or_trace) * (trace_cap > 0 ? trace_cap : 1)) : NULL;
+    int st = drive(chem_rhs_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps, h_inout,
+                   nacc, nrej, tr, trace_cap, trace_len);
+    if (tr) {
+        for (int i = 0; i < *trace_len; i++) {
+            trace_out[4 * i + 0] = tr[i].t; trace_out[4 * i + 1] = tr[i].h;
+            trace_out[4 * i + 2] = tr[i].err; trace_out[4 * i + 3] = tr[i].accepted;
+        }
+        free(tr);
+    }
+    return st;
+}
+
+/* All cells of an SoA state block: state[v*ld + i], rows v = 0 T, 1..N Y_k,
+ * N+1 rho (read only), N+2 h (in: step hint, <= 0 => dt; out: next step).
+ * counts (may be NULL) receives n_acc in [i] and n_rej in [n + i]. */
+int or_integrate(const or_mech *m, double *state, int64_t ld, int64_t n, double dt,
+                 double rtol, double atol, int max_steps, int fixed_steps, int nthreads,
+                 int32_t *status, int32_t *counts) {
+    int N = m->ns;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+    for (int64_t i = 0; i < n; i++) {
+        double u[1 + 64];
+        for (int v = 0; v <= N; v++) u[v] = state[v * ld + i];
+        double rho = state[(N + 1) * ld + i];
+        double h = state[(N + 2) * ld + i];
+        int na = 0, nr = 0;
+        int st = or_integrate_cell(m, rho, u, dt, rtol, atol, max_steps, fixed_steps, &h, &na, &nr,
+                                   NULL, 0, NULL);
+        if (st != OR_NONFINITE) {
+            for (int v = 0; v <= N; v++) state[v * ld + i] = u[v];
+            state[(N + 2) * ld + i] = h;
+        }
+        if (status) status[i] = st;
+        if (counts) { counts[i] = na; counts[n + i] = nr; }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------- linear test problems */
+typedef struct { int n; const double *A; } lin_ctx;
+
+static void lin_rhs_cb(const void *ctx, const double *u, double *f) {
+    const lin_ctx *c = ctx;
+    for (int i = 0; i < c->n; i++) {
+        double s = 0.0;
+        for (int j = 0; j < c->n; j++) s += c->A[i * c->n + j] * u[j];
+        f[i] = s;
+    }
+}
+
+/* u' = A u with the same step, controller and driver as the chemistry path. */
+int or_integrate_linear(int n, const double *A, double *u, double dt, double rtol, double atol,
+                        int max_steps, int fixed_steps, double *h_inout, int *nacc, int *nrej,
+                        double *trace_out, int trace_cap, int *trace_len) {
+    lin_ctx ctx = {n, A};
+    or_trace *tr = trace_out ? malloc(sizeof(or_trace) * (trace_cap > 0 ? trace_cap : 1)) : NULL;
+    int st = drive(lin_rhs_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps, h_inout, nacc,
+                   nrej, tr, trace_cap, trace_len);
+    if (tr) {
+        for (int i = 0; i < *trace_len; i++) {
+            trace_out[4 * i + 0] = tr[i].t; trace_out[4 * i + 1] = tr[i].h;
+            trace_out[4 * i + 2] = tr[i].err; trace_out[4 * i + 3] = tr[i].accepted;
+        }
+        free(tr);
+    }
+    return st;
+}
