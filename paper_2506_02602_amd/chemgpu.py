@@ -1,0 +1,135 @@
+"""Thin ctypes binding of ``libchemgpu.so`` (argument marshalling only).
+
+Every function forwards to the C entry point of the same name in
+``include/chemgpu.h``; device buffers are torch tensors on the GPU (their
+``data_ptr()`` is passed through) and the stream is torch's current HIP stream
+unless one is given.  There is no fallback: if the built library is missing
+the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libchemgpu.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+
+# torch ships its own HIP runtime under the same SONAME (libamdhip64.so.7);
+# loading torch first makes the library bind to that copy, so the process
+# holds one runtime and torch's device memory and streams are usable here.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+CHEM_OK = 0
+CELL_OK, CELL_MAXSTEPS, CELL_NONFINITE, CELL_H_UNDERFLOW = 0, 1, 2, 3
+
+
+class chem_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
+                ("chunk_steps", C.c_int32), ("block_size", C.c_int32),
+                ("fixed_steps", C.c_int32)]
+
+
+class ChemError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib.chem_last_error().decode()
+        super().__init__(f"{where}: {_lib.chem_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+_P = C.c_void_p
+_lib.chem_strerror.argtypes = [C.c_int]
+_lib.chem_strerror.restype = C.c_char_p
+_lib.chem_last_error.argtypes = []
+_lib.chem_last_error.restype = C.c_char_p
+_lib.chem_mech_load.argtypes = [C.c_char_p, C.POINTER(_P)]
+_lib.chem_mech_load.restype = C.c_int
+_lib.chem_mech_query.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_uint64)]
+_lib.chem_mech_query.restype = C.c_int
+_lib.chem_mech_free.argtypes = [_P]
+_lib.chem_mech_free.restype = None
+_lib.chem_workspace_reserve.argtypes = [_P, C.c_int64]
+_lib.chem_workspace_reserve.restype = C.c_int
+_lib.chem_integrate.argtypes = [_P, _P, C.c_int64, C.c_int64, C.c_double,
+                                C.POINTER(chem_opts), _P, _P, _P]
+_lib.chem_integrate.restype = C.c_int
+
+
+def _check(rc, where):
+    if rc != CHEM_OK:
+        raise ChemError(rc, where)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def make_opts(rtol=0.0, atol=0.0, max_steps=0, chunk_steps=0, block_size=0, fixed_steps=0):
+    return chem_opts(rtol, atol, max_steps, chunk_steps, block_size, fixed_steps)
+
+
+class Mechanism:
+    """Owns a ``chem_mech`` handle."""
+
+    def __init__(self, path: str):
+        h = _P()
+        _check(_lib.chem_mech_load(path.encode(), C.byref(h)), "chem_mech_load")
+        self.handle = h
+        ns, nr, hsh = C.c_int32(), C.c_int32(), C.c_uint64()
+        _check(_lib.chem_mech_query(h, C.byref(ns), C.byref(nr), C.byref(hsh)), "chem_mech_query")
+        self.n_species, self.n_reactions, self.hash = ns.value, nr.value, hsh.value
+        self.path = path
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.chem_mech_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chem_mech_load(path: str) -> Mechanism:
+    return Mechanism(path)
+
+
+def chem_workspace_reserve(mech: Mechanism, max_cells: int) -> None:
+    _check(_lib.chem_workspace_reserve(mech.handle, int(max_cells)), "chem_workspace_reserve")
+
+
+def chem_integrate(mech: Mechanism, state, dt: float, opts: chem_opts | None = None,
+                   stream=None, status=None, counts=None, n_cells=None) -> None:
+    """state: float64 CUDA tensor [N+3, ld] (rows T, Y.., rho, h), updated in place."""
+    ld = state.shape[1]
+    n = ld if n_cells is None else int(n_cells)
+    assert state.dtype.itemsize == 8 and state.is_contiguous() and state.shape[0] == mech.n_species + 3
+    if status is not None:
+        assert status.numel() >= n and status.element_size() == 4
+    if counts is not None:
+        assert counts.numel() >= 2 * n and counts.element_size() == 4
+    o = opts if opts is not None else make_opts()
+    _check(_lib.chem_integrate(mech.handle, _ptr(state), ld, n, float(dt), C.byref(o),
+                               _stream(stream), _ptr(status), _ptr(counts)), "chem_integrate")
+
+
+def exported_symbols():
+    """Names declared in include/chemgpu.h that this library must export."""
+    return ["chem_mech_load", "chem_mech_query", "chem_mech_free", "chem_workspace_reserve",
+            "chem_integrate", "chem_strerror", "chem_last_error"]

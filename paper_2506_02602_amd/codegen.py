@@ -1,0 +1,326 @@
+"""Build-time code generator: ``.mech`` text -> fully unrolled FP64 HIP RHS.
+
+For one mechanism it emits a struct with the species count, the content hash
+of the file (FNV-1a 64 over its bytes, the key ``chem_mech_load`` binds by) and
+a ``__device__`` right-hand side of the chemistry ODE (paper Eq. 20 with the
+source of Eq. 14-16) in which every stoichiometric coefficient, Arrhenius
+parameter and NASA-7 coefficient is a literal:
+
+* thermo (Eq. 10 fits): per species cp/R, h/RT and g/RT = h/RT - s/R in Horner
+  form, with a wave-coherent branch on T < Tmid (one branch per distinct Tmid);
+* forward rate k_f = exp(ln A + b ln T - Ea/(R T)), reverse rate
+  k_r = k_f / K_c computed as exp(ln k_f + sum_k nu_k g_k/RT - dnu ln(P/(R T)));
+* progress q_j = [M]_j (k_f prod c^nu' - k_r prod c^nu''), integer powers as
+  products; production rates accumulated straight into N registers;
+* dY_k/dt = W_k wdot_k / rho and the constant-volume adiabatic dT/dt.
+
+This parser is the GPU side's own; it shares nothing with the CPU oracle.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+R_J = 8.31446261815324
+R_CGS = 8.31446261815324e7
+
+
+def fnv1a64(data: bytes) -> int:
+    h = 0xCBF29CE484222325
+    for b in data:
+        h ^= b
+        h = (h * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def parse(path: str) -> dict:
+    raw = open(path, "rb").read()
+    lines = [ln.strip() for ln in raw.decode().splitlines()]
+    lines = [ln for ln in lines if ln and not ln.startswith("#")]
+    if not lines or lines[0] != "MECH 1":
+        raise ValueError(f"{path}: not a MECH 1 file")
+    m = {"hash": fnv1a64(raw), "name": "mech", "pstd": 1.01325e6, "elements": [],
+         "species": [], "reactions": []}
+    i = 1
+    while i < len(lines):
+        tok = lines[i].split()
+        key = tok[0]
+        if key == "name":
+            m["name"] = tok[1]
+            i += 1
+        elif key == "pstd":
+            m["pstd"] = float(tok[1])
+            i += 1
+        elif key == "elements":
+            ne = int(tok[1])
+            m["elements"] = [lines[i + 1 + e].split()[0] for e in range(ne)]
+            i += 1 + ne
+        elif key == "species":
+            ns = int(tok[1])
+            ne = len(m["elements"])
+            for k in range(ns):
+                t = lines[i + 1 + k].split()
+                vals = [float(x) for x in t[2 + ne:]]
+                m["species"].append(dict(name=t[0], W=float(t[1]), Tmid=vals[1],
+                                         lo=vals[3:10], hi=vals[10:17]))
+            i += 1 + ns
+        elif key == "reactions":
+            nr = int(tok[1])
+            names = [s["name"] for s in m["species"]]
+            i += 1
+            for _ in range(nr):
+                t = lines[i].split()
+                rx = dict(A=float(t[1]), b=float(t[2]), Ea=float(t[3]), tb=int(t[4]) == 1,
+                          reac={}, prod={}, eff=None)
+                for side, key2 in ((lines[i + 1], "reac"), (lines[i + 2], "prod")):
+                    st = side.split()
+                    n = int(st[1])
+                    for q in range(n):
+                        rx[key2][names.index(st[2 + 2 * q])] = int(st[3 + 2 * q])
+                i += 3
+                if rx["tb"]:
+                    rx["eff"] = [float(x) for x in lines[i].split()[1:]]
+                    i += 1
+                m["reactions"].append(rx)
+        elif key == "end":
+            break
+        else:
+            raise ValueError(f"{path}: unexpected record {key}")
+    return m
+
+
+def lit(x: float) -> str:
+    """A C double literal that round-trips exactly."""
+    if x == 0.0:
+        return "0.0"
+    r = repr(float(x))
+    if "e" not in r and "." not in r and "inf" not in r and "nan" not in r:
+        r += ".0"
+    return r
+
+
+def _horner(coefs, var):
+    """coefs[0] + var*(coefs[1] + var*(...)) as a C expression."""
+    expr = lit(coefs[-1])
+    for c in reversed(coefs[:-1]):
+        expr = f"{lit(c)} + {var} * ({expr})"
+    return expr
+
+
+def _thermo_block(species, idx, rng, suffix="", den="den"):
+    out = []
+    for k in idx:
+        a = species[k][rng]
+        # h/RT = a1 + a2 T/2 + a3 T^2/3 + a4 T^3/4 + a5 T^4/5 + a6/T
+        h = _horner([a[0], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5], "T")
+        # g/RT = h/RT - s/R = a1 (1 - ln T) - (a2 T/2 + a3 T^2/6 + a4 T^3/12 + a5 T^4/20) + a6/T - a7
+        gp = _horner([a[1] / 2, a[2] / 6, a[3] / 12, a[4] / 20], "T")
+        # c_k (cp_k/R - 1), cp/R = a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4
+        out.append(f"    {den} += c{k} * ({_horner([a[0] - 1.0] + list(a[1:5]), 'T')});")
+        decl = "const double " if suffix else ""
+        out.append(f"    {decl}h{k}{suffix} = {h} + {lit(a[5])} * invT;")
+        out.append(f"    {decl}g{k}{suffix} = {lit(a[0])} * omlnT - T * ({gp}) + {lit(a[5])} * invT - {lit(a[6])};")
+    return out
+
+
+def _thermo(species):
+    """Range selection made wave-uniform: waves whose lanes all sit in one
+    NASA-7 range evaluate that range with literal coefficients; a wave that
+    straddles T_mid evaluates both ranges and selects per lane."""
+    groups: dict = {}
+    for k, s in enumerate(species):
+        groups.setdefault(s["Tmid"], []).append(k)
+    L = []
+    for gi, (tm, idx) in enumerate(groups.items()):
+        L.append(f"    const bool lo{gi} = T < {lit(tm)};")
+        L.append(f"    if (__all(lo{gi})) {{")
+        L += ["  " + x for x in _thermo_block(species, idx, "lo")]
+        L.append(f"    }} else if (!__any(lo{gi})) {{")
+        L += ["  " + x for x in _thermo_block(species, idx, "hi")]
+        L.append("    } else {")
+        L.append("      double dlo = 0.0, dhi = 0.0;")
+        for k in idx:
+            L.append("      {")
+            L += ["    " + x for x in _thermo_block(species, [k], "lo", "_l", "dlo")]
+            L += ["    " + x for x in _thermo_block(species, [k], "hi", "_h", "dhi")]
+            L.append(f"        h{k} = lo{gi} ? h{k}_l : h{k}_h;")
+            L.append(f"        g{k} = lo{gi} ? g{k}_l : g{k}_h;")
+            L.append("      }")
+        L.append(f"      den += lo{gi} ? dlo : dhi;")
+        L.append("    }")
+    return L
+
+
+def _prod_expr(coef: str, side: dict) -> str:
+    terms = [coef]
+    for k, nu in sorted(side.items()):
+        terms += [f"c{k}"] * nu
+    return " * ".join(terms)
+
+
+def gen_rhs(m: dict) -> str:
+    sp = m["species"]
+    N = len(sp)
+    L = []
+    L.append("  __device__ __forceinline__ static void rhs(const double* __restrict__ u, double rho,")
+    L.append("                                             double inv_rho, double* __restrict__ f) {")
+    L.append("    // Hide rho's loop invariance from the optimiser: otherwise every")
+    L.append("    // rho-dependent product (rho/W_k, third-body alpha_k rho/W_k, ...) is")
+    L.append("    // hoisted out of the step loop and pinned in registers.")
+    L.append("    asm volatile(\"\" : \"+v\"(rho), \"+v\"(inv_rho));")
+    L.append("    const double T = u[0];")
+    L.append("    const double lnT = log(T);")
+    L.append("    const double invT = 1.0 / T;")
+    L.append("    const double omlnT = 1.0 - lnT;")
+    L.append(f"    const double lnPRT = {lit(math.log(m['pstd'] / R_CGS))} - lnT;")
+    for k, s in enumerate(sp):
+        L.append(f"    const double c{k} = u[{k + 1}] * (rho * {lit(1.0 / s['W'])});")
+    L.append("    double " + ", ".join(f"h{k}, g{k}" for k in range(N)) + ";")
+    L.append("    double den = 0.0;  // sum_k c_k (cp_k/R - 1)")
+    L += _thermo(sp)
+    L.append("    double " + ", ".join(f"w{k} = 0.0" for k in range(N)) + ";")
+    for j, rx in enumerate(m["reactions"]):
+        L.append(f"    {{  // reaction {j}")
+        e = [lit(math.log(rx["A"]))]
+        if rx["b"] != 0.0:
+            e.append(f"{lit(rx['b'])} * lnT")
+        if rx["Ea"] != 0.0:
+            e.append(f"- {lit(rx['Ea'] / R_J)} * invT")
+        L.append(f"      const double lkf = {' + '.join(e).replace('+ -', '-')};")
+        L.append("      const double kf = exp(lkf);")
+        nu = {}
+        for k, v in rx["reac"].items():
+            nu[k] = nu.get(k, 0) - v
+        for k, v in rx["prod"].items():
+            nu[k] = nu.get(k, 0) + v
+        dnu = sum(nu.values())
+        gterms = []
+        for k, v in sorted(nu.items()):
+            if v == 0:
+                continue
+            sign = "+" if v > 0 else "-"
+            mag = abs(v)
+            gterms.append(f" {sign} {'' if mag == 1 else lit(float(mag)) + ' * '}g{k}")
+        if dnu != 0:
+            sign = "-" if dnu > 0 else "+"
+            mag = abs(dnu)
+            gterms.append(f" {sign} {'' if mag == 1 else lit(float(mag)) + ' * '}lnPRT")
+        L.append(f"      const double kr = exp(lkf{''.join(gterms)});")
+        q = f"{_prod_expr('kf', rx['reac'])} - {_prod_expr('kr', rx['prod'])}"
+        if rx["tb"]:
+            mt = " + ".join(f"{lit(a)} * c{k}" for k, a in enumerate(rx["eff"]))
+            L.append(f"      const double q = ({mt}) * ({q});")
+        else:
+            L.append(f"      const double q = {q};")
+        for k, v in sorted(nu.items()):
+            if v == 0:
+                continue
+            if v == 1:
+                L.append(f"      w{k} += q;")
+            elif v == -1:
+                L.append(f"      w{k} -= q;")
+            else:
+                L.append(f"      w{k} += {lit(float(v))} * q;")
+        L.append("    }")
+    num = " + ".join(f"(h{k} - 1.0) * w{k}" for k in range(N))
+    L.append(f"    const double num = {num};")
+    L.append("    f[0] = -T * num / den;")
+    for k, s in enumerate(sp):
+        L.append(f"    f[{k + 1}] = w{k} * ({lit(s['W'])} * inv_rho);")
+    L.append("  }")
+    return "\n".join(L)
+
+
+def op_counts(m: dict) -> dict:
+    """Algorithmic FP64 operation counts of one RHS evaluation as generated.
+
+    Counted per the expressions above (FMA-able pairs count as 2 flops):
+    thermo 13 FMA + 4 mul/add per species (one range), concentrations 2 mul,
+    per reaction: lkf (up to 2 FMA), kr exponent (1 add per nu term), products,
+    third-body sum (1 FMA per species), accumulation (1 add per nu term),
+    assembly 2 FMA per species + 2 mul per species.  Transcendentals counted
+    separately."""
+    sp, rx = m["species"], m["reactions"]
+    N = len(sp)
+    flops = 0
+    flops += N * (2 * 13 + 4)            # cp (4 FMA), h (4 FMA + 1 FMA), g (3 FMA + 1 mul + 2 FMA + 2 add)
+    flops += N * 2                       # c_k
+    exps = 0
+    for r in rx:
+        flops += 2 * (1 if r["b"] != 0 else 0) + 2 * (1 if r["Ea"] != 0 else 0)
+        nu = {}
+        for k, v in r["reac"].items():
+            nu[k] = nu.get(k, 0) - v
+        for k, v in r["prod"].items():
+            nu[k] = nu.get(k, 0) + v
+        nz = sum(1 for v in nu.values() if v != 0)
+        flops += nz + (1 if sum(nu.values()) != 0 else 0)      # kr exponent
+        flops += sum(r["reac"].values()) + sum(r["prod"].values()) + 1  # products and difference
+        if r["tb"]:
+            flops += 2 * N + 1
+        flops += nz                                             # accumulation
+        exps += 2
+    flops += 2 * N * 2 + 2 + N                                  # num, den, dT, dY
+    return dict(flops=flops, exp=exps, log=1, div=2, n_species=N, n_reactions=len(rx))
+
+
+# Algorithmic FP64 cost assigned to each non-polynomial operation, in flops
+# (FMA = 2): exp = range reduction (1 mul, 2 FMA) + degree-11 polynomial
+# (11 FMA) = 27; log similar = 30; a correctly rounded divide or square root
+# = reciprocal seed + 2 Newton refinements + correction = 10; pow(e, -1/4) =
+# log + exp = 57.
+FLOP_EXP, FLOP_LOG, FLOP_DIV, FLOP_SQRT, FLOP_POW = 27, 30, 10, 10, 57
+
+
+def rhs_flops(m: dict) -> int:
+    c = op_counts(m)
+    return c["flops"] + FLOP_EXP * c["exp"] + FLOP_LOG * c["log"] + FLOP_DIV * c["div"]
+
+
+def step_flops(m: dict) -> int:
+    """Flops of one LSRK step: 5 RHS + stage updates + WRMS norm + control.
+
+    Stage updates: E, U, X each one FMA per component for stages 1-4, E and X
+    for stage 5: 14 FMA = 28 flops per component.  WRMS: weight (FMA), divide,
+    square-accumulate (FMA) per component, then a scale, a sqrt and the
+    factor's pow, plus 4 scalar flops of control."""
+    n1 = len(m["species"]) + 1
+    upd = 28 * n1
+    wrms = n1 * (2 + FLOP_DIV + 2) + 1 + FLOP_SQRT
+    return 5 * rhs_flops(m) + upd + wrms + FLOP_POW + 4
+
+
+def gen_header(path: str) -> tuple[str, dict]:
+    m = parse(path)
+    N = len(m["species"])
+    tag = f"{m['name']}_{m['hash']:016x}"
+    body = [
+        f"// Generated from {os.path.basename(path)} -- do not edit.",
+        f"struct Mech_{tag} {{",
+        f"  static constexpr int NS = {N};",
+        f"  static constexpr int NR = {len(m['reactions'])};",
+        f"  static constexpr unsigned long long HASH = 0x{m['hash']:016x}ULL;",
+        f"  static constexpr const char* NAME = \"{m['name']}\";",
+        gen_rhs(m),
+        "};",
+    ]
+    return "\n".join(body) + "\n", dict(tag=tag, hash=m["hash"], ns=N, nr=len(m["reactions"]),
+                                        name=m["name"], ops=op_counts(m))
+
+
+def generate(mech_files, out_dir: str) -> list:
+    os.makedirs(out_dir, exist_ok=True)
+    infos = []
+    for p in mech_files:
+        text, info = gen_header(p)
+        with open(os.path.join(out_dir, f"mech_{info['tag']}.inc"), "w") as f:
+            f.write(text)
+        infos.append(info)
+    reg = ["// Generated list of built-in mechanisms -- do not edit."]
+    for info in infos:
+        reg.append(f"#include \"mech_{info['tag']}.inc\"")
+    reg.append("#define CHEM_FOR_EACH_MECH(X) \\")
+    reg.append(" \\\n".join(f"  X(Mech_{info['tag']})" for info in infos))
+    with open(os.path.join(out_dir, "registry.inc"), "w") as f:
+        f.write("\n".join(reg) + "\n")
+    return infos

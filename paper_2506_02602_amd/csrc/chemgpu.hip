@@ -1,0 +1,541 @@
+// chemgpu.hip -- kernels and C ABI of the per-cell FP64 chemistry integrator.
+//
+// Kernels
+//   lsrk_direct     one cell per lane for the whole flow step (no compaction).
+//   lsrk_persistent persistent workgroups over a pool of work items (cells of
+//                   one or more state blocks); every `chunk` steps the
+//                   still-active cells of a workgroup are packed through LDS
+//                   into its lowest lanes and the freed lanes take fresh
+//                   items from a global atomic counter.  A work item is
+//                   (block, cell); a block may ask for n_sub successive
+//                   sub-calls of its own dt (AMR subcycling: a level-l box
+//                   runs 2^l calls of dt0 / 2^l, paper Algorithm 1).
+//
+// Memory: the caller's SoA state is read when a lane claims an item and
+// written when the item finishes; no cell's data is touched by two
+// workgroups, so no cross-workgroup coherence is needed beyond the pool
+// counter's atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "chemgpu.h"
+#include "lsrk.hip.h"
+
+using namespace chemgpu;
+
+#include "generated/registry.inc"
+
+namespace {
+
+struct BoxDesc {
+  double* state;
+  int64_t ld;
+  int64_t n;
+  int64_t start;  // first pool index of this block
+  double dt;
+  int32_t n_sub;
+  int32_t pad;
+  int32_t* status;
+  int32_t* counts;
+};
+
+struct PoolArgs {
+  BoxDesc one;                 // used when boxes == nullptr
+  const BoxDesc* boxes;        // device table, sorted by start
+  int32_t n_boxes;
+  int64_t total;               // pool size
+  unsigned long long* next;    // pool counter (zeroed before launch)
+  Control c;
+  int chunk;
+  int fixed_steps;
+};
+
+__device__ __forceinline__ int find_box(const PoolArgs& a, int64_t g) {
+  if (!a.boxes) return 0;
+  int lo = 0, hi = a.n_boxes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.boxes[mid].start <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ const BoxDesc& box_ref(const PoolArgs& a, int b) {
+  return a.boxes ? a.boxes[b] : a.one;
+}
+
+template <class M>
+__device__ __forceinline__ void load_cell(const BoxDesc& bd, int64_t i, double (&u)[M::NS + 1],
+                                          double& rho, double& h) {
+  const double* s = bd.state;
+#pragma unroll
+  for (int v = 0; v <= M::NS; ++v) u[v] = s[v * bd.ld + i];
+  rho = s[(M::NS + 1) * bd.ld + i];
+  h = s[(M::NS + 2) * bd.ld + i];
+}
+
+template <class M>
+__device__ __forceinline__ void store_cell(const BoxDesc& bd, int64_t i, const double (&u)[M::NS + 1],
+                                           double h, int status, int nacc, int nrej) {
+  double* s = bd.state;
+  if (status != CELL_NONFINITE) {
+#pragma unroll
+    for (int v = 0; v <= M::NS; ++v) s[v * bd.ld + i] = u[v];
+    s[(M::NS + 2) * bd.ld + i] = h;
+  }
+  if (bd.status) bd.status[i] = status;
+  if (bd.counts) { bd.counts[i] = nacc; bd.counts[bd.n + i] = nrej; }
+}
+
+__device__ __forceinline__ double initial_h(double h, double dt) {
+  return (h > 0.0 && h < dt) ? h : dt;
+}
+
+// ------------------------------------------------------------ direct kernel
+template <class M, int LB>
+__global__ __launch_bounds__(LB) void lsrk_direct(PoolArgs a) {
+  constexpr int N1 = M::NS + 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const BoxDesc& bd = a.one;
+  if (i >= bd.n) return;
+  double u[N1], rho, h;
+  load_cell<M>(bd, i, u, rho, h);
+  int nacc = 0, nrej = 0, st;
+  if (!all_finite(u, rho)) {
+    st = CELL_NONFINITE;
+  } else {
+    const double inv_rho = 1.0 / rho;
+    if (a.fixed_steps > 0) {
+      advance_fixed<M>(u, rho, inv_rho, bd.dt, a.fixed_steps, h, nacc, a.c);
+      st = CELL_OK;
+    } else {
+      double t = 0.0;
+      h = initial_h(h, bd.dt);
+      st = advance<M>(u, rho, inv_rho, bd.dt, t, h, nacc, nrej, a.c, a.c.max_steps);
+    }
+  }
+  store_cell<M>(bd, i, u, h, st, nacc, nrej);
+}
+
+// -------------------------------------------------------- persistent kernel
+// Per-lane slot in LDS used to pack active cells: u[N1], t, h, rho (doubles)
+// then item, nacc, nrej, sub, base (ints).
+template <class M>
+struct Slots {
+  static constexpr int N1 = M::NS + 1;
+  static constexpr int ND = N1 + 3;
+  static constexpr int NI = 5;
+  static size_t bytes(int block) { return (size_t)block * (ND * sizeof(double) + NI * sizeof(int)); }
+};
+
+__global__ void pool_reset(unsigned long long* next) { *next = 0ull; }
+
+template <class M, int LB>
+__global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
+  constexpr int N1 = M::NS + 1;
+  constexpr int ND = Slots<M>::ND;
+  extern __shared__ double smem[];
+  const int B = blockDim.x;
+  const int tid = threadIdx.x;
+  double* sd = smem;                                       // [ND][B]
+  int* si = reinterpret_cast<int*>(smem + (size_t)ND * B);  // [5][B]
+  __shared__ int s_active;
+  __shared__ long long s_base;
+  __shared__ int s_take;
+  __shared__ int s_wave_cnt[16];
+
+  // lane state
+  int64_t item = -1;
+  double u[N1], t = 0.0, h = 0.0, rho = 1.0;
+  int nacc = 0, nrej = 0, sub = 0, base = 0;
+  int bx = 0;
+
+  // claim the first B items
+  if (tid == 0) {
+    const unsigned long long got = atomicAdd(a.next, (unsigned long long)B);
+    s_base = (long long)got;
+  }
+  __syncthreads();
+  int free_from = 0;  // lanes [free_from, B) need a fresh item
+  for (;;) {
+    // ---- refill lanes [free_from, B) from the pool base s_base
+    if (tid >= free_from) {
+      const int64_t g = s_base + (tid - free_from);
+      item = -1;
+      if (g < a.total) {
+        item = g;
+        bx = find_box(a, g);
+        const BoxDesc& bd = box_ref(a, bx);
+        const int64_t i = g - bd.start;
+        load_cell<M>(bd, i, u, rho, h);
+        nacc = nrej = 0; sub = 0; base = 0; t = 0.0;
+        if (!all_finite(u, rho)) {
+          store_cell<M>(bd, i, u, h, CELL_NONFINITE, 0, 0);
+          item = -1;
+        } else if (a.fixed_steps > 0) {
+          const double inv_rho = 1.0 / rho;
+          for (int s = 0; s < bd.n_sub; ++s)
+            advance_fixed<M>(u, rho, inv_rho, bd.dt, a.fixed_steps, h, nacc, a.c);
+          nacc = a.fixed_steps * bd.n_sub;
+          store_cell<M>(bd, i, u, h, CELL_OK, nacc, 0);
+          item = -1;
+        } else {
+          h = initial_h(h, bd.dt);
+        }
+      }
+    }
+    // ---- run one chunk
+    if (item >= 0) {
+      const BoxDesc& bd = box_ref(a, bx);
+      const double inv_rho = 1.0 / rho;
+      int budget = a.chunk;
+      Control c = a.c;
+      for (;;) {
+        c.max_steps = base + a.c.max_steps;  // per sub-call step budget
+        const int before = nacc + nrej;
+        int st = advance<M>(u, rho, inv_rho, bd.dt, t, h, nacc, nrej, c, budget);
+        budget -= (nacc + nrej) - before;
+        if (st == CELL_RUNNING) break;
+        if (st == CELL_OK && sub + 1 < bd.n_sub) {
+          ++sub; t = 0.0; base = nacc + nrej;
+          h = initial_h(h, bd.dt);
+          if (budget > 0) continue;
+          break;
+        }
+        store_cell<M>(bd, item - bd.start, u, h, st, nacc, nrej);
+        item = -1;
+        break;
+      }
+    }
+    // ---- pack active lanes to the front through LDS
+    const bool act = item >= 0;
+    const unsigned long long ball = __ballot(act);
+    const int lane = tid & 63, wave = tid >> 6, nw = (B + 63) >> 6;
+    if (lane == 0) s_wave_cnt[wave] = __popcll(ball);
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int cnt = s_wave_cnt[w];
+      if (w < wave) off += cnt;
+      total += cnt;
+    }
+    const int rank = off + __popcll(ball & ((1ull << lane) - 1ull));
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < N1; ++v) sd[(size_t)v * B + rank] = u[v];
+      sd[(size_t)N1 * B + rank] = t;
+      sd[(size_t)(N1 + 1) * B + rank] = h;
+      sd[(size_t)(N1 + 2) * B + rank] = rho;
+      si[0 * B + rank] = (int)item;
+      si[1 * B + rank] = nacc;
+      si[2 * B + rank] = nrej;
+      si[3 * B + rank] = sub;
+      si[4 * B + rank] = base;
+    }
+    if (tid == 0) {
+      int take = 0;
+      long long gbase = 0;
+      const int want = B - total;
+      if (want > 0) {
+        const unsigned long long cur = __hip_atomic_load(a.next, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        if ((int64_t)cur < a.total) {
+          gbase = (long long)atomicAdd(a.next, (unsigned long long)want);
+          take = want;
+        }
+      }
+      s_base = gbase;
+      s_take = take;
+      s_active = total;
+    }
+    __syncthreads();
+    const int A = s_active;
+    if (tid < A) {
+#pragma unroll
+      for (int v = 0; v < N1; ++v) u[v] = sd[(size_t)v * B + tid];
+      t = sd[(size_t)N1 * B + tid];
+      h = sd[(size_t)(N1 + 1) * B + tid];
+      rho = sd[(size_t)(N1 + 2) * B + tid];
+      item = si[0 * B + tid];
+      nacc = si[1 * B + tid];
+      nrej = si[2 * B + tid];
+      sub = si[3 * B + tid];
+      base = si[4 * B + tid];
+      bx = find_box(a, item);
+    } else {
+      item = -1;
+    }
+    const int take = s_take;
+    __syncthreads();  // LDS slots and s_* reused next round
+    if (A == 0 && (take == 0 || s_base >= a.total)) break;
+    free_from = take > 0 ? A : B;
+  }
+}
+
+// ------------------------------------------------------------- registry
+struct MechEntry {
+  unsigned long long hash;
+  int ns, nr;
+  const char* name;
+  hipError_t (*launch_direct)(const PoolArgs&, int block, hipStream_t);
+  hipError_t (*launch_persistent)(const PoolArgs&, int block, int grid, hipStream_t);
+  int (*max_blocks_per_cu)(int block);
+  size_t (*lds_per_lane)();
+};
+
+// Kernels are instantiated for launch bounds 256 (blocks of 64..256 threads)
+// and 512; the bound caps the registers the compiler may give a lane.
+template <class M>
+hipError_t launch_direct(const PoolArgs& a, int block, hipStream_t s) {
+  const int64_t grid = (a.one.n + block - 1) / block;
+  if (grid == 0) return hipSuccess;
+  if (block <= 256)
+    hipLaunchKernelGGL((lsrk_direct<M, 256>), dim3((unsigned)grid), dim3(block), 0, s, a);
+  else
+    hipLaunchKernelGGL((lsrk_direct<M, 512>), dim3((unsigned)grid), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class M>
+hipError_t launch_persistent(const PoolArgs& a, int block, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(pool_reset, dim3(1), dim3(1), 0, s, a.next);
+  if (block <= 256)
+    hipLaunchKernelGGL((lsrk_persistent<M, 256>), dim3(grid), dim3(block),
+                       Slots<M>::bytes(block), s, a);
+  else
+    hipLaunchKernelGGL((lsrk_persistent<M, 512>), dim3(grid), dim3(block),
+                       Slots<M>::bytes(block), s, a);
+  return hipGetLastError();
+}
+
+template <class M>
+int max_blocks_per_cu(int block) {
+  int nb = 0;
+  hipError_t e;
+  if (block <= 256)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 256>, block,
+                                                     Slots<M>::bytes(block));
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 512>, block,
+                                                     Slots<M>::bytes(block));
+  if (e != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <class M>
+size_t lds_per_lane() {
+  return Slots<M>::bytes(1);
+}
+
+#define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, &launch_direct<M>, &launch_persistent<M>, \
+                       &max_blocks_per_cu<M>, &lds_per_lane<M>},
+const MechEntry g_registry[] = {CHEM_FOR_EACH_MECH(CHEM_ENTRY)};
+#undef CHEM_ENTRY
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(CHEM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+uint64_t fnv1a64(const std::vector<char>& d) {
+  uint64_t h = 0xCBF29CE484222325ull;
+  for (char c : d) { h ^= (unsigned char)c; h *= 0x100000001B3ull; }
+  return h;
+}
+
+}  // namespace
+
+struct chem_mech_s {
+  const MechEntry* entry;
+  unsigned long long* d_next = nullptr;
+  BoxDesc* d_boxes = nullptr;
+  BoxDesc* h_boxes = nullptr;      // pinned staging for the box table
+  hipEvent_t boxes_copied = nullptr;
+  int32_t box_cap = 0;
+  int64_t reserved = 0;
+  int device = 0;
+  int n_cu = 0;
+};
+
+namespace {
+
+int ensure_pool(chem_mech m) {
+  if (m->d_next) return CHEM_OK;
+  hipError_t e = hipMalloc(&m->d_next, sizeof(unsigned long long));
+  if (e != hipSuccess) { m->d_next = nullptr; return hip_fail(e, "hipMalloc(pool counter)"); }
+  return CHEM_OK;
+}
+
+int ensure_box_table(chem_mech m, int32_t n) {
+  if (n <= m->box_cap) return CHEM_OK;
+  if (m->boxes_copied) hipEventSynchronize(m->boxes_copied);
+  if (m->d_boxes) hipFree(m->d_boxes);
+  if (m->h_boxes) hipHostFree(m->h_boxes);
+  m->d_boxes = nullptr; m->h_boxes = nullptr; m->box_cap = 0;
+  hipError_t e = hipMalloc(&m->d_boxes, sizeof(BoxDesc) * n);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(box table)");
+  e = hipHostMalloc(&m->h_boxes, sizeof(BoxDesc) * n, hipHostMallocDefault);
+  if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(box table)");
+  if (!m->boxes_copied) {
+    e = hipEventCreateWithFlags(&m->boxes_copied, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  }
+  m->box_cap = n;
+  return CHEM_OK;
+}
+
+Control make_control(const chem_opts* o) {
+  Control c;
+  c.rtol = (o && o->rtol > 0) ? o->rtol : 1e-8;
+  c.atol = (o && o->atol > 0) ? o->atol : 1e-10;
+  c.max_steps = (o && o->max_steps > 0) ? o->max_steps : 100000;
+  return c;
+}
+
+int check_opts(const chem_opts* o) {
+  if (!o) return CHEM_OK;
+  if (!(o->rtol >= 0) || !(o->atol >= 0) || o->max_steps < 0 || o->fixed_steps < 0)
+    return fail(CHEM_EINVAL, "chem_opts: negative or NaN field");
+  if (o->block_size != 0 && (o->block_size % 64 != 0 || o->block_size > 512 || o->block_size < 64))
+    return fail(CHEM_EINVAL, "chem_opts.block_size must be a multiple of 64 in [64, 512]");
+  return CHEM_OK;
+}
+
+constexpr int kDefaultBlock = 128;
+constexpr int kDefaultChunk = 8;
+
+int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
+  const int block = (o && o->block_size) ? o->block_size : kDefaultBlock;
+  if (m->entry->lds_per_lane() * block > 65536)
+    return fail(CHEM_EINVAL, "block_size too large for this mechanism's LDS compaction slots");
+  if (a.total > 0x7fffffff) return fail(CHEM_EINVAL, "more than 2^31-1 work items in one call");
+  int rc = ensure_pool(m);
+  if (rc) return rc;
+  a.next = m->d_next;
+  a.chunk = (o && o->chunk_steps > 0) ? o->chunk_steps : kDefaultChunk;
+  const int per_cu = m->entry->max_blocks_per_cu(block);
+  const int64_t need = (a.total + block - 1) / block;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * m->n_cu));
+  hipError_t e = m->entry->launch_persistent(a, block, (int)grid, s);
+  if (e != hipSuccess) return hip_fail(e, "launch lsrk_persistent");
+  return CHEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* chem_strerror(int code) {
+  switch (code) {
+    case CHEM_OK: return "ok";
+    case CHEM_EINVAL: return "invalid argument";
+    case CHEM_ENOMEM: return "out of memory";
+    case CHEM_EHIP: return "HIP runtime error";
+    case CHEM_EPARSE: return "mechanism file unreadable or malformed";
+    case CHEM_EUNSUPPORTED: return "no kernel built for this mechanism";
+    case CHEM_ECAPACITY: return "more cells than the reserved workspace";
+    default: return "unknown error";
+  }
+}
+
+const char* chem_last_error(void) { return g_err.c_str(); }
+
+int chem_mech_load(const char* path, chem_mech* out) {
+  if (!path || !out) return fail(CHEM_EINVAL, "chem_mech_load: null argument");
+  *out = nullptr;
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(CHEM_EPARSE, std::string("cannot open ") + path);
+  std::vector<char> data;
+  char buf[65536];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof buf, f)) > 0) data.insert(data.end(), buf, buf + k);
+  fclose(f);
+  if (data.size() < 6 || memcmp(data.data(), "MECH 1", 6) != 0)
+    return fail(CHEM_EPARSE, std::string(path) + ":1: missing 'MECH 1' header");
+  const uint64_t hsh = fnv1a64(data);
+  const MechEntry* hit = nullptr;
+  for (const auto& e : g_registry)
+    if (e.hash == hsh) hit = &e;
+  if (!hit) {
+    char msg[128];
+    snprintf(msg, sizeof msg, "no built-in kernel for mechanism hash %016llx",
+             (unsigned long long)hsh);
+    return fail(CHEM_EUNSUPPORTED, msg);
+  }
+  chem_mech m = new (std::nothrow) chem_mech_s();
+  if (!m) return fail(CHEM_ENOMEM, "chem_mech_load: host allocation");
+  m->entry = hit;
+  hipError_t e = hipGetDevice(&m->device);
+  if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
+  e = hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
+  if (e != hipSuccess) { delete m; return hip_fail(e, "hipDeviceGetAttribute"); }
+  *out = m;
+  return CHEM_OK;
+}
+
+int chem_mech_query(chem_mech m, int32_t* n_species, int32_t* n_reactions, uint64_t* hash) {
+  if (!m) return fail(CHEM_EINVAL, "chem_mech_query: null handle");
+  if (n_species) *n_species = m->entry->ns;
+  if (n_reactions) *n_reactions = m->entry->nr;
+  if (hash) *hash = m->entry->hash;
+  return CHEM_OK;
+}
+
+void chem_mech_free(chem_mech m) {
+  if (!m) return;
+  if (m->boxes_copied) { hipEventSynchronize(m->boxes_copied); hipEventDestroy(m->boxes_copied); }
+  if (m->d_next) hipFree(m->d_next);
+  if (m->d_boxes) hipFree(m->d_boxes);
+  if (m->h_boxes) hipHostFree(m->h_boxes);
+  delete m;
+}
+
+int chem_workspace_reserve(chem_mech m, int64_t max_cells) {
+  if (!m || max_cells < 0) return fail(CHEM_EINVAL, "chem_workspace_reserve: bad argument");
+  int rc = ensure_pool(m);
+  if (rc) return rc;
+  m->reserved = std::max(m->reserved, max_cells);
+  return CHEM_OK;
+}
+
+int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, double dt,
+                   const chem_opts* opts, void* stream, int32_t* status, int32_t* counts) {
+  if (!m) return fail(CHEM_EINVAL, "chem_integrate: null mechanism");
+  if (n_cells < 0 || ld < n_cells) return fail(CHEM_EINVAL, "chem_integrate: need 0 <= n_cells <= ld");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "chem_integrate: dt must be finite and > 0");
+  if (n_cells > 0 && !state) return fail(CHEM_EINVAL, "chem_integrate: null state");
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (n_cells == 0) return CHEM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  PoolArgs a{};
+  a.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts};
+  a.boxes = nullptr;
+  a.n_boxes = 1;
+  a.total = n_cells;
+  a.c = make_control(opts);
+  a.fixed_steps = opts ? opts->fixed_steps : 0;
+  if (opts && opts->chunk_steps < 0) {
+    const int block = opts->block_size ? opts->block_size : kDefaultBlock;
+    hipError_t e = m->entry->launch_direct(a, block, s);
+    if (e != hipSuccess) return hip_fail(e, "launch lsrk_direct");
+    return CHEM_OK;
+  }
+  return run_pool(m, a, opts, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Device side of the per-cell LSRK chemistry integrator (gfx950, FP64 VALU).
+//
+// One cell per lane.  The cell's state vector u = (T, Y_1..Y_N) lives in
+// registers as a fully unrolled array; the right-hand side is the
+// mechanism's generated straight-line function M::rhs.
+//
+// Step (paper Eq. 21, two registers plus the error register): with
+// F_i = f(U), for stages i = 1..5
+//     E <- E + (b_i - bhat_i) h F_i
+//     U <- X + a_{i+1,i} h F_i ;  X <- U + (b_i - a_{i+1,i}) h F_i      (i < 5)
+//     X <- X + b_5 h F_5                                               (i = 5)
+// Control (Eq. 22): err = WRMS(E) with weights rtol |u_n| + atol over all
+// N+1 components; accept iff err <= 1; factor 0.9 err^(-1/4) clamped to
+// [0.2, 5] (NaN error: 0.2; zero error: 5); the last step is clipped to end
+// on dt.  Coefficients: Kennedy-Carpenter-Lewis RK4(3)5[2R+]C, the scheme
+// the paper cites as its ref. [37].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chemgpu {
+
+// Exact rationals of the published tableau; each quotient is a compile-time
+// IEEE division of two exactly representable integers (correctly rounded).
+constexpr double LS_A[4] = {970286171893.0 / 4311952581923.0,
+                            6584761158862.0 / 12103376702013.0,
+                            2251764453980.0 / 15575788980749.0,
+                            26877169314380.0 / 34165994151039.0};
+constexpr double LS_B[5] = {1153189308089.0 / 22510343858157.0,
+                            1772645290293.0 / 4653164025191.0,
+                            -1672844663538.0 / 4480602732383.0,
+                            2114624349019.0 / 3568978502595.0,
+                            5198255086312.0 / 14908931495163.0};
+constexpr double LS_BH[5] = {1016888040809.0 / 7410784769900.0,
+                             11231460423587.0 / 58533540763752.0,
+                             -1563879915014.0 / 6823010717585.0,
+                             606302364029.0 / 971179775848.0,
+                             1097981568119.0 / 3980877426909.0};
+
+enum : int { CELL_RUNNING = -1, CELL_OK = 0, CELL_MAXSTEPS = 1, CELL_NONFINITE = 2,
+             CELL_H_UNDERFLOW = 3 };
+
+struct Control {
+  double rtol, atol;
+  int max_steps;
+};
+
+// One LSRK step of size h from u; X receives the new state, returns the WRMS
+// error.  The stage loop stays rolled so that the generated RHS is inlined
+// once; the stage coefficients are wave-uniform scalars.
+template <class M>
+__device__ __forceinline__ double lsrk_step(const double (&u)[M::NS + 1], double rho,
+                                            double inv_rho, double h, double (&X)[M::NS + 1],
+                                            const Control& c) {
+  constexpr int N1 = M::NS + 1;
+  double U[N1], E[N1], F[N1];
+#pragma unroll
+  for (int i = 0; i < N1; ++i) { X[i] = u[i]; U[i] = u[i]; E[i] = 0.0; }
+#pragma unroll 1
+  for (int s = 0; s < 5; ++s) {
+    M::rhs(U, rho, inv_rho, F);
+    const double bs = s == 0 ? LS_B[0] : s == 1 ? LS_B[1] : s == 2 ? LS_B[2] : s == 3 ? LS_B[3] : LS_B[4];
+    const double bhs = s == 0 ? LS_BH[0] : s == 1 ? LS_BH[1] : s == 2 ? LS_BH[2] : s == 3 ? LS_BH[3] : LS_BH[4];
+    const double as = s == 0 ? LS_A[0] : s == 1 ? LS_A[1] : s == 2 ? LS_A[2] : s == 3 ? LS_A[3] : 0.0;
+    const double eh = (bs - bhs) * h;
+    if (s < 4) {
+      const double ah = as * h;
+      const double bah = (bs - as) * h;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) {
+        E[i] += eh * F[i];
+        U[i] = X[i] + ah * F[i];
+        X[i] = U[i] + bah * F[i];
+      }
+    } else {
+      const double bh = bs * h;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) {
+        E[i] += eh * F[i];
+        X[i] = X[i] + bh * F[i];
+      }
+    }
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    const double w = E[i] / (c.rtol * fabs(u[i]) + c.atol);
+    sum += w * w;
+  }
+  return sqrt(sum * (1.0 / N1));
+}
+
+__device__ __forceinline__ double step_factor(double err) {
+  if (err != err) return 0.2;
+  if (err == 0.0) return 5.0;
+  double fac = 0.9 * pow(err, -0.25);
+  fac = fac < 0.2 ? 0.2 : fac;
+  fac = fac > 5.0 ? 5.0 : fac;
+  return fac;
+}
+
+// Advance one cell by at most `budget` steps towards dt.  (t, h, nacc, nrej)
+// carry the cell's progress.  Returns CELL_RUNNING or a final CELL_* code.
+template <class M>
+__device__ __forceinline__ int advance(double (&u)[M::NS + 1], double rho, double inv_rho,
+                                       double dt, double& t, double& h, int& nacc, int& nrej,
+                                       const Control& c, int budget) {
+  constexpr int N1 = M::NS + 1;
+#pragma unroll 1
+  for (int s = 0; s < budget; ++s) {
+    bool last = false;
+    double hh = h;
+    if (hh >= dt - t) { hh = dt - t; last = true; }
+    double X[N1];
+    const double err = lsrk_step<M>(u, rho, inv_rho, hh, X, c);
+    const double fac = step_factor(err);
+    if (err <= 1.0) {
+#pragma unroll
+      for (int i = 0; i < N1; ++i) u[i] = X[i];
+      ++nacc;
+      if (last) { h = hh * fac; return CELL_OK; }
+      t = t + hh;
+    } else {
+      ++nrej;
+    }
+    h = hh * fac;
+    if (nacc + nrej >= c.max_steps) return CELL_MAXSTEPS;
+    if (h < 1e-14 * dt) return CELL_H_UNDERFLOW;
+  }
+  return CELL_RUNNING;
+}
+
+// Test mode: exactly n steps of dt/n, every step accepted.
+template <class M>
+__device__ __forceinline__ void advance_fixed(double (&u)[M::NS + 1], double rho, double inv_rho,
+                                              double dt, int n, double& h, int& nacc,
+                                              const Control& c) {
+  constexpr int N1 = M::NS + 1;
+  const double hh = dt / n;
+#pragma unroll 1
+  for (int s = 0; s < n; ++s) {
+    double X[N1];
+    (void)lsrk_step<M>(u, rho, inv_rho, hh, X, c);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) u[i] = X[i];
+  }
+  nacc = n;
+  h = hh;
+}
+
+template <int N1>
+__device__ __forceinline__ bool all_finite(const double (&u)[N1], double rho) {
+  bool ok = isfinite(rho);
+#pragma unroll
+  for (int i = 0; i < N1; ++i) ok = ok && isfinite(u[i]);
+  return ok;
+}
+
+}  // namespace chemgpu

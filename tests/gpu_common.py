@@ -1,0 +1,85 @@
+"""Shared helpers for the GPU parity tests (HIP path vs the CPU oracle)."""
+import numpy as np
+
+# Parity bar for one flow step from identical inputs: per component
+# |gpu - cpu| <= RTOL_PARITY |cpu| + floor, floor 1e-3 atol for Y and 0 for T.
+RTOL_PARITY = 1e-8
+FLOOR_Y = 1e-13
+
+
+def to_gpu(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def run_gpu(mech, state, dt, **opt):
+    import torch
+    from paper_2506_02602_amd import chemgpu
+    n = state.shape[1]
+    s = to_gpu(state)
+    st = torch.full((max(n, 1),), -7, dtype=torch.int32, device="cuda")
+    cn = torch.full((2 * max(n, 1),), -7, dtype=torch.int32, device="cuda")
+    chemgpu.chem_integrate(mech, s, dt, chemgpu.make_opts(**opt), status=st, counts=cn)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), st.cpu().numpy()[:n], cn.cpu().numpy()[:2 * n].reshape(2, n)
+
+
+def parity_violations(gpu, cpu, ns, rtol=RTOL_PARITY, floor_y=FLOOR_Y):
+    """Boolean mask [n] of cells where T or any Y misses the parity bar."""
+    dT = np.abs(gpu[0] - cpu[0]) > rtol * np.abs(cpu[0])
+    dY = (np.abs(gpu[1:ns + 1] - cpu[1:ns + 1]) >
+          rtol * np.abs(cpu[1:ns + 1]) + floor_y).any(axis=0)
+    return dT | dY
+
+
+def max_rel(gpu, cpu, ns, floor_y=FLOOR_Y):
+    eT = np.max(np.abs(gpu[0] - cpu[0]) / np.abs(cpu[0]))
+    eY = np.max(np.abs(gpu[1:ns + 1] - cpu[1:ns + 1]) / (np.abs(cpu[1:ns + 1]) + floor_y / RTOL_PARITY))
+    return float(eT), float(eY)
+
+
+def assert_parity(gmech, omech, s_full, dt, idx=None, max_flag_frac=0.15, label="", **opt):
+    """Parity of one flow step, GPU vs oracle, on the cells `idx` of s_full.
+
+    The GPU integrates the whole block; the oracle integrates the sampled cells.
+    Every cell must meet the 1e-8 bar, except cells whose adaptive step path
+    differs from the oracle's: in the stability-limited regime the
+    accept/reject sequence of an explicit controller depends on last-bit
+    rounding (the two sides evaluate exp and the rate sums in different
+    orders), so two correct integrators can take different, equally valid
+    paths.  Such flagged cells must (a) agree within 100 tolerance units
+    (rtol |x| + atol) and (b) meet the 1e-8 bar when both sides re-run them at
+    rtol 1e-11, atol 1e-14, where the paths coincide again.  Returns the
+    number of flagged cells."""
+    ns = omech.ns
+    n = s_full.shape[1]
+    idx = np.arange(n) if idx is None else np.asarray(idx)
+    g, gst, gcn = run_gpu(gmech, s_full, dt, **opt)
+    sub = np.ascontiguousarray(s_full[:, idx])
+    c = sub.copy()
+    kw = {k: v for k, v in opt.items() if k in ("rtol", "atol", "max_steps", "fixed_steps")}
+    cst, ccn = omech.integrate(c, dt, **kw)
+    gsub = np.ascontiguousarray(g[:, idx])
+    assert np.array_equal(gst[idx], cst), "per-cell status differs"
+    bad = parity_violations(gsub, c, ns)
+    rtol = opt.get("rtol", 1e-8) or 1e-8
+    atol = opt.get("atol", 1e-10) or 1e-10
+    if bad.any():
+        fi = np.where(bad)[0]
+        scale = rtol * np.abs(c[:ns + 1, fi]) + np.r_[0.0, [atol] * ns][:, None]
+        scale[0] = rtol * np.abs(c[0, fi])
+        tol_units = (np.abs(gsub[:ns + 1, fi] - c[:ns + 1, fi]) / scale).max()
+        assert tol_units < 100, f"{label}: flagged cells differ by {tol_units:.1f} tolerance units"
+        tight = np.ascontiguousarray(sub[:, fi])
+        o2 = dict(opt, rtol=1e-11, atol=1e-14, max_steps=2000000)
+        g2, _, _ = run_gpu(gmech, tight, dt, **o2)
+        c2 = tight.copy()
+        omech.integrate(c2, dt, rtol=1e-11, atol=1e-14, max_steps=2000000)
+        tb = parity_violations(g2, c2, ns)
+        assert not tb.any(), f"{label}: {tb.sum()} flagged cells still differ at rtol 1e-11"
+    frac = bad.mean() if len(bad) else 0.0
+    print(f"[parity] {label}: {len(idx)} cells, {int(bad.sum())} flagged "
+          f"({100 * frac:.2f} %); the rest within 1e-8, flagged ones pass the rtol 1e-11 re-run",
+          flush=True)
+    assert frac <= max_flag_frac
+    return int(bad.sum())

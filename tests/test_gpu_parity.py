@@ -1,0 +1,205 @@
+"""GPU parity: the HIP integrator (through the C ABI) against the CPU oracle on
+identical seeded inputs.  Bar (one flow step): |gpu - cpu| <= 1e-8 |cpu| on T
+and on each Y_k (+1e-13 floor on Y); fixed-step test mode <= 1e-12."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_02602_amd import workloads as wl
+
+from gpu_common import assert_parity, max_rel, parity_violations, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def chemgpu():
+    from paper_2506_02602_amd import chemgpu as c
+    return c
+
+
+@pytest.fixture(scope="module")
+def gmech9(chemgpu, mech9_path):
+    return chemgpu.chem_mech_load(mech9_path)
+
+
+@pytest.fixture(scope="module")
+def gmech32(chemgpu, mech32_path):
+    return chemgpu.chem_mech_load(mech32_path)
+
+
+def _oracle_run(om, state, dt, **kw):
+    s = state.copy()
+    st, cnt = om.integrate(s, dt, **kw)
+    return s, st, cnt
+
+
+def _report(name, gpu, cpu, ns):
+    eT, eY = max_rel(gpu, cpu, ns)
+    print(f"[parity] {name}: max rel err T {eT:.3e}, Y {eY:.3e}", flush=True)
+
+
+def test_mech_query(gmech9, gmech32):
+    assert (gmech9.n_species, gmech9.n_reactions) == (9, 21)
+    assert (gmech32.n_species, gmech32.n_reactions) == (32, 150)
+
+
+@pytest.mark.parametrize("chunk", [-1, 0, 1, 7])
+def test_uniform_cells_all(gmech9, omech9, mech9_path, chunk):
+    """4096 independent cells, T ~ U[1000, 1600] K, 1 atm: every cell."""
+    s0 = wl.cells_uniform(mech9_path)
+    g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=chunk)
+    c, cst, ccn = _oracle_run(omech9, s0, wl.DT_FLOW)
+    _report(f"cells_uniform chunk={chunk}", g, c, 9)
+    assert np.array_equal(gst, cst)
+    assert np.array_equal(gcn, ccn)
+    assert not parity_violations(g, c, 9).any()
+    assert np.allclose(g[11], c[11], rtol=1e-6)        # next-step hint
+    assert np.array_equal(g[10], s0[10])                # rho untouched
+
+
+def _hot_cells(path, n, seed):
+    s, hot = wl.front_2d(path, nx=256, ny=256, seed=seed, band=10)
+    idx = np.where(hot)[0][:n]
+    return np.ascontiguousarray(s[:, idx])
+
+
+@pytest.mark.parametrize("chunk", [-1, 4])
+def test_hot_front_cells(gmech9, omech9, mech9_path, chunk):
+    """Stiff front cells (1500-3000 K, 5-30 atm): ~50 adaptive steps each."""
+    s0 = _hot_cells(mech9_path, 3000, seed=31)
+    assert_parity(gmech9, omech9, s0, wl.DT_FLOW, label=f"hot front chunk={chunk}",
+                  max_flag_frac=0.02, chunk_steps=chunk)
+
+
+def test_fixed_step_mode_tight(gmech9, omech9, mech9_path):
+    s0 = _hot_cells(mech9_path, 512, seed=32)
+    g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, fixed_steps=400)
+    c, _, ccn = _oracle_run(omech9, s0, wl.DT_FLOW, fixed_steps=400)
+    _report("fixed 400 steps", g, c, 9)
+    assert (gst == 0).all() and (gcn[0] == 400).all()
+    assert not parity_violations(g, c, 9, rtol=1e-12, floor_y=1e-15).any()
+
+
+def test_isomer_closed_form(chemgpu, isomer_path):
+    """A <-> B, kf = kr = k = 2e7 /s: c_A - c_B decays as exp(-2 k t), T fixed."""
+    m = chemgpu.chem_mech_load(isomer_path)
+    n = 300
+    rng = np.random.Generator(np.random.PCG64(5))
+    YA = rng.uniform(0.0, 1.0, n)
+    T = rng.uniform(800.0, 2000.0, n)
+    names, W = wl.read_species(isomer_path)
+    Y = np.stack([YA, 1.0 - YA])
+    rho = wl.density(T, np.full(n, wl.P_ATM), Y, W)
+    s0 = wl.pack(T, Y, rho)
+    g, gst, _ = run_gpu(m, s0, 1e-7, rtol=1e-12, atol=1e-16)
+    assert (gst == 0).all()
+    expect = (Y[0] - Y[1]) * np.exp(-2 * 2.0e7 * 1e-7)
+    # error budget of an rtol 1e-12 integration on O(1) mass fractions
+    assert np.abs((g[1] - g[2]) - expect).max() < 2e-11
+    assert np.allclose(g[0], T, rtol=1e-13)
+
+
+def test_ragged_sizes_and_padding(gmech9, omech9, mech9_path, chemgpu):
+    """n not a multiple of any block; ld > n: padding columns untouched."""
+    import torch
+    s0 = wl.cells_uniform(mech9_path, n=1000, seed=9)
+    ld = 1037
+    pad = np.full((12, ld), 123.0)
+    pad[:, :1000] = s0
+    t = torch.from_numpy(pad).cuda()
+    st = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    chemgpu.chem_integrate(gmech9, t, wl.DT_FLOW, chemgpu.make_opts(block_size=192),
+                           status=st, n_cells=1000)
+    torch.cuda.synchronize()
+    out = t.cpu().numpy()
+    assert (out[:, 1000:] == 123.0).all()
+    c, cst, _ = _oracle_run(omech9, s0, wl.DT_FLOW)
+    assert not parity_violations(np.ascontiguousarray(out[:, :1000]), c, 9).any()
+    # n = 0 is a no-op
+    chemgpu.chem_integrate(gmech9, t, wl.DT_FLOW, n_cells=0)
+
+
+def test_status_paths(gmech9, omech9, mech9_path):
+    s0 = _hot_cells(mech9_path, 70, seed=33)
+    s0[3, 5] = np.nan
+    s0[0, 6] = np.inf
+    g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, max_steps=3)
+    c, cst, ccn = _oracle_run(omech9, s0, wl.DT_FLOW, max_steps=3)
+    assert np.array_equal(gst, cst)
+    assert gst[5] == 2 and gst[6] == 2
+    assert np.isnan(g[3, 5]) and np.isinf(g[0, 6])
+    assert np.array_equal(gcn, ccn)
+    ok = np.ones(70, bool)
+    ok[[5, 6]] = False
+    assert not parity_violations(g[:, ok], c[:, ok], 9).any()
+
+
+def test_invalid_arguments(gmech9, chemgpu):
+    import torch
+    s = torch.zeros((12, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(chemgpu.ChemError) as e:
+        chemgpu.chem_integrate(gmech9, s, 0.0)
+    assert e.value.code == -1
+    with pytest.raises(chemgpu.ChemError) as e:
+        chemgpu.chem_integrate(gmech9, s, 1e-7, n_cells=9)
+    assert e.value.code == -1
+    with pytest.raises(chemgpu.ChemError) as e:
+        chemgpu.chem_integrate(gmech9, s, 1e-7, chemgpu.make_opts(block_size=100))
+    assert e.value.code == -1
+
+
+def test_unknown_mechanism_rejected(chemgpu, mech9_path):
+    txt = open(mech9_path).read().replace("name mech9", "name other")
+    fd, p = tempfile.mkstemp(suffix=".mech")
+    with os.fdopen(fd, "w") as f:
+        f.write(txt)
+    try:
+        with pytest.raises(chemgpu.ChemError) as e:
+            chemgpu.chem_mech_load(p)
+        assert e.value.code == -5
+    finally:
+        os.unlink(p)
+
+
+def test_front_field_sampled(gmech9, omech9, mech9_path):
+    """The full 1024 x 1024 front field in one call; the oracle checks every hot
+    cell and a seeded sample of cold cells."""
+    s0, hot = wl.front_2d(mech9_path)
+    rng = np.random.Generator(np.random.PCG64(77))
+    idx = np.concatenate([np.where(hot)[0],
+                          rng.choice(np.where(~hot)[0], 20000, replace=False)])
+    assert_parity(gmech9, omech9, s0, wl.DT_FLOW, idx=idx, label="front 1024^2 sampled",
+                  max_flag_frac=0.02)
+
+
+def test_stress_mech32_sampled(gmech32, omech32, mech32_path):
+    """32 species / 150 reactions on a slab of the independent-T,p stress field."""
+    s0 = wl.stress_3d(mech32_path, shape=(64, 64, 2), seed=4)
+    idx = np.arange(0, s0.shape[1], 7)
+    assert_parity(gmech32, omech32, s0, wl.DT_FLOW, idx=idx, label="stress mech32 sampled")
+
+
+def test_stress_mech9_sampled(gmech9, omech9, mech9_path):
+    """The 9-species mechanism on the same kind of independent-T,p field."""
+    s0 = wl.stress_3d(mech9_path, shape=(64, 64, 4), seed=4)
+    idx = np.arange(0, s0.shape[1], 5)
+    assert_parity(gmech9, omech9, s0, wl.DT_FLOW, idx=idx, label="stress mech9 sampled")
+
+
+def test_chunk_and_block_invariance(gmech9, mech9_path):
+    """Compaction only moves cells between lanes: for a given kernel build the
+    results are bitwise identical for any chunk length or block size; the
+    uncompacted kernel agrees to rounding."""
+    s0 = _hot_cells(mech9_path, 2000, seed=34)
+    ref, rst, rcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=8, block_size=128)
+    for chunk, block in [(1, 64), (3, 128), (16, 256), (64, 192)]:
+        g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=chunk, block_size=block)
+        assert np.array_equal(g, ref) and np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
+    for chunk, block in [(-1, 256), (5, 512)]:
+        g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=chunk, block_size=block)
+        assert np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
+        assert not parity_violations(g, ref, 9, rtol=1e-12, floor_y=1e-16).any()
