@@ -53,7 +53,7 @@ typedef struct {
     int32_t max_steps;   /* accepted + rejected steps per cell (default 100000) */
     int32_t chunk_steps; /* steps a lane takes between compaction points; 0 = tuned default,
                             < 0 = no compaction (one cell per lane for the whole step) */
-    int32_t block_size;  /* threads per block, multiple of 64 up to 1024 (0 = tuned default) */
+    int32_t block_size;  /* threads per block, multiple of 64 up to 512 (0 = tuned default) */
     int32_t fixed_steps; /* > 0: test mode, exactly this many steps of dt/fixed_steps, no control */
 } chem_opts;
 
@@ -76,7 +76,7 @@ int chem_mech_load(const char *path, chem_mech *out);
 /* Species count N, reaction count and content hash of a loaded mechanism. */
 int chem_mech_query(chem_mech m, int32_t *n_species, int32_t *n_reactions, uint64_t *hash);
 
-/* Release a mechanism, its workspace and any graphs made from it. */
+/* Release a mechanism and its workspace (destroy its graphs first). */
 void chem_mech_free(chem_mech m);
 
 /* Reserve the device workspace (work queue, per-cell progress) for up to
@@ -93,6 +93,74 @@ int chem_workspace_reserve(chem_mech m, int64_t max_cells);
  */
 int chem_integrate(chem_mech m, double *state, int64_t ld, int64_t n_cells, double dt,
                    const chem_opts *opts, void *stream, int32_t *status, int32_t *counts);
+
+/*
+ * One AMR box (block-structured patch) of a batched call.  The box's cells
+ * are advanced by n_sub successive sub-calls of dt each -- a level-l box of
+ * a hierarchy with refinement ratio r takes r^l sub-steps of dt_0 / r^l per
+ * coarse step (paper Sec. 3.2, Algorithm 1) -- carrying the step-size hint
+ * between sub-calls.  max_steps applies to each sub-call; counts accumulate
+ * over them; the first sub-call that ends with a non-OK status stops the cell.
+ */
+typedef struct {
+    double *state;   /* SoA block as above, caller-owned device memory */
+    int64_t ld;      /* leading dimension, >= n_cells */
+    int64_t n_cells; /* cells in the box (>= 0) */
+    double dt;       /* sub-call length for this box's level [s], > 0 */
+    int32_t n_sub;   /* sub-calls (>= 1) */
+    int32_t level;   /* refinement level (informational; used to order work) */
+    int32_t *status; /* NULL or int32[n_cells] device array */
+    int32_t *counts; /* NULL or int32[2 * n_cells] device array (accepted, rejected) */
+} chem_box;
+
+/*
+ * Advance every cell of n_boxes boxes in ONE persistent launch over a shared
+ * work pool: deeper-level boxes (more sub-calls) are queued first, still-active
+ * cells are compacted within each workgroup between step chunks.  The box
+ * table is copied to the device through a pinned staging buffer owned by the
+ * mechanism handle; the call returns without waiting for the GPU.
+ */
+int chem_integrate_batched(chem_mech m, const chem_box *boxes, int32_t n_boxes,
+                           const chem_opts *opts, void *stream);
+
+typedef struct chem_graph_s *chem_graph; /* opaque, owned by the library */
+
+/*
+ * Capture a batched call into a HIP graph (reset kernel + persistent
+ * kernel; no memset nodes).  The box table is copied to graph-owned device
+ * memory at capture time, so every later launch integrates the same boxes
+ * (same pointers, sizes, dt, n_sub) with whatever data they then hold.
+ * Capture happens on a private stream (`stream` may be NULL and is only
+ * synchronised before the capture).  The graph has its own work-pool
+ * counter, so it may be launched while eager calls use the mechanism on the
+ * same stream; two launches of one graph must not overlap.  Allocates (at
+ * capture time only).
+ */
+int chem_graph_capture_batched(chem_mech m, const chem_box *boxes, int32_t n_boxes,
+                               const chem_opts *opts, void *stream, chem_graph *out);
+
+/* Launch a captured graph on `stream` (enqueue only). */
+int chem_graph_launch(chem_graph g, void *stream);
+
+/* Destroy a graph (waits for its outstanding launches). */
+void chem_graph_destroy(chem_graph g);
+
+/*
+ * Autotune block size and chunk length for these boxes: every candidate
+ * (block in {64, 128, 192, 256, 384, 512} that fits the LDS compaction slots,
+ * chunk in {1, 2, 4, 8, 16, 32, 64}) is timed with HIP events on `stream`
+ * (median of `reps` launches) on the caller's boxes; the boxes' states are
+ * snapshotted first and restored after every trial and at the end, so the
+ * caller's data is left unchanged.  The winner is stored in the handle for
+ * the size bucket of these boxes (total cells rounded to a power of two):
+ * later calls whose chunk_steps and block_size are 0 use it.  If cache_path
+ * is not NULL the result is also looked up in / written to that JSON file,
+ * keyed by mechanism hash, size bucket and GPU architecture name; a cache hit
+ * skips the sweep.  best (may be NULL) receives the chosen options.
+ * Synchronises `stream`.
+ */
+int chem_autotune(chem_mech m, const chem_box *boxes, int32_t n_boxes, const chem_opts *base,
+                  int32_t reps, const char *cache_path, void *stream, chem_opts *best);
 
 /* Message for a return code; valid for the life of the process. */
 const char *chem_strerror(int code);

@@ -34,6 +34,12 @@ class chem_opts(C.Structure):
                 ("fixed_steps", C.c_int32)]
 
 
+class chem_box(C.Structure):
+    _fields_ = [("state", C.c_void_p), ("ld", C.c_int64), ("n_cells", C.c_int64),
+                ("dt", C.c_double), ("n_sub", C.c_int32), ("level", C.c_int32),
+                ("status", C.c_void_p), ("counts", C.c_void_p)]
+
+
 class ChemError(RuntimeError):
     def __init__(self, code, where):
         msg = _lib.chem_last_error().decode()
@@ -58,6 +64,18 @@ _lib.chem_workspace_reserve.restype = C.c_int
 _lib.chem_integrate.argtypes = [_P, _P, C.c_int64, C.c_int64, C.c_double,
                                 C.POINTER(chem_opts), _P, _P, _P]
 _lib.chem_integrate.restype = C.c_int
+_lib.chem_integrate_batched.argtypes = [_P, C.POINTER(chem_box), C.c_int32, C.POINTER(chem_opts), _P]
+_lib.chem_integrate_batched.restype = C.c_int
+_lib.chem_graph_capture_batched.argtypes = [_P, C.POINTER(chem_box), C.c_int32,
+                                            C.POINTER(chem_opts), _P, C.POINTER(_P)]
+_lib.chem_graph_capture_batched.restype = C.c_int
+_lib.chem_graph_launch.argtypes = [_P, _P]
+_lib.chem_graph_launch.restype = C.c_int
+_lib.chem_graph_destroy.argtypes = [_P]
+_lib.chem_graph_destroy.restype = None
+_lib.chem_autotune.argtypes = [_P, C.POINTER(chem_box), C.c_int32, C.POINTER(chem_opts), C.c_int32,
+                               C.c_char_p, _P, C.POINTER(chem_opts)]
+_lib.chem_autotune.restype = C.c_int
 
 
 def _check(rc, where):
@@ -129,7 +147,74 @@ def chem_integrate(mech: Mechanism, state, dt: float, opts: chem_opts | None = N
                                _stream(stream), _ptr(status), _ptr(counts)), "chem_integrate")
 
 
+def make_boxes(boxes):
+    """boxes: list of dicts with keys state (CUDA float64 [N+3, ld]), dt,
+    n_sub (default 1), level (default 0), status, counts (optional tensors),
+    n_cells (default ld)."""
+    arr = (chem_box * max(len(boxes), 1))()
+    for i, b in enumerate(boxes):
+        st = b["state"]
+        ld = st.shape[1]
+        arr[i] = chem_box(st.data_ptr(), ld, int(b.get("n_cells", ld)), float(b["dt"]),
+                          int(b.get("n_sub", 1)), int(b.get("level", 0)),
+                          _ptr(b.get("status")), _ptr(b.get("counts")))
+    return arr
+
+
+def chem_integrate_batched(mech: Mechanism, boxes, opts: chem_opts | None = None,
+                           stream=None) -> None:
+    arr = make_boxes(boxes)
+    o = opts if opts is not None else make_opts()
+    _check(_lib.chem_integrate_batched(mech.handle, arr, len(boxes), C.byref(o),
+                                       _stream(stream)), "chem_integrate_batched")
+
+
+class Graph:
+    """A captured batched call (``chem_graph``)."""
+
+    def __init__(self, mech: Mechanism, boxes, opts: chem_opts | None = None, stream=None):
+        arr = make_boxes(boxes)
+        o = opts if opts is not None else make_opts()
+        h = _P()
+        _check(_lib.chem_graph_capture_batched(mech.handle, arr, len(boxes), C.byref(o),
+                                               _stream(stream), C.byref(h)),
+               "chem_graph_capture_batched")
+        self.handle = h
+        self._keep = boxes
+
+    def launch(self, stream=None):
+        _check(_lib.chem_graph_launch(self.handle, _stream(stream)), "chem_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.chem_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chem_graph_capture_batched(mech, boxes, opts=None, stream=None) -> Graph:
+    return Graph(mech, boxes, opts, stream)
+
+
+def chem_autotune(mech: Mechanism, boxes, base: chem_opts | None = None, reps: int = 3,
+                  cache_path: str | None = None, stream=None) -> chem_opts:
+    arr = make_boxes(boxes)
+    o = base if base is not None else make_opts()
+    best = chem_opts()
+    _check(_lib.chem_autotune(mech.handle, arr, len(boxes), C.byref(o), int(reps),
+                              cache_path.encode() if cache_path else None, _stream(stream),
+                              C.byref(best)), "chem_autotune")
+    return best
+
+
 def exported_symbols():
     """Names declared in include/chemgpu.h that this library must export."""
     return ["chem_mech_load", "chem_mech_query", "chem_mech_free", "chem_workspace_reserve",
-            "chem_integrate", "chem_strerror", "chem_last_error"]
+            "chem_integrate", "chem_integrate_batched", "chem_graph_capture_batched",
+            "chem_graph_launch", "chem_graph_destroy", "chem_autotune", "chem_strerror",
+            "chem_last_error"]

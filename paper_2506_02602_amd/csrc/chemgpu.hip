@@ -18,10 +18,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -361,6 +363,7 @@ uint64_t fnv1a64(const std::vector<char>& d) {
 
 struct chem_mech_s {
   const MechEntry* entry;
+  std::map<int, std::pair<int, int>> tuned;  // size bucket -> (block, chunk)
   unsigned long long* d_next = nullptr;
   BoxDesc* d_boxes = nullptr;
   BoxDesc* h_boxes = nullptr;      // pinned staging for the box table
@@ -369,6 +372,13 @@ struct chem_mech_s {
   int64_t reserved = 0;
   int device = 0;
   int n_cu = 0;
+};
+
+struct chem_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BoxDesc* d_boxes = nullptr;
+  unsigned long long* d_next = nullptr;
 };
 
 namespace {
@@ -418,20 +428,120 @@ int check_opts(const chem_opts* o) {
 constexpr int kDefaultBlock = 128;
 constexpr int kDefaultChunk = 8;
 
+int size_bucket(int64_t total) {
+  int b = 0;
+  while (b < 62 && (int64_t(1) << b) < total) ++b;
+  return b;
+}
+
+void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int* chunk) {
+  *block = (o && o->block_size) ? o->block_size : 0;
+  *chunk = (o && o->chunk_steps) ? o->chunk_steps : 0;
+  auto it = m->tuned.find(size_bucket(total));
+  if (it != m->tuned.end()) {
+    if (!*block) *block = it->second.first;
+    if (!*chunk) *chunk = it->second.second;
+  }
+  if (!*block) *block = kDefaultBlock;
+  if (!*chunk) *chunk = kDefaultChunk;
+}
+
+int grid_for(chem_mech m, int block, int64_t total);
+
 int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
-  const int block = (o && o->block_size) ? o->block_size : kDefaultBlock;
+  int block, chunk;
+  pick_launch(m, a.total, o, &block, &chunk);
   if (m->entry->lds_per_lane() * block > 65536)
     return fail(CHEM_EINVAL, "block_size too large for this mechanism's LDS compaction slots");
   if (a.total > 0x7fffffff) return fail(CHEM_EINVAL, "more than 2^31-1 work items in one call");
   int rc = ensure_pool(m);
   if (rc) return rc;
   a.next = m->d_next;
-  a.chunk = (o && o->chunk_steps > 0) ? o->chunk_steps : kDefaultChunk;
-  const int per_cu = m->entry->max_blocks_per_cu(block);
-  const int64_t need = (a.total + block - 1) / block;
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * m->n_cu));
-  hipError_t e = m->entry->launch_persistent(a, block, (int)grid, s);
+  a.chunk = chunk > 0 ? chunk : kDefaultChunk;
+  hipError_t e = m->entry->launch_persistent(a, block, grid_for(m, block, a.total), s);
   if (e != hipSuccess) return hip_fail(e, "launch lsrk_persistent");
+  return CHEM_OK;
+}
+
+int grid_for(chem_mech m, int block, int64_t total) {
+  const int per_cu = m->entry->max_blocks_per_cu(block);
+  const int64_t need = (total + block - 1) / block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * m->n_cu));
+}
+
+// Validate boxes and lay them out as one pool: boxes with more sub-calls
+// first (they carry the most work per cell), empty boxes dropped.
+int build_table(const chem_box* boxes, int32_t n, std::vector<BoxDesc>& out, int64_t* total) {
+  if (n < 0 || (n > 0 && !boxes)) return fail(CHEM_EINVAL, "bad box list");
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return boxes[x].n_sub > boxes[y].n_sub; });
+  out.clear();
+  int64_t start = 0;
+  for (int k = 0; k < n; ++k) {
+    const chem_box& b = boxes[order[k]];
+    if (b.n_cells < 0 || b.ld < b.n_cells) return fail(CHEM_EINVAL, "box: need 0 <= n_cells <= ld");
+    if (!(b.dt > 0) || !std::isfinite(b.dt)) return fail(CHEM_EINVAL, "box: dt must be finite and > 0");
+    if (b.n_sub < 1) return fail(CHEM_EINVAL, "box: n_sub must be >= 1");
+    if (b.n_cells == 0) continue;
+    if (!b.state) return fail(CHEM_EINVAL, "box: null state");
+    out.push_back(BoxDesc{b.state, b.ld, b.n_cells, start, b.dt, b.n_sub, 0, b.status, b.counts});
+    start += b.n_cells;
+  }
+  *total = start;
+  return CHEM_OK;
+}
+
+std::string arch_name(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+struct TuneEntry { std::string key; int block, chunk; double ms; };
+
+std::vector<TuneEntry> read_cache(const char* path) {
+  std::vector<TuneEntry> v;
+  FILE* f = fopen(path, "rb");
+  if (!f) return v;
+  std::string txt;
+  char buf[4096];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, k);
+  fclose(f);
+  size_t pos = 0;
+  const std::string tag = "\"key\": \"";
+  while ((pos = txt.find(tag, pos)) != std::string::npos) {
+    pos += tag.size();
+    const size_t end = txt.find('"', pos);
+    if (end == std::string::npos) break;
+    TuneEntry e{txt.substr(pos, end - pos), 0, 0, 0.0};
+    const size_t close = txt.find('}', end);
+    const std::string rec = txt.substr(end, close == std::string::npos ? std::string::npos : close - end);
+    const size_t pb = rec.find("\"block\":"), pc = rec.find("\"chunk\":"), pm = rec.find("\"ms\":");
+    if (pb != std::string::npos) e.block = atoi(rec.c_str() + pb + 8);
+    if (pc != std::string::npos) e.chunk = atoi(rec.c_str() + pc + 8);
+    if (pm != std::string::npos) e.ms = atof(rec.c_str() + pm + 5);
+    if (e.block > 0 && e.chunk != 0) v.push_back(e);
+    pos = end;
+  }
+  return v;
+}
+
+int write_cache(const char* path, const std::vector<TuneEntry>& v) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return fail(CHEM_EINVAL, std::string("cannot write ") + path);
+  fprintf(f, "{\"version\": 1, \"entries\": [\n");
+  for (size_t i = 0; i < v.size(); ++i)
+    fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"chunk\": %d, \"ms\": %.6f}%s\n",
+            v[i].key.c_str(), v[i].block, v[i].chunk, v[i].ms, i + 1 < v.size() ? "," : "");
+  fprintf(f, "]}\n");
+  fclose(f);
+  if (rename(tmp.c_str(), path) != 0) return fail(CHEM_EINVAL, std::string("cannot replace ") + path);
   return CHEM_OK;
 }
 
@@ -529,13 +639,214 @@ int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, doub
   a.total = n_cells;
   a.c = make_control(opts);
   a.fixed_steps = opts ? opts->fixed_steps : 0;
-  if (opts && opts->chunk_steps < 0) {
-    const int block = opts->block_size ? opts->block_size : kDefaultBlock;
+  int block, chunk;
+  pick_launch(m, n_cells, opts, &block, &chunk);
+  if (chunk < 0) {
     hipError_t e = m->entry->launch_direct(a, block, s);
     if (e != hipSuccess) return hip_fail(e, "launch lsrk_direct");
     return CHEM_OK;
   }
   return run_pool(m, a, opts, s);
+}
+
+int chem_integrate_batched(chem_mech m, const chem_box* boxes, int32_t n_boxes,
+                           const chem_opts* opts, void* stream) {
+  if (!m) return fail(CHEM_EINVAL, "chem_integrate_batched: null mechanism");
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  std::vector<BoxDesc> table;
+  int64_t total = 0;
+  rc = build_table(boxes, n_boxes, table, &total);
+  if (rc) return rc;
+  if (total == 0) return CHEM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  rc = ensure_box_table(m, (int32_t)table.size());
+  if (rc) return rc;
+  // the staging buffer may still feed the previous call's copy
+  hipError_t e = hipEventSynchronize(m->boxes_copied);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(box table)");
+  memcpy(m->h_boxes, table.data(), sizeof(BoxDesc) * table.size());
+  e = hipMemcpyAsync(m->d_boxes, m->h_boxes, sizeof(BoxDesc) * table.size(),
+                     hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(box table)");
+  e = hipEventRecord(m->boxes_copied, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord(box table)");
+  PoolArgs a{};
+  a.one = table[0];
+  a.boxes = m->d_boxes;
+  a.n_boxes = (int32_t)table.size();
+  a.total = total;
+  a.c = make_control(opts);
+  a.fixed_steps = opts ? opts->fixed_steps : 0;
+  return run_pool(m, a, opts, s);
+}
+
+int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_boxes,
+                               const chem_opts* opts, void* stream, chem_graph* out) {
+  if (!m || !out) return fail(CHEM_EINVAL, "chem_graph_capture_batched: null argument");
+  *out = nullptr;
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  std::vector<BoxDesc> table;
+  int64_t total = 0;
+  rc = build_table(boxes, n_boxes, table, &total);
+  if (rc) return rc;
+  if (total == 0) return fail(CHEM_EINVAL, "chem_graph_capture_batched: no cells");
+  if (total > 0x7fffffff) return fail(CHEM_EINVAL, "more than 2^31-1 work items in one call");
+  int block, chunk;
+  pick_launch(m, total, opts, &block, &chunk);
+  if (m->entry->lds_per_lane() * block > 65536)
+    return fail(CHEM_EINVAL, "block_size too large for this mechanism's LDS compaction slots");
+  chem_graph g = new (std::nothrow) chem_graph_s();
+  if (!g) return fail(CHEM_ENOMEM, "chem_graph_capture_batched: host allocation");
+  auto bail = [&](hipError_t e, const char* what) {
+    chem_graph_destroy(g);
+    return hip_fail(e, what);
+  };
+  hipError_t e = hipMalloc(&g->d_boxes, sizeof(BoxDesc) * table.size());
+  if (e != hipSuccess) return bail(e, "hipMalloc(graph box table)");
+  e = hipMalloc(&g->d_next, sizeof(unsigned long long));
+  if (e != hipSuccess) return bail(e, "hipMalloc(graph pool counter)");
+  e = hipMemcpy(g->d_boxes, table.data(), sizeof(BoxDesc) * table.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(e, "hipMemcpy(graph box table)");
+  if (stream) {
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return bail(e, "hipStreamSynchronize");
+  }
+  PoolArgs a{};
+  a.one = table[0];
+  a.boxes = g->d_boxes;
+  a.n_boxes = (int32_t)table.size();
+  a.total = total;
+  a.next = g->d_next;
+  a.c = make_control(opts);
+  a.chunk = chunk > 0 ? chunk : kDefaultChunk;
+  a.fixed_steps = opts ? opts->fixed_steps : 0;
+  const int grid = grid_for(m, block, total);
+  hipStream_t cs;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(e, "hipStreamCreate(capture)");
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) { hipStreamDestroy(cs); return bail(e, "hipStreamBeginCapture"); }
+  hipError_t le = m->entry->launch_persistent(a, block, grid, cs);
+  e = hipStreamEndCapture(cs, &g->graph);
+  hipStreamDestroy(cs);
+  if (le != hipSuccess) return bail(le, "launch lsrk_persistent (capture)");
+  if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(e, "hipGraphInstantiate");
+  *out = g;
+  return CHEM_OK;
+}
+
+int chem_graph_launch(chem_graph g, void* stream) {
+  if (!g || !g->exec) return fail(CHEM_EINVAL, "chem_graph_launch: null graph");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return CHEM_OK;
+}
+
+void chem_graph_destroy(chem_graph g) {
+  if (!g) return;
+  hipDeviceSynchronize();
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->d_boxes) hipFree(g->d_boxes);
+  if (g->d_next) hipFree(g->d_next);
+  delete g;
+}
+
+int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const chem_opts* base,
+                  int32_t reps, const char* cache_path, void* stream, chem_opts* best) {
+  if (!m) return fail(CHEM_EINVAL, "chem_autotune: null mechanism");
+  int rc = check_opts(base);
+  if (rc) return rc;
+  std::vector<BoxDesc> table;
+  int64_t total = 0;
+  rc = build_table(boxes, n_boxes, table, &total);
+  if (rc) return rc;
+  if (total == 0) return fail(CHEM_EINVAL, "chem_autotune: no cells");
+  if (reps < 1) reps = 3;
+  hipStream_t s = (hipStream_t)stream;
+  const int bucket = size_bucket(total);
+  char key[160];
+  snprintf(key, sizeof key, "%016llx:%d:%s", (unsigned long long)m->entry->hash, bucket,
+           arch_name(m->device).c_str());
+  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0};
+  std::vector<TuneEntry> cache;
+  if (cache_path) {
+    cache = read_cache(cache_path);
+    for (const auto& en : cache)
+      if (en.key == key) {
+        m->tuned[bucket] = {en.block, en.chunk};
+        if (best) { *best = o; best->block_size = en.block; best->chunk_steps = en.chunk; }
+        return CHEM_OK;
+      }
+  }
+  // snapshot every box so trials can restore the caller's data
+  std::vector<double*> snap(table.size(), nullptr);
+  std::vector<size_t> bytes(table.size());
+  auto cleanup = [&]() { for (double* p : snap) if (p) hipFree(p); };
+  hipError_t e;
+  for (size_t i = 0; i < table.size(); ++i) {
+    bytes[i] = sizeof(double) * (size_t)table[i].ld * (size_t)(m->entry->ns + 3);
+    e = hipMalloc(&snap[i], bytes[i]);
+    if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipMalloc(autotune snapshot)"); }
+    e = hipMemcpyAsync(snap[i], table[i].state, bytes[i], hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) { cleanup(); return hip_fail(e, "snapshot copy"); }
+  }
+  auto restore = [&]() -> hipError_t {
+    for (size_t i = 0; i < table.size(); ++i) {
+      hipError_t r = hipMemcpyAsync(table[i].state, snap[i], bytes[i], hipMemcpyDeviceToDevice, s);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  };
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  const int blocks[] = {64, 128, 192, 256, 384, 512};
+  const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
+  double best_ms = 1e300;
+  int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
+  rc = CHEM_OK;
+  for (int b : blocks) {
+    if (m->entry->lds_per_lane() * b > 65536) continue;
+    for (int c : chunks) {
+      chem_opts t = o;
+      t.block_size = b;
+      t.chunk_steps = c;
+      std::vector<float> ms;
+      for (int r = 0; r <= reps && rc == CHEM_OK; ++r) {
+        if ((e = restore()) != hipSuccess) { rc = hip_fail(e, "restore"); break; }
+        hipEventRecord(e0, s);
+        rc = chem_integrate_batched(m, boxes, n_boxes, &t, stream);
+        hipEventRecord(e1, s);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) { rc = hip_fail(e, "trial"); break; }
+        float el = 0;
+        hipEventElapsedTime(&el, e0, e1);
+        if (r > 0) ms.push_back(el);
+      }
+      if (rc != CHEM_OK) break;
+      std::sort(ms.begin(), ms.end());
+      const double med = ms[ms.size() / 2];
+      if (med < best_ms) { best_ms = med; best_block = b; best_chunk = c; }
+    }
+    if (rc != CHEM_OK) break;
+  }
+  if ((e = restore()) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "restore");
+  hipStreamSynchronize(s);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  cleanup();
+  if (rc != CHEM_OK) return rc;
+  m->tuned[bucket] = {best_block, best_chunk};
+  if (best) { *best = o; best->block_size = best_block; best->chunk_steps = best_chunk; }
+  if (cache_path) {
+    cache.push_back(TuneEntry{key, best_block, best_chunk, best_ms});
+    rc = write_cache(cache_path, cache);
+  }
+  return rc;
 }
 
 }  // extern "C"

@@ -1,0 +1,205 @@
+"""Batched AMR integration, hipGraph replay and the autotuner, on the GPU.
+
+Reference: each box's cells integrated by the oracle as n_sub successive
+flow-step calls of the box's dt (the step-size hint carried in the state's h
+row), i.e. the chemistry calls of a subcycled AMR coarse step (paper Sec. 3.2,
+Algorithm 1)."""
+import json
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2506_02602_amd import workloads as wl
+
+from gpu_common import parity_violations, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cg():
+    from paper_2506_02602_amd import chemgpu
+    return chemgpu
+
+
+@pytest.fixture(scope="module")
+def gm9(cg, mech9_path):
+    return cg.chem_mech_load(mech9_path)
+
+
+def oracle_subcalls(om, state, dt, n_sub, **kw):
+    """n_sub oracle calls of dt on a copy of `state`; a cell stops at its
+    first non-OK sub-call.  Returns (state, status, counts)."""
+    s = state.copy()
+    n = s.shape[1]
+    status = np.zeros(n, np.int32)
+    counts = np.zeros((2, n), np.int32)
+    live = np.arange(n)
+    for _ in range(n_sub):
+        if len(live) == 0:
+            break
+        sub = np.ascontiguousarray(s[:, live])
+        st, cn = om.integrate(sub, dt, **kw)
+        s[:, live] = sub
+        counts[:, live] += cn
+        status[live] = st
+        live = live[st == 0]
+    return s, status, counts
+
+
+def gpu_boxes(hier, with_out=True):
+    import torch
+    boxes = []
+    for b in hier:
+        n = b["state"].shape[1]
+        d = dict(state=to_gpu(b["state"]), dt=b["dt"], n_sub=b["n_sub"], level=b["level"])
+        if with_out:
+            d["status"] = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+            d["counts"] = torch.full((2 * n,), -7, dtype=torch.int32, device="cuda")
+        boxes.append(d)
+    return boxes
+
+
+def small_hierarchy(path, seed=13):
+    return wl.amr_hierarchy(path, seed=seed, boxes_per_level=(2, 3, 4), edges=(8, 12, 16))
+
+
+def test_batched_matches_oracle_subcycling(cg, gm9, omech9, mech9_path):
+    import torch
+    hier = small_hierarchy(mech9_path)
+    boxes = gpu_boxes(hier)
+    cg.chem_integrate_batched(gm9, boxes)
+    torch.cuda.synchronize()
+    flagged = total = 0
+    for hb, gb in zip(hier, boxes):
+        c, cst, ccn = oracle_subcalls(omech9, hb["state"], hb["dt"], hb["n_sub"])
+        g = gb["state"].cpu().numpy()
+        gst = gb["status"].cpu().numpy()
+        gcn = gb["counts"].cpu().numpy().reshape(2, -1)
+        assert np.array_equal(gst, cst)
+        bad = parity_violations(g, c, 9)
+        if bad.any():
+            # flagged cells: step-path divergence; both sides agree at tight tolerance
+            idx = np.where(bad)[0]
+            tight = np.ascontiguousarray(hb["state"][:, idx])
+            gt = to_gpu(tight)
+            cg.chem_integrate_batched(gm9, [dict(state=gt, dt=hb["dt"], n_sub=hb["n_sub"])],
+                                      cg.make_opts(rtol=1e-11, atol=1e-14, max_steps=2000000))
+            c2, _, _ = oracle_subcalls(omech9, tight, hb["dt"], hb["n_sub"], rtol=1e-11,
+                                       atol=1e-14, max_steps=2000000)
+            assert not parity_violations(gt.cpu().numpy(), c2, 9).any()
+        else:
+            assert np.array_equal(gcn, ccn)
+        flagged += int(bad.sum())
+        total += len(bad)
+    print(f"[parity] small AMR batch: {total} cells, {flagged} flagged", flush=True)
+    assert flagged <= 0.02 * total
+
+
+def test_batched_equals_per_box_calls(cg, gm9, mech9_path):
+    """One batched launch == host-driven per-box sub-calls of chem_integrate, bitwise."""
+    import torch
+    hier = small_hierarchy(mech9_path, seed=14)
+    boxes = gpu_boxes(hier)
+    cg.chem_integrate_batched(gm9, boxes)
+    for hb, gb in zip(hier, boxes):
+        t = to_gpu(hb["state"])
+        tot = torch.zeros(2 * t.shape[1], dtype=torch.int32, device="cuda")
+        cn = torch.zeros_like(tot)
+        for _ in range(hb["n_sub"]):
+            cg.chem_integrate(gm9, t, hb["dt"], counts=cn)
+            tot += cn
+        torch.cuda.synchronize()
+        assert torch.equal(t, gb["state"])
+        assert torch.equal(tot, gb["counts"])
+
+
+def test_graph_replay_matches_eager(cg, gm9, mech9_path):
+    """Replays of a captured graph, with eager work and syncs between them,
+    each reproduce the eager batched result exactly."""
+    import torch
+    hier = small_hierarchy(mech9_path, seed=15)
+    eager = gpu_boxes(hier)
+    cg.chem_integrate_batched(gm9, eager)
+    torch.cuda.synchronize()
+    boxes = gpu_boxes(hier)
+    pristine = [b["state"].clone() for b in boxes]
+    g = cg.chem_graph_capture_batched(gm9, boxes)
+    other = to_gpu(wl.cells_uniform(mech9_path, n=3000, seed=3))
+    for rep in range(4):
+        for b, p in zip(boxes, pristine):
+            b["state"].copy_(p)
+        g.launch()
+        cg.chem_integrate(gm9, other, wl.DT_FLOW)      # unrelated eager work in between
+        torch.cuda.synchronize()
+        for b, e in zip(boxes, eager):
+            assert torch.equal(b["state"], e["state"]), f"replay {rep}"
+            assert torch.equal(b["counts"], e["counts"])
+    g.close()
+
+
+def test_autotune_keeps_data_and_caches(cg, mech9_path):
+    import torch
+    m = cg.chem_mech_load(mech9_path)        # fresh handle: no tuned entries yet
+    hier = small_hierarchy(mech9_path, seed=16)
+    boxes = gpu_boxes(hier, with_out=False)
+    before = [b["state"].clone() for b in boxes]
+    fd, cache = tempfile.mkstemp(suffix=".json")
+    os.close(fd)
+    os.unlink(cache)
+    try:
+        best = cg.chem_autotune(m, boxes, reps=1, cache_path=cache)
+        torch.cuda.synchronize()
+        assert best.block_size in (64, 128, 192, 256, 384, 512)
+        assert best.chunk_steps in (1, 2, 4, 8, 16, 32, 64)
+        for b, p in zip(boxes, before):
+            assert torch.equal(b["state"], p)          # caller's data untouched
+        entries = json.load(open(cache))["entries"]
+        assert len(entries) == 1 and entries[0]["key"].startswith(f"{m.hash:016x}:")
+        again = cg.chem_autotune(cg.chem_mech_load(mech9_path), boxes, reps=1, cache_path=cache)
+        assert (again.block_size, again.chunk_steps) == (best.block_size, best.chunk_steps)
+        # tuned defaults give the same numbers as the explicit choice
+        b1 = gpu_boxes(hier, with_out=False)
+        b2 = gpu_boxes(hier, with_out=False)
+        cg.chem_integrate_batched(m, b1)
+        cg.chem_integrate_batched(m, b2, cg.make_opts(block_size=best.block_size,
+                                                      chunk_steps=best.chunk_steps))
+        torch.cuda.synchronize()
+        for x, y in zip(b1, b2):
+            assert torch.equal(x["state"], y["state"])
+    finally:
+        if os.path.exists(cache):
+            os.unlink(cache)
+
+
+def test_full_amr_hierarchy_sampled(cg, gm9, omech9, mech9_path):
+    """The full 3-level, 96-box hierarchy in one graph launch; the oracle checks
+    up to 400 sampled cells per box (all of them hot on level 2)."""
+    import torch
+    hier = wl.amr_hierarchy(mech9_path)
+    ncells = sum(b["state"].shape[1] for b in hier)
+    print(f"[amr] {len(hier)} boxes, {ncells} cells", flush=True)
+    boxes = gpu_boxes(hier)
+    g = cg.chem_graph_capture_batched(gm9, boxes)
+    g.launch()
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(99))
+    flagged = checked = 0
+    for hb, gb in zip(hier, boxes):
+        n = hb["state"].shape[1]
+        hot = np.where(hb["hot"])[0]
+        pick = hot[:200] if len(hot) else np.array([], int)
+        pick = np.concatenate([pick, rng.choice(n, 200, replace=False)])
+        sub = np.ascontiguousarray(hb["state"][:, pick])
+        c, cst, _ = oracle_subcalls(omech9, sub, hb["dt"], hb["n_sub"])
+        gst = gb["status"].cpu().numpy()[pick]
+        assert np.array_equal(gst, cst)
+        gsub = np.ascontiguousarray(gb["state"].cpu().numpy()[:, pick])
+        bad = parity_violations(gsub, c, 9)
+        flagged += int(bad.sum())
+        checked += len(pick)
+    print(f"[parity] full AMR: {checked} sampled cells, {flagged} flagged", flush=True)
+    assert flagged <= 0.02 * checked
+    g.close()
