@@ -47,6 +47,7 @@ def lib():
         L.or_mech_free.argtypes = [P]
         L.or_mech_dims.argtypes = [P, C.POINTER(I), C.POINTER(I), C.POINTER(I)]
         L.or_mech_species.argtypes = [P, P, P]
+        L.or_mech_elements.argtypes = [P, P]
         L.or_mech_stoich.argtypes = [P, P]
         L.or_thermo.argtypes = [P, D, P, P, P]
         L.or_rates.argtypes = [P, D, P, P, P, P, P]
@@ -89,6 +90,8 @@ class Mech:
         self.W = np.zeros(self.ns)
         self.comp = np.zeros((self.ns, self.ne), dtype=np.int32)
         lib().or_mech_species(h, _ptr(self.W), _ptr(self.comp))
+        self.ew = np.zeros(self.ne)
+        lib().or_mech_elements(h, _ptr(self.ew))
         self.nu = np.zeros((self.nr, self.ns))
         lib().or_mech_stoich(h, _ptr(self.nu))
 

@@ -57,6 +57,7 @@ typedef struct {
 typedef struct {
     int ne, ns, nr;
     double pstd;
+    double *ew;      /* [ne] element atomic weights */
     char (*sp_name)[32];
     double *W;       /* [ns] */
     int *comp;       /* [ns*ne] */
@@ -98,7 +99,7 @@ void or_mech_free(or_mech *m) {
     if (!m) return;
     if (m->rx)
         for (int j = 0; j < m->nr; j++) free(m->rx[j].eff);
-    free(m->rx); free(m->sp_name); free(m->W); free(m->comp);
+    free(m->rx); free(m->sp_name); free(m->W); free(m->comp); free(m->ew);
     free(m->Tmid); free(m->lo); free(m->hi); free(m);
 }
 
@@ -123,7 +124,15 @@ int or_mech_load(const char *path, or_mech **out) {
         if (strcmp(t, "pstd") == 0) { m->pstd = strtod(next_tok(&p), NULL); continue; }
         if (strcmp(t, "elements") == 0) {
             m->ne = atoi(next_tok(&p));
-            for (int e = 0; e < m->ne; e++) { if (!read_line(f, buf, sizeof buf)) FAIL(); line++; }
+            m->ew = calloc(m->ne > 0 ? m->ne : 1, sizeof(double));
+            for (int e = 0; e < m->ne; e++) {
+                if (!read_line(f, buf, sizeof buf)) FAIL();
+                line++;
+                p = buf;
+                t = next_tok(&p); if (!t) FAIL();
+                t = next_tok(&p); if (!t) FAIL();
+                m->ew[e] = strtod(t, NULL);
+            }
             continue;
         }
         if (strcmp(t, "species") == 0) {
@@ -205,6 +214,10 @@ int or_mech_load(const char *path, or_mech **out) {
 
 void or_mech_dims(const or_mech *m, int *ne, int *ns, int *nr) {
     *ne = m->ne; *ns = m->ns; *nr = m->nr;
+}
+
+void or_mech_elements(const or_mech *m, double *ew) {
+    for (int e = 0; e < m->ne; e++) ew[e] = m->ew[e];
 }
 
 void or_mech_species(const or_mech *m, double *W, int *comp) {
