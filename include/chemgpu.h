@@ -162,6 +162,99 @@ void chem_graph_destroy(chem_graph g);
 int chem_autotune(chem_mech m, const chem_box *boxes, int32_t n_boxes, const chem_opts *base,
                   int32_t reps, const char *cache_path, void *stream, chem_opts *best);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate.  The paper names machine-learned acceleration of the
+ * chemistry as future work (Sec. 7) without a design; this one is an MLP
+ * mapping one cell's (T, ln p, ln dt, Y_1..Y_N) to the increment
+ * (dT, dY_1..dY_N) of one flow step: N+3 -> 128 -> 128 -> 128 -> N+1, SiLU
+ * hidden layers, BF16 GEMM operands with FP32 accumulation on the matrix
+ * cores, FP32 master weights, inputs and outputs standardised by the mean and
+ * standard deviation of the first training set.  Parameter vector (FP32):
+ * W1[128][N+3] b1[128] W2[128][128] b2 W3[128][128] b3 W4[N+1][128] b4[N+1];
+ * normaliser vector (FP32): mu_in[N+3] sd_in[N+3] mu_out[N+1] sd_out[N+1]
+ * zmin[N+3] zmax[N+3] (zmin/zmax: the standardised training hull).
+ * ------------------------------------------------------------------------ */
+typedef struct chem_surr_s *chem_surr; /* opaque, owned by the library */
+
+/* Trust-test failure bits (0 = trusted). */
+#define CHEM_TRUST_HULL 1      /* a standardised input outside [zmin - m, zmax + m] */
+#define CHEM_TRUST_ELEM 2      /* an element mass fraction changed by more than elem_tol */
+#define CHEM_TRUST_POS 4       /* some Y_k + dY_k < -pos_tol */
+#define CHEM_TRUST_ENERGY 8    /* |e(T+dT, Y+dY) - e(T, Y)| / c_v(T, Y) > energy_tol [K] */
+#define CHEM_TRUST_NONFINITE 16
+
+/* New surrogate for mechanism m (hidden must be 128, depth 3); weights
+ * He-uniform (bound sqrt(6/fan_in)) from a splitmix64 stream seeded by seed,
+ * biases zero.  Synchronises the device. */
+int surrogate_create(chem_mech m, int32_t hidden, int32_t depth, uint64_t seed, chem_surr *out);
+
+/* Inputs N+3, outputs N+1 and parameter count of a surrogate. */
+int surrogate_query(chem_surr s, int32_t *n_in, int32_t *n_out, int64_t *n_params);
+
+/* Copy the FP32 parameter and normaliser vectors to / from host memory
+ * (either pointer may be NULL).  Synchronise the device. */
+int surrogate_get_params(chem_surr s, float *theta_host, float *norm_host);
+int surrogate_set_params(chem_surr s, const float *theta_host, const float *norm_host);
+
+/*
+ * Training pairs from two SoA state blocks of the same cells (layout as
+ * above): X[i] = (T, ln p, ln dt, Y_1..Y_N) of `before` (p from the ideal gas
+ * law, dt = dt_cells[i] if dt_cells is not NULL, else dt) and
+ * Y[i] = after - before for (T, Y_1..Y_N).  X is float[n][N+3], Y is
+ * float[n][N+1], all device memory.  Enqueue only.
+ */
+int surrogate_make_pairs(chem_mech m, const double *before, const double *after, int64_t ld,
+                         int64_t n, double dt, const double *dt_cells, float *X, float *Y,
+                         void *stream);
+
+/*
+ * Train on n raw pairs (device float X[n][N+3], Y[n][N+1]): the first call
+ * fits the normaliser and the hull on its data; then `epochs` passes of
+ * floor(n / batch) Adam steps (beta 0.9 / 0.999, eps 1e-8, learning rate
+ * lr with a cosine decay to zero over the call) on the MSE of the
+ * standardised outputs.  Each epoch visits samples in the order
+ * i -> (a i + b) mod n with a coprime to n, drawn from `seed`.  loss_host
+ * (may be NULL) receives the mean training loss of each epoch.  Synchronises
+ * `stream`.
+ */
+int surrogate_train(chem_surr s, const float *X, const float *Y, int64_t n, int32_t epochs,
+                    int32_t batch, float lr, uint64_t seed, void *stream, float *loss_host);
+
+/* Network outputs (standardised, float[n][N+1]) for raw inputs X
+ * (float[n][N+3]).  Synchronises `stream`. */
+int surrogate_forward(chem_surr s, const float *X, int64_t n, float *out, void *stream);
+
+/* Gradient of the batch MSE for already standardised Xn[B][N+3], Yn[B][N+1]
+ * into grad_out (device float[n_params], may be NULL); loss_host (may be
+ * NULL) receives the loss and then the call synchronises `stream`. */
+int surrogate_grad(chem_surr s, const float *Xn, const float *Yn, int32_t B, float *grad_out,
+                   float *loss_host, void *stream);
+
+/*
+ * One flow step of dt for n_cells cells through the surrogate: features in
+ * FP64, the MLP on the matrix cores, then the FP64 trust test with
+ * trust = {hull_margin, elem_tol, pos_tol, energy_tol}.  Trusted cells get
+ * T + dT, Y + dY in place (rho and h untouched).  Untrusted cells keep their
+ * state and, if `fallback` is non-zero, are integrated from it by the FP64
+ * LSRK path (opts as for chem_integrate) in the same stream, with no host
+ * round trip: a device-side list feeds the persistent kernel.  Optional
+ * device outputs: trust_code int32[n] (CHEM_TRUST_* bits), out_std
+ * float[n][N+1] (raw network outputs), status / counts (as chem_integrate,
+ * written for fallback cells only).  n_fallback_host (may be NULL) receives
+ * the number of untrusted cells and then the call synchronises `stream`.
+ */
+int surrogate_infer(chem_surr s, chem_mech m, double *state, int64_t ld, int64_t n_cells, double dt,
+                    const double trust[4], int32_t fallback, const chem_opts *opts, void *stream,
+                    int32_t *trust_code, float *out_std, int32_t *status, int32_t *counts,
+                    int64_t *n_fallback_host);
+
+/* Save / load parameters and normaliser (binary; tied to the mechanism hash). */
+int surrogate_save(chem_surr s, const char *path);
+int surrogate_load(chem_mech m, const char *path, chem_surr *out);
+
+/* Release a surrogate (synchronises the device). */
+void surrogate_free(chem_surr s);
+
 /* Message for a return code; valid for the life of the process. */
 const char *chem_strerror(int code);
 

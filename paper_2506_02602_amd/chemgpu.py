@@ -147,6 +147,149 @@ def chem_integrate(mech: Mechanism, state, dt: float, opts: chem_opts | None = N
                                _stream(stream), _ptr(status), _ptr(counts)), "chem_integrate")
 
 
+_lib.surrogate_create.argtypes = [_P, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_P)]
+_lib.surrogate_query.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+_lib.surrogate_get_params.argtypes = [_P, _P, _P]
+_lib.surrogate_set_params.argtypes = [_P, _P, _P]
+_lib.surrogate_make_pairs.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_double, _P, _P, _P, _P]
+_lib.surrogate_train.argtypes = [_P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
+                                 _P, _P]
+_lib.surrogate_forward.argtypes = [_P, _P, C.c_int64, _P, _P]
+_lib.surrogate_grad.argtypes = [_P, _P, _P, C.c_int32, _P, C.POINTER(C.c_float), _P]
+_lib.surrogate_infer.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_double, C.POINTER(C.c_double),
+                                 C.c_int32, C.POINTER(chem_opts), _P, _P, _P, _P, _P,
+                                 C.POINTER(C.c_int64)]
+_lib.surrogate_save.argtypes = [_P, C.c_char_p]
+_lib.surrogate_load.argtypes = [_P, C.c_char_p, C.POINTER(_P)]
+_lib.surrogate_free.argtypes = [_P]
+_lib.surrogate_free.restype = None
+for _n in ("surrogate_create", "surrogate_query", "surrogate_get_params", "surrogate_set_params",
+           "surrogate_make_pairs", "surrogate_train", "surrogate_forward", "surrogate_grad",
+           "surrogate_infer", "surrogate_save", "surrogate_load"):
+    getattr(_lib, _n).restype = C.c_int
+
+TRUST_HULL, TRUST_ELEM, TRUST_POS, TRUST_ENERGY, TRUST_NONFINITE = 1, 2, 4, 8, 16
+
+
+class Surrogate:
+    """Owns a ``chem_surr`` handle (see include/chemgpu.h)."""
+
+    def __init__(self, mech: Mechanism, seed: int = 0, handle=None):
+        self.mech = mech
+        if handle is None:
+            h = _P()
+            _check(_lib.surrogate_create(mech.handle, 128, 3, int(seed), C.byref(h)),
+                   "surrogate_create")
+            handle = h
+        self.handle = handle
+        ni, no, P = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(_lib.surrogate_query(self.handle, C.byref(ni), C.byref(no), C.byref(P)),
+               "surrogate_query")
+        self.n_in, self.n_out, self.n_params = ni.value, no.value, P.value
+
+    @property
+    def norm_size(self):
+        return 4 * self.n_in + 2 * self.n_out
+
+    def get_params(self):
+        import numpy as np
+        th = np.zeros(self.n_params, np.float32)
+        nm = np.zeros(self.norm_size, np.float32)
+        _check(_lib.surrogate_get_params(self.handle, th.ctypes.data, nm.ctypes.data),
+               "surrogate_get_params")
+        return th, nm
+
+    def set_params(self, theta=None, norm=None):
+        import numpy as np
+        th = None if theta is None else np.ascontiguousarray(theta, np.float32)
+        nm = None if norm is None else np.ascontiguousarray(norm, np.float32)
+        _check(_lib.surrogate_set_params(self.handle, None if th is None else th.ctypes.data,
+                                         None if nm is None else nm.ctypes.data),
+               "surrogate_set_params")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.surrogate_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def surrogate_create(mech: Mechanism, seed: int = 0) -> Surrogate:
+    return Surrogate(mech, seed)
+
+
+def surrogate_make_pairs(mech: Mechanism, before, after, dt=0.0, dt_cells=None, X=None, Y=None,
+                         stream=None):
+    import torch
+    n = before.shape[1]
+    if X is None:
+        X = torch.empty((n, mech.n_species + 3), dtype=torch.float32, device=before.device)
+    if Y is None:
+        Y = torch.empty((n, mech.n_species + 1), dtype=torch.float32, device=before.device)
+    _check(_lib.surrogate_make_pairs(mech.handle, before.data_ptr(), after.data_ptr(), n, n,
+                                     float(dt), _ptr(dt_cells), X.data_ptr(), Y.data_ptr(),
+                                     _stream(stream)), "surrogate_make_pairs")
+    return X, Y
+
+
+def surrogate_train(s: Surrogate, X, Y, epochs=1, batch=4096, lr=1e-3, seed=0, stream=None):
+    import numpy as np
+    loss = np.zeros(max(epochs, 1), np.float32)
+    _check(_lib.surrogate_train(s.handle, X.data_ptr(), Y.data_ptr(), X.shape[0], int(epochs),
+                                int(batch), float(lr), int(seed), _stream(stream), loss.ctypes.data),
+           "surrogate_train")
+    return loss[:epochs]
+
+
+def surrogate_forward(s: Surrogate, X, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((X.shape[0], s.n_out), dtype=torch.float32, device=X.device)
+    _check(_lib.surrogate_forward(s.handle, X.data_ptr(), X.shape[0], out.data_ptr(),
+                                  _stream(stream)), "surrogate_forward")
+    return out
+
+
+def surrogate_grad(s: Surrogate, Xn, Yn, grad=None, stream=None):
+    import torch
+    if grad is None:
+        grad = torch.empty(s.n_params, dtype=torch.float32, device=Xn.device)
+    loss = C.c_float()
+    _check(_lib.surrogate_grad(s.handle, Xn.data_ptr(), Yn.data_ptr(), Xn.shape[0], grad.data_ptr(),
+                               C.byref(loss), _stream(stream)), "surrogate_grad")
+    return grad, loss.value
+
+
+def surrogate_infer(s: Surrogate, mech: Mechanism, state, dt, trust, fallback=True, opts=None,
+                    stream=None, trust_code=None, out_std=None, status=None, counts=None,
+                    n_cells=None, want_count=False):
+    ld = state.shape[1]
+    n = ld if n_cells is None else int(n_cells)
+    tr = (C.c_double * 4)(*[float(x) for x in trust])
+    o = opts if opts is not None else make_opts()
+    cnt = C.c_int64(-1)
+    _check(_lib.surrogate_infer(s.handle, mech.handle, state.data_ptr(), ld, n, float(dt), tr,
+                                1 if fallback else 0, C.byref(o), _stream(stream), _ptr(trust_code),
+                                _ptr(out_std), _ptr(status), _ptr(counts),
+                                C.byref(cnt) if want_count else None), "surrogate_infer")
+    return cnt.value if want_count else None
+
+
+def surrogate_save(s: Surrogate, path: str) -> None:
+    _check(_lib.surrogate_save(s.handle, path.encode()), "surrogate_save")
+
+
+def surrogate_load(mech: Mechanism, path: str) -> Surrogate:
+    h = _P()
+    _check(_lib.surrogate_load(mech.handle, path.encode(), C.byref(h)), "surrogate_load")
+    return Surrogate(mech, handle=h)
+
+
 def make_boxes(boxes):
     """boxes: list of dicts with keys state (CUDA float64 [N+3, ld]), dt,
     n_sub (default 1), level (default 0), status, counts (optional tensors),
@@ -217,4 +360,7 @@ def exported_symbols():
     return ["chem_mech_load", "chem_mech_query", "chem_mech_free", "chem_workspace_reserve",
             "chem_integrate", "chem_integrate_batched", "chem_graph_capture_batched",
             "chem_graph_launch", "chem_graph_destroy", "chem_autotune", "chem_strerror",
-            "chem_last_error"]
+            "chem_last_error", "surrogate_create", "surrogate_query", "surrogate_get_params",
+            "surrogate_set_params", "surrogate_make_pairs", "surrogate_train", "surrogate_forward",
+            "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
+            "surrogate_free"]

@@ -54,6 +54,7 @@ def parse(path: str) -> dict:
         elif key == "elements":
             ne = int(tok[1])
             m["elements"] = [lines[i + 1 + e].split()[0] for e in range(ne)]
+            m["element_weights"] = [float(lines[i + 1 + e].split()[1]) for e in range(ne)]
             i += 1 + ne
         elif key == "species":
             ns = int(tok[1])
@@ -62,6 +63,7 @@ def parse(path: str) -> dict:
                 t = lines[i + 1 + k].split()
                 vals = [float(x) for x in t[2 + ne:]]
                 m["species"].append(dict(name=t[0], W=float(t[1]), Tmid=vals[1],
+                                         comp=[int(x) for x in t[2:2 + ne]],
                                          lo=vals[3:10], hi=vals[10:17]))
             i += 1 + ns
         elif key == "reactions":
@@ -231,6 +233,42 @@ def gen_rhs(m: dict) -> str:
     return "\n".join(L)
 
 
+def gen_aux(m: dict) -> str:
+    """Constants and thermo helpers used by the surrogate's features and trust
+    test: molecular weights, element mass coefficients a_ek m_e / W_k, and the
+    mixture internal energy e = R T sum_k Y_k (h_k/RT - 1)/W_k [erg/g] with
+    c_v = R sum_k Y_k (cp_k/R - 1)/W_k [erg/(g K)] from the same NASA-7 fits."""
+    sp = m["species"]
+    N = len(sp)
+    E = len(m["elements"])
+    L = []
+    L.append(f"  static constexpr int NE = {E};")
+    L.append("  static constexpr double W[NS] = {" + ", ".join(lit(s["W"]) for s in sp) + "};")
+    coefs = []
+    for e, el in enumerate(m["elements"]):
+        aw = m["element_weights"][e]
+        coefs.append("{" + ", ".join(lit(s["comp"][e] * aw / s["W"]) for s in sp) + "}")
+    L.append("  static constexpr double ELEM[NE][NS] = {" + ", ".join(coefs) + "};")
+    L.append("  __device__ __forceinline__ static void energy_cv(double T, const double* Y, "
+             "double& e, double& cv) {")
+    L.append("    const double invT = 1.0 / T;")
+    L.append("    double se = 0.0, sc = 0.0;")
+    for k, s in enumerate(sp):
+        iw = lit(1.0 / s["W"])
+        for rng, head in (("lo", f"    if (T < {lit(s['Tmid'])}) {{"), ("hi", "    } else {")):
+            a = s[rng]
+            hm1 = _horner([a[0] - 1.0, a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5], "T")
+            cpm1 = _horner([a[0] - 1.0] + list(a[1:5]), "T")
+            L.append(head)
+            L.append(f"      se += Y[{k}] * {iw} * ({hm1} + {lit(a[5])} * invT);")
+            L.append(f"      sc += Y[{k}] * {iw} * ({cpm1});")
+        L.append("    }")
+    L.append(f"    e = {lit(R_CGS)} * T * se;")
+    L.append(f"    cv = {lit(R_CGS)} * sc;")
+    L.append("  }")
+    return "\n".join(L)
+
+
 def op_counts(m: dict) -> dict:
     """Algorithmic FP64 operation counts of one RHS evaluation as generated.
 
@@ -302,6 +340,7 @@ def gen_header(path: str) -> tuple[str, dict]:
         f"  static constexpr unsigned long long HASH = 0x{m['hash']:016x}ULL;",
         f"  static constexpr const char* NAME = \"{m['name']}\";",
         gen_rhs(m),
+        gen_aux(m),
         "};",
     ]
     return "\n".join(body) + "\n", dict(tag=tag, hash=m["hash"], ns=N, nr=len(m["reactions"]),

@@ -47,6 +47,7 @@ struct BoxDesc {
   int32_t pad;
   int32_t* status;
   int32_t* counts;
+  const int32_t* index;  // NULL, or the cell index of each of this block's pool items
 };
 
 struct PoolArgs {
@@ -54,6 +55,7 @@ struct PoolArgs {
   const BoxDesc* boxes;        // device table, sorted by start
   int32_t n_boxes;
   int64_t total;               // pool size
+  const unsigned int* total_dev;  // NULL, or a device word holding the pool size
   unsigned long long* next;    // pool counter (zeroed before launch)
   Control c;
   int chunk;
@@ -72,6 +74,11 @@ __device__ __forceinline__ int find_box(const PoolArgs& a, int64_t g) {
 
 __device__ __forceinline__ const BoxDesc& box_ref(const PoolArgs& a, int b) {
   return a.boxes ? a.boxes[b] : a.one;
+}
+
+__device__ __forceinline__ int64_t cell_index(const BoxDesc& bd, int64_t g) {
+  const int64_t j = g - bd.start;
+  return bd.index ? (int64_t)bd.index[j] : j;
 }
 
 template <class M>
@@ -159,6 +166,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   double u[N1], t = 0.0, h = 0.0, rho = 1.0;
   int nacc = 0, nrej = 0, sub = 0, base = 0;
   int bx = 0;
+  const int64_t total = a.total_dev ? (int64_t)*a.total_dev : a.total;
 
   // claim the first B items
   if (tid == 0) {
@@ -172,11 +180,11 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
     if (tid >= free_from) {
       const int64_t g = s_base + (tid - free_from);
       item = -1;
-      if (g < a.total) {
+      if (g < total) {
         item = g;
         bx = find_box(a, g);
         const BoxDesc& bd = box_ref(a, bx);
-        const int64_t i = g - bd.start;
+        const int64_t i = cell_index(bd, g);
         load_cell<M>(bd, i, u, rho, h);
         nacc = nrej = 0; sub = 0; base = 0; t = 0.0;
         if (!all_finite(u, rho)) {
@@ -212,7 +220,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
           if (budget > 0) continue;
           break;
         }
-        store_cell<M>(bd, item - bd.start, u, h, st, nacc, nrej);
+        store_cell<M>(bd, cell_index(bd, item), u, h, st, nacc, nrej);
         item = -1;
         break;
       }
@@ -249,7 +257,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
       if (want > 0) {
         const unsigned long long cur = __hip_atomic_load(a.next, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
-        if ((int64_t)cur < a.total) {
+        if ((int64_t)cur < total) {
           gbase = (long long)atomicAdd(a.next, (unsigned long long)want);
           take = want;
         }
@@ -277,10 +285,16 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
     }
     const int take = s_take;
     __syncthreads();  // LDS slots and s_* reused next round
-    if (A == 0 && (take == 0 || s_base >= a.total)) break;
+    if (A == 0 && (take == 0 || s_base >= total)) break;
     free_from = take > 0 ? A : B;
   }
 }
+
+}  // namespace
+
+#include "surrogate_kernels.hip.h"
+
+namespace {
 
 // ------------------------------------------------------------- registry
 struct MechEntry {
@@ -291,6 +305,9 @@ struct MechEntry {
   hipError_t (*launch_persistent)(const PoolArgs&, int block, int grid, hipStream_t);
   int (*max_blocks_per_cu)(int block);
   size_t (*lds_per_lane)();
+  hipError_t (*launch_surr_infer)(const surr::InferArgs&, int grid, hipStream_t);
+  hipError_t (*launch_make_pairs)(const double*, const double*, long, long, double, const double*,
+                                  float*, float*, hipStream_t);
 };
 
 // Kernels are instantiated for launch bounds 256 (blocks of 64..256 threads)
@@ -338,7 +355,8 @@ size_t lds_per_lane() {
 }
 
 #define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, &launch_direct<M>, &launch_persistent<M>, \
-                       &max_blocks_per_cu<M>, &lds_per_lane<M>},
+                       &max_blocks_per_cu<M>, &lds_per_lane<M>, \
+                       &launch_surr_infer<M>, &launch_make_pairs<M>},
 const MechEntry g_registry[] = {CHEM_FOR_EACH_MECH(CHEM_ENTRY)};
 #undef CHEM_ENTRY
 
@@ -486,7 +504,8 @@ int build_table(const chem_box* boxes, int32_t n, std::vector<BoxDesc>& out, int
     if (b.n_sub < 1) return fail(CHEM_EINVAL, "box: n_sub must be >= 1");
     if (b.n_cells == 0) continue;
     if (!b.state) return fail(CHEM_EINVAL, "box: null state");
-    out.push_back(BoxDesc{b.state, b.ld, b.n_cells, start, b.dt, b.n_sub, 0, b.status, b.counts});
+    out.push_back(BoxDesc{b.state, b.ld, b.n_cells, start, b.dt, b.n_sub, 0, b.status, b.counts,
+                          nullptr});
     start += b.n_cells;
   }
   *total = start;
@@ -633,7 +652,7 @@ int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, doub
   if (n_cells == 0) return CHEM_OK;
   hipStream_t s = (hipStream_t)stream;
   PoolArgs a{};
-  a.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts};
+  a.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts, nullptr};
   a.boxes = nullptr;
   a.n_boxes = 1;
   a.total = n_cells;
@@ -850,3 +869,5 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
 }
 
 }  // extern "C"
+
+#include "surrogate_api.hip.h"

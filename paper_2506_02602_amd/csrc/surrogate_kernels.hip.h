@@ -1,0 +1,560 @@
+// Learned-surrogate kernels: BF16 MFMA (gfx950 v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation) for training and inference of the 3-hidden-layer SiLU
+// MLP that maps (T, ln p, ln dt, Y_1..Y_N) to the increment (dT, dY) of one
+// flow step, plus the FP64 feature and trust-test code around it.
+//
+// MFMA operand layout used throughout (one wave, D = A B, A 16x32, B 32x16):
+//   lane l supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16],
+//   j = 0..7, and receives D[4 (l / 16) + i][l % 16], i = 0..3.
+// BF16 values are kept as their 16-bit patterns (round to nearest even from
+// FP32).
+#pragma once
+
+namespace surr {
+
+constexpr int HID = 128;
+
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(unsigned short b) {
+  return __uint_as_float(((unsigned)b) << 16);
+}
+
+__device__ __forceinline__ f32x4 mfma(v8s a, v8s b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+
+__device__ __forceinline__ float dsilu_f(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// ----------------------------------------------------------- training GEMM
+// C[M x N] = A[M x K] B[K x N] with BF16 operands addressed by strides; one
+// wave per 16x16 output tile; blockIdx.z splits K (partial sums written to
+// C + z * cz, reduced by a separate kernel).
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_DSILU = 3 };
+
+struct GemmArgs {
+  const unsigned short* A; long sam, sak;
+  const unsigned short* B; long sbk, sbn;
+  int M, N, K;
+  float* C; long scm, scn, cz;
+  unsigned short* Cb; long sbm, sbc;   // BF16 copy of the epilogue result (optional)
+  const float* bias;
+  const float* Z; long szm, szn;       // saved pre-activations for EPI_DSILU
+  int kper;                            // K range per split (multiple of 32)
+};
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tiles_n = (g.N + 15) >> 4;
+  const long tile = (long)blockIdx.x * 4 + wave;
+  const long tm = tile / tiles_n, tn = tile % tiles_n;
+  if (tm * 16 >= g.M) return;
+  const int r = lane & 15, grp = lane >> 4;
+  const long kbeg = (long)blockIdx.z * g.kper;
+  const long kend = kbeg + g.kper < g.K ? kbeg + g.kper : g.K;
+  const long m = tm * 16 + r, n = tn * 16 + r;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (long k0 = kbeg; k0 < kend; k0 += 32) {
+    v8s a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const long k = k0 + grp * 8 + j;
+      a[j] = (m < g.M && k < kend) ? (short)g.A[m * g.sam + k * g.sak] : (short)0;
+      b[j] = (n < g.N && k < kend) ? (short)g.B[k * g.sbk + n * g.sbn] : (short)0;
+    }
+    acc = mfma(a, b, acc);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const long cm = tm * 16 + grp * 4 + i, cn = tn * 16 + r;
+    if (cm >= g.M || cn >= g.N) continue;
+    float v = acc[i];
+    if (EPI == EPI_BIAS_SILU || EPI == EPI_BIAS) v += g.bias[cn];
+    if (EPI == EPI_DSILU) v *= dsilu_f(g.Z[cm * g.szm + cn * g.szn]);
+    g.C[blockIdx.z * g.cz + cm * g.scm + cn * g.scn] = v;
+    if (EPI == EPI_BIAS_SILU) g.Cb[cm * g.sbm + cn * g.sbc] = f2bf(silu_f(v));
+    if (EPI == EPI_DSILU) g.Cb[cm * g.sbm + cn * g.sbc] = f2bf(v);
+  }
+}
+
+// sum of `splits` partial [rows x cols] blocks into dst (row-major)
+__global__ void reduce_splits(const float* part, int splits, long stride, long count, float* dst) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float s = 0.f;
+  for (int k = 0; k < splits; ++k) s += part[k * stride + i];
+  dst[i] = s;
+}
+
+// column sums of a BF16 [rows x cols] matrix (bias gradients); one block per column
+__global__ __launch_bounds__(256) void colsum_bf16(const unsigned short* x, long rows, int cols,
+                                                   float* dst) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (long r = threadIdx.x; r < rows; r += blockDim.x) s += bf2f(x[r * cols + c]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dst[c] = red[0];
+}
+
+// batch gather through the epoch's permutation src = (pa * i + pb) mod n
+__global__ void gather_batch(const float* Xn, const float* Yn, long n, int ni, int no, long first,
+                             int B, unsigned long long pa, unsigned long long pb,
+                             unsigned short* X0, float* Yb) {
+  const int rr = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= B) return;
+  const unsigned long long idx = (unsigned long long)(first + rr);
+  const long src = (long)((pa * (idx % (unsigned long long)n) + pb) % (unsigned long long)n);
+  for (int k = 0; k < ni; ++k) X0[(long)rr * ni + k] = f2bf(Xn[src * ni + k]);
+  for (int o = 0; o < no; ++o) Yb[(long)rr * no + o] = Yn[src * no + o];
+}
+
+// dL/dout = 2 (out - y) / (B no) as BF16, and the batch's squared error
+__global__ __launch_bounds__(256) void mse_grad(const float* out, const float* y, long count,
+                                                float scale, unsigned short* dout, double* sse) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long)gridDim.x * blockDim.x) {
+    const float d = out[i] - y[i];
+    dout[i] = f2bf(scale * d);
+    s += (double)d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(sse, red[0]);
+}
+
+// Adam on FP32 master weights, then the BF16 copy used by the GEMMs
+__global__ void adam_update(float* theta, float* m, float* v, const float* grad, long P, float lr,
+                            float b1, float b2, float c1, float c2, float eps,
+                            unsigned short* wbf) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const float g = grad[i];
+  const float mi = b1 * m[i] + (1.f - b1) * g;
+  const float vi = b2 * v[i] + (1.f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float th = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  theta[i] = th;
+  wbf[i] = f2bf(th);
+}
+
+__global__ void cast_bf16(const float* x, long n, unsigned short* y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+// per-column mean / std (FP64 sums) of an [n x cols] FP32 matrix; one block per column
+__global__ __launch_bounds__(256) void col_moments(const float* x, long n, int cols, float* mu,
+                                                   float* sd) {
+  __shared__ double s1[256], s2[256];
+  const int c = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (long r = threadIdx.x; r < n; r += blockDim.x) {
+    const double v = x[r * cols + c];
+    a += v;
+    b += v * v;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) { s1[threadIdx.x] += s1[threadIdx.x + w]; s2[threadIdx.x] += s2[threadIdx.x + w]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mean = s1[0] / (double)n;
+    double var = s2[0] / (double)n - mean * mean;
+    double sdv = var > 0 ? sqrt(var) : 0.0;
+    if (!(sdv > 1e-30 * (fabs(mean) + 1e-300))) sdv = 1.0;  // a constant column
+    mu[c] = (float)mean;
+    sd[c] = (float)sdv;
+  }
+}
+
+// standardise an [n x cols] matrix in place
+__global__ void standardise(float* x, long n, int cols, const float* mu, const float* sd) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * cols) return;
+  const int c = (int)(i % cols);
+  x[i] = (x[i] - mu[c]) / sd[c];
+}
+
+// per-column min and max (the training hull); one block per column
+__global__ __launch_bounds__(256) void col_minmax(const float* x, long n, int cols, float* zmin,
+                                                  float* zmax) {
+  __shared__ float lo[256], hi[256];
+  const int c = blockIdx.x;
+  float mn = 3.4e38f, mx = -3.4e38f;
+  for (long r = threadIdx.x; r < n; r += blockDim.x) {
+    const float z = x[r * cols + c];
+    mn = fminf(mn, z);
+    mx = fmaxf(mx, z);
+  }
+  lo[threadIdx.x] = mn;
+  hi[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      lo[threadIdx.x] = fminf(lo[threadIdx.x], lo[threadIdx.x + w]);
+      hi[threadIdx.x] = fmaxf(hi[threadIdx.x], hi[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { zmin[c] = lo[0]; zmax[c] = hi[0]; }
+}
+
+// FP64 -> BF16 pattern, rounded once (nearest even) to 8 significant bits
+__device__ __forceinline__ unsigned short d2bf(double x) {
+  if (!(fabs(x) < 3.0e38)) return f2bf((float)x);
+  unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  b += 0x00000FFFFFFFFFFFull + ((b >> 45) & 1ull);
+  b &= ~0x00001FFFFFFFFFFFull;
+  return (unsigned short)(__float_as_uint((float)__longlong_as_double((long long)b)) >> 16);
+}
+
+// Packed column order of the hidden layers: column c of a packed matrix holds
+// input feature perm(c), so that a layer's MFMA output registers are already
+// the next layer's B operand (no LDS round trip between layers).
+__device__ __forceinline__ int packed_feature(int c) {
+  const int kc = c >> 5, rr = c & 31, gg = rr >> 3, j = rr & 7;
+  return 32 * kc + (j < 4 ? 4 * gg + j : 16 + 4 * gg + (j - 4));
+}
+
+// theta (FP32 master, natural layout) -> BF16 packed weights + FP32 biases
+__global__ void pack_weights(const float* theta, int ni, int no, int kc1, int ot4,
+                             unsigned short* wp, float* bp) {
+  const long w1 = (long)HID * kc1 * 32, w2 = (long)HID * HID, w4 = (long)ot4 * 16 * HID;
+  const long oW1 = 0, ob1 = (long)HID * ni, oW2 = ob1 + HID, ob2 = oW2 + (long)HID * HID;
+  const long oW3 = ob2 + HID, ob3 = oW3 + (long)HID * HID, oW4 = ob3 + HID, ob4 = oW4 + (long)no * HID;
+  const long total = w1 + 2 * w2 + w4 + 3 * HID + ot4 * 16;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    if (i < w1) {
+      const long row = i / (kc1 * 32), k = i % (kc1 * 32);
+      wp[i] = k < ni ? f2bf(theta[oW1 + row * ni + k]) : (unsigned short)0;
+    } else if (i < w1 + 2 * w2) {
+      const long j = i - w1, which = j / w2, jj = j % w2, row = jj / HID, c = jj % HID;
+      const long base = which == 0 ? oW2 : oW3;
+      wp[i] = f2bf(theta[base + row * HID + packed_feature((int)c)]);
+    } else if (i < w1 + 2 * w2 + w4) {
+      const long jj = i - w1 - 2 * w2, row = jj / HID, c = jj % HID;
+      wp[i] = row < no ? f2bf(theta[oW4 + row * HID + packed_feature((int)c)]) : (unsigned short)0;
+    } else {
+      const long b = i - (w1 + 2 * w2 + w4);
+      float v;
+      if (b < HID) v = theta[ob1 + b];
+      else if (b < 2 * HID) v = theta[ob2 + b - HID];
+      else if (b < 3 * HID) v = theta[ob3 + b - 2 * HID];
+      else v = (b - 3 * HID) < no ? theta[ob4 + b - 3 * HID] : 0.f;
+      bp[b] = v;
+    }
+  }
+}
+
+struct InferArgs {
+  double* state; long ld; long n; double dt;
+  const unsigned short* wpack; const float* bpack;
+  const float* norm;            // mu_in[ni] sd_in[ni] mu_out[no] sd_out[no] zmin[ni] zmax[ni]
+  double hull_margin, elem_tol, pos_tol, energy_tol;
+  int32_t* fb_list; unsigned* fb_count;
+  int32_t* trust_code; float* out_std;
+};
+
+enum { TRUST_HULL = 1, TRUST_ELEM = 2, TRUST_POS = 4, TRUST_ENERGY = 8, TRUST_NONFINITE = 16 };
+
+template <class M>
+struct InferShape {
+  static constexpr int NS = M::NS, NI = NS + 3, NO = NS + 1;
+  static constexpr int KC1 = (NI + 31) / 32, OT4 = (NO + 15) / 16;
+  static constexpr int WAVES = NS <= 15 ? 4 : 2, CELLS = WAVES * 64;
+  static constexpr long W1 = (long)HID * KC1 * 32, W2 = (long)HID * HID, W4 = (long)OT4 * 16 * HID;
+  static constexpr long WTOT = W1 + 2 * W2 + W4;
+  static constexpr long BTOT = 3 * HID + OT4 * 16;
+  static constexpr long F_OFF = WTOT * 2 + BTOT * 4;           // bytes
+  static constexpr long O_OFF = F_OFF + (long)KC1 * 32 * CELLS * 2;
+  static constexpr long BYTES = O_OFF + (long)OT4 * 16 * CELLS * 4;
+};
+
+// Fused inference: FP64 features -> BF16 MFMA MLP (weights in LDS, hidden
+// activations never leave registers) -> FP64 trust test -> either the new
+// state or an entry in the fallback list for the FP64 integrator.
+template <class M>
+__global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
+  using S = InferShape<M>;
+  constexpr int NS = S::NS, NI = S::NI, NO = S::NO, KC1 = S::KC1, OT4 = S::OT4, CELLS = S::CELLS;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  unsigned short* sW = reinterpret_cast<unsigned short*>(smem);
+  const unsigned short* sW1 = sW;
+  const unsigned short* sW2 = sW + S::W1;
+  const unsigned short* sW3 = sW2 + S::W2;
+  const unsigned short* sW4 = sW3 + S::W2;
+  float* sB = reinterpret_cast<float*>(smem + S::WTOT * 2);
+  unsigned short* sF = reinterpret_cast<unsigned short*>(smem + S::F_OFF);
+  float* sO = reinterpret_cast<float*>(smem + S::O_OFF);
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(a.wpack);
+    uint4* dst = reinterpret_cast<uint4*>(sW);
+    for (long i = tid; i < S::WTOT / 8; i += blockDim.x) dst[i] = src[i];
+    for (long i = tid; i < S::BTOT; i += blockDim.x) sB[i] = a.bpack[i];
+  }
+  __syncthreads();
+  const float* mu_in = a.norm;
+  const float* sd_in = a.norm + NI;
+  const float* mu_out = a.norm + 2 * NI;
+  const float* sd_out = a.norm + 2 * NI + NO;
+  const float* zmin = a.norm + 2 * NI + 2 * NO;
+  const float* zmax = zmin + NI;
+
+  for (long base = (long)blockIdx.x * CELLS; base < a.n; base += (long)gridDim.x * CELLS) {
+    const long cell = base + tid;
+    const bool valid = cell < a.n;
+    int code = 0;
+    // ---- stage 0: features of this thread's cell (FP64), standardised, BF16 to LDS
+    {
+      double f[NI];
+#pragma unroll
+      for (int k = 0; k < NI; ++k) f[k] = 0.0;
+      if (valid) {
+        const double T = a.state[cell];
+        double sy = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const double y = a.state[(k + 1) * a.ld + cell];
+          f[3 + k] = y;
+          sy += y * (1.0 / M::W[k]);
+        }
+        const double rho = a.state[(NS + 1) * a.ld + cell];
+        f[0] = T;
+        f[1] = log(rho * 8.31446261815324e7 * T * sy);
+        f[2] = log(a.dt);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+          const double z = (f[k] - (double)mu_in[k]) / (double)sd_in[k];
+          if (!(z >= (double)zmin[k] - a.hull_margin && z <= (double)zmax[k] + a.hull_margin))
+            code |= TRUST_HULL;
+          f[k] = z;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KC1 * 32; ++k)
+        sF[k * CELLS + tid] = (valid && k < NI) ? d2bf(f[k < NI ? k : 0]) : (unsigned short)0;
+    }
+    __syncthreads();
+    // ---- stage 1: the MLP on this wave's 64 cells (4 column tiles of 16)
+    {
+      const int c0 = wave * 64;
+      f32x4 acc[8][4];
+      v8s bn[4][4];
+#pragma unroll
+      for (int ot = 0; ot < 8; ++ot)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+      // layer 1: B from the feature tile in LDS
+#pragma unroll
+      for (int kc = 0; kc < KC1; ++kc) {
+        v8s b1[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            b1[ct][j] = (short)sF[(kc * 32 + 8 * g + j) * CELLS + c0 + ct * 16 + r16];
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot) {
+          const v8s aw = *reinterpret_cast<const v8s*>(sW1 + (ot * 16 + r16) * (KC1 * 32) + kc * 32 + 8 * g);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = mfma(aw, b1[ct], acc[ot][ct]);
+        }
+      }
+      // layers 2 and 3: epilogue (bias, SiLU, BF16) straight into the next B operand
+#pragma unroll
+      for (int layer = 0; layer < 3; ++layer) {
+        const float* bias = sB + layer * HID;
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int ot = 2 * kc + (j >> 2), i = j & 3;
+              const float zv = acc[ot][ct][i] + bias[ot * 16 + 4 * g + i];
+              bn[kc][ct][j] = (short)f2bf(silu_f(zv));
+            }
+        if (layer == 2) break;
+        const unsigned short* Wl = layer == 0 ? sW2 : sW3;
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot)
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+          for (int ot = 0; ot < 8; ++ot) {
+            const v8s aw = *reinterpret_cast<const v8s*>(Wl + (ot * 16 + r16) * HID + kc * 32 + 8 * g);
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = mfma(aw, bn[kc][ct], acc[ot][ct]);
+          }
+      }
+      // output layer
+      f32x4 acc4[OT4][4];
+#pragma unroll
+      for (int ot = 0; ot < OT4; ++ot)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc4[ot][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+        for (int ot = 0; ot < OT4; ++ot) {
+          const v8s aw = *reinterpret_cast<const v8s*>(sW4 + (ot * 16 + r16) * HID + kc * 32 + 8 * g);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc4[ot][ct] = mfma(aw, bn[kc][ct], acc4[ot][ct]);
+        }
+#pragma unroll
+      for (int ot = 0; ot < OT4; ++ot)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int o = ot * 16 + 4 * g + i;
+            sO[o * CELLS + c0 + ct * 16 + r16] = acc4[ot][ct][i] + sB[3 * HID + o];
+          }
+    }
+    __syncthreads();
+    // ---- stage 2: de-standardise and trust-test this thread's cell (FP64)
+    bool fall = false;
+    if (valid) {
+      double inc[NO];
+      bool fin = true;
+#pragma unroll
+      for (int k = 0; k < NO; ++k) {
+        const float o = sO[k * CELLS + tid];
+        if (a.out_std) a.out_std[cell * NO + k] = o;
+        inc[k] = (double)o * (double)sd_out[k] + (double)mu_out[k];
+        fin = fin && isfinite(inc[k]);
+      }
+      const double T = a.state[cell];
+      double Y[NS], Y1[NS];
+      double ymin = 1e300;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        Y[k] = a.state[(k + 1) * a.ld + cell];
+        Y1[k] = Y[k] + inc[1 + k];
+        ymin = Y1[k] < ymin ? Y1[k] : ymin;
+      }
+      const double T1 = T + inc[0];
+      if (!fin) {
+        code |= TRUST_NONFINITE;
+      } else {
+#pragma unroll
+        for (int e = 0; e < M::NE; ++e) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < NS; ++k) s += M::ELEM[e][k] * (Y1[k] - Y[k]);
+          if (fabs(s) > a.elem_tol) code |= TRUST_ELEM;
+        }
+        if (ymin < -a.pos_tol) code |= TRUST_POS;
+        double e0, cv0, e1, cv1;
+        M::energy_cv(T, Y, e0, cv0);
+        M::energy_cv(T1, Y1, e1, cv1);
+        if (!(fabs(e1 - e0) / cv0 <= a.energy_tol)) code |= TRUST_ENERGY;
+      }
+      if (a.trust_code) a.trust_code[cell] = code;
+      if (code == 0) {
+        a.state[cell] = T1;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) a.state[(k + 1) * a.ld + cell] = Y1[k];
+      } else {
+        fall = true;
+      }
+    }
+    if (a.fb_list) {
+      const unsigned long long ball = __ballot(fall);
+      if (ball) {
+        const int cnt = __popcll(ball);
+        const int leader = __ffsll((long long)ball) - 1;
+        unsigned base_idx = 0;
+        if (lane == leader) base_idx = atomicAdd(a.fb_count, (unsigned)cnt);
+        base_idx = __shfl(base_idx, leader);
+        if (fall) a.fb_list[base_idx + __popcll(ball & ((1ull << lane) - 1ull))] = (int32_t)cell;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// raw features and increments of (state_before -> state_after) pairs
+template <class M>
+__global__ void make_pairs(const double* before, const double* after, long ld, long n, double dt,
+                           const double* dt_cells, float* X, float* Yd) {
+  constexpr int NS = M::NS, NI = NS + 3, NO = NS + 1;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double T = before[i];
+  double sy = 0.0;
+  for (int k = 0; k < NS; ++k) {
+    const double y = before[(k + 1) * ld + i];
+    sy += y * (1.0 / M::W[k]);
+    X[i * NI + 3 + k] = (float)y;
+    Yd[i * NO + 1 + k] = (float)(after[(k + 1) * ld + i] - y);
+  }
+  const double rho = before[(NS + 1) * ld + i];
+  X[i * NI + 0] = (float)T;
+  X[i * NI + 1] = (float)log(rho * 8.31446261815324e7 * T * sy);
+  X[i * NI + 2] = (float)log(dt_cells ? dt_cells[i] : dt);
+  Yd[i * NO + 0] = (float)(after[i] - T);
+}
+
+__global__ void zero_u32(unsigned* p) { *p = 0u; }
+
+}  // namespace surr
+
+template <class M>
+hipError_t launch_surr_infer(const surr::InferArgs& a, int grid, hipStream_t s) {
+  using S = surr::InferShape<M>;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)surr::surr_infer<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)S::BYTES);
+    attr = true;
+  }
+  hipLaunchKernelGGL(surr::surr_infer<M>, dim3(grid), dim3(S::CELLS), S::BYTES, s, a);
+  return hipGetLastError();
+}
+
+template <class M>
+hipError_t launch_make_pairs(const double* before, const double* after, long ld, long n, double dt,
+                             const double* dt_cells, float* X, float* Y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(surr::make_pairs<M>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     before, after, ld, n, dt, dt_cells, X, Y);
+  return hipGetLastError();
+}
