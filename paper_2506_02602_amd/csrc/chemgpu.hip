@@ -231,11 +231,11 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
     const int lane = tid & 63, wave = tid >> 6, nw = (B + 63) >> 6;
     if (lane == 0) s_wave_cnt[wave] = __popcll(ball);
     __syncthreads();
-    int off = 0, total = 0;
+    int off = 0, n_active = 0;
     for (int w = 0; w < nw; ++w) {
       const int cnt = s_wave_cnt[w];
       if (w < wave) off += cnt;
-      total += cnt;
+      n_active += cnt;
     }
     const int rank = off + __popcll(ball & ((1ull << lane) - 1ull));
     if (act) {
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
     if (tid == 0) {
       int take = 0;
       long long gbase = 0;
-      const int want = B - total;
+      const int want = B - n_active;
       if (want > 0) {
         const unsigned long long cur = __hip_atomic_load(a.next, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
       }
       s_base = gbase;
       s_take = take;
-      s_active = total;
+      s_active = n_active;
     }
     __syncthreads();
     const int A = s_active;

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void col_moments(const float* x, long n, int c
     const double mean = s1[0] / (double)n;
     double var = s2[0] / (double)n - mean * mean;
     double sdv = var > 0 ? sqrt(var) : 0.0;
-    if (!(sdv > 1e-30 * (fabs(mean) + 1e-300))) sdv = 1.0;  // a constant column
+    if (!(sdv > 1e-12 * fabs(mean))) sdv = 0.0;  // a constant column: standardised to 0
     mu[c] = (float)mean;
     sd[c] = (float)sdv;
   }
@@ -204,7 +204,7 @@ __global__ void standardise(float* x, long n, int cols, const float* mu, const f
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * cols) return;
   const int c = (int)(i % cols);
-  x[i] = (x[i] - mu[c]) / sd[c];
+  x[i] = sd[c] > 0.f ? (x[i] - mu[c]) / sd[c] : 0.f;
 }
 
 // per-column min and max (the training hull); one block per column
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
         f[2] = log(a.dt);
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
-          const double z = (f[k] - (double)mu_in[k]) / (double)sd_in[k];
+          const double z = sd_in[k] > 0.f ? (f[k] - (double)mu_in[k]) / (double)sd_in[k] : 0.0;
           if (!(z >= (double)zmin[k] - a.hull_margin && z <= (double)zmax[k] + a.hull_margin))
             code |= TRUST_HULL;
           f[k] = z;
@@ -542,7 +542,7 @@ hipError_t launch_surr_infer(const surr::InferArgs& a, int grid, hipStream_t s) 
   using S = surr::InferShape<M>;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void*)surr::surr_infer<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)surr::surr_infer<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)S::BYTES);
     attr = true;
   }

@@ -203,3 +203,26 @@ def test_chunk_and_block_invariance(gmech9, mech9_path):
         g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=chunk, block_size=block)
         assert np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
         assert not parity_violations(g, ref, 9, rtol=1e-12, floor_y=1e-16).any()
+
+
+def test_every_cell_of_a_large_field_is_integrated(gmech9, omech9, mech9_path):
+    """2,097,152 cells = 512 copies of 4096 distinct cells: every cell takes at
+    least one accepted step, every copy ends identical, and equals the oracle
+    (regression for a pool-refill bug that stopped blocks after one chunk)."""
+    import torch
+    from paper_2506_02602_amd import chemgpu
+    base = wl.cells_uniform(mech9_path, n=4096, seed=12)
+    base[0, :512] = np.linspace(1800.0, 2600.0, 512)          # some cells need many steps
+    big = torch.from_numpy(np.ascontiguousarray(np.tile(base, (1, 512)))).cuda()
+    n = big.shape[1]
+    st = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+    cn = torch.zeros(2 * n, dtype=torch.int32, device="cuda")
+    chemgpu.chem_integrate(gmech9, big, wl.DT_FLOW, status=st, counts=cn)
+    torch.cuda.synchronize()
+    assert (st == 0).all()
+    assert (cn[:n] >= 1).all()
+    out = big.cpu().numpy().reshape(12, 512, 4096)
+    assert (out == out[:, :1, :]).all()
+    c = base.copy()
+    omech9.integrate(c, wl.DT_FLOW)
+    assert not parity_violations(np.ascontiguousarray(out[:, 0, :]), c, 9).any()
