@@ -445,7 +445,7 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
     a.fb_count = s->fb_count;
     a.trust_code = trust_code;
     a.out_std = out_std;
-    const int grid = std::max(1, std::min<int>((int)((n_cells + 255) / 256), 2 * m->n_cu));
+    const int grid = std::max(1, std::min<int>((int)((n_cells + 511) / 512), m->n_cu));
     e = m->entry->launch_surr_infer(a, grid, st);
     if (e != hipSuccess) return hip_fail(e, "launch surr_infer");
     if (fallback) {

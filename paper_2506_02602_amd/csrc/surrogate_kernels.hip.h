@@ -18,11 +18,9 @@ typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// FP32 -> BF16 pattern, round to nearest even (gfx950's v_cvt_pk_bf16_f32)
 __device__ __forceinline__ unsigned short f2bf(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
 __device__ __forceinline__ float bf2f(unsigned short b) {
@@ -35,6 +33,12 @@ __device__ __forceinline__ f32x4 mfma(v8s a, v8s b, f32x4 c) {
 }
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+
+// SiLU for the inference epilogue: native exp2 and reciprocal (a few ulp in
+// FP32), far below the BF16 rounding that follows.
+__device__ __forceinline__ float silu_fast(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
 
 __device__ __forceinline__ float dsilu_f(float z) {
   const float s = 1.0f / (1.0f + expf(-z));
@@ -294,22 +298,35 @@ template <class M>
 struct InferShape {
   static constexpr int NS = M::NS, NI = NS + 3, NO = NS + 1;
   static constexpr int KC1 = (NI + 31) / 32, OT4 = (NO + 15) / 16;
-  static constexpr int WAVES = NS <= 15 ? 4 : 2, CELLS = WAVES * 64;
+  static constexpr int WAVES = NS <= 15 ? 8 : 4, THREADS = WAVES * 64;
   static constexpr long W1 = (long)HID * KC1 * 32, W2 = (long)HID * HID, W4 = (long)OT4 * 16 * HID;
   static constexpr long WTOT = W1 + 2 * W2 + W4;
   static constexpr long BTOT = 3 * HID + OT4 * 16;
-  static constexpr long F_OFF = WTOT * 2 + BTOT * 4;           // bytes
-  static constexpr long O_OFF = F_OFF + (long)KC1 * 32 * CELLS * 2;
-  static constexpr long BYTES = O_OFF + (long)OT4 * 16 * CELLS * 4;
+  static constexpr long F_WAVE = (long)KC1 * 32 * 64 * 2;        // bytes per wave
+  static constexpr long O_WAVE = (long)OT4 * 16 * 64 * 4;
+  static constexpr long F_OFF = WTOT * 2 + BTOT * 4;
+  static constexpr long O_OFF = F_OFF + WAVES * F_WAVE;
+  static constexpr long BYTES = O_OFF + WAVES * O_WAVE;
 };
 
-// Fused inference: FP64 features -> BF16 MFMA MLP (weights in LDS, hidden
-// activations never leave registers) -> FP64 trust test -> either the new
-// state or an entry in the fallback list for the FP64 integrator.
+// Orders this wave's LDS writes before its later LDS reads of other lanes'
+// data (a wave executes in lockstep; this keeps the compiler from moving
+// the accesses across the hand-off).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Fused inference: FP64 features -> BF16 MFMA MLP (weights in LDS, shared by
+// the block; hidden activations never leave registers) -> FP64 trust test ->
+// either the new state or an entry in the fallback list for the FP64
+// integrator.  Each wave runs its own 64-cell tiles through all stages with
+// wave-private LDS staging, so waves overlap their FP64 and MFMA phases.
 template <class M>
-__global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
+__global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a) {
   using S = InferShape<M>;
-  constexpr int NS = S::NS, NI = S::NI, NO = S::NO, KC1 = S::KC1, OT4 = S::OT4, CELLS = S::CELLS;
+  constexpr int NS = S::NS, NI = S::NI, NO = S::NO, KC1 = S::KC1, OT4 = S::OT4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   unsigned short* sW = reinterpret_cast<unsigned short*>(smem);
   const unsigned short* sW1 = sW;
@@ -317,10 +334,9 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
   const unsigned short* sW3 = sW2 + S::W2;
   const unsigned short* sW4 = sW3 + S::W2;
   float* sB = reinterpret_cast<float*>(smem + S::WTOT * 2);
-  unsigned short* sF = reinterpret_cast<unsigned short*>(smem + S::F_OFF);
-  float* sO = reinterpret_cast<float*>(smem + S::O_OFF);
-
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
+  unsigned short* sF = reinterpret_cast<unsigned short*>(smem + S::F_OFF + wave * S::F_WAVE);
+  float* sO = reinterpret_cast<float*>(smem + S::O_OFF + wave * S::O_WAVE);
   {
     const uint4* src = reinterpret_cast<const uint4*>(a.wpack);
     uint4* dst = reinterpret_cast<uint4*>(sW);
@@ -335,11 +351,13 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
   const float* zmin = a.norm + 2 * NI + 2 * NO;
   const float* zmax = zmin + NI;
 
-  for (long base = (long)blockIdx.x * CELLS; base < a.n; base += (long)gridDim.x * CELLS) {
-    const long cell = base + tid;
+  const long ntiles = (a.n + 63) / 64;
+  for (long tile = (long)blockIdx.x * S::WAVES + wave; tile < ntiles;
+       tile += (long)gridDim.x * S::WAVES) {
+    const long cell = tile * 64 + lane;
     const bool valid = cell < a.n;
     int code = 0;
-    // ---- stage 0: features of this thread's cell (FP64), standardised, BF16 to LDS
+    // ---- stage 0: this lane's cell features (FP64), standardised, BF16 to LDS
     {
       double f[NI];
 #pragma unroll
@@ -367,19 +385,17 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
       }
 #pragma unroll
       for (int k = 0; k < KC1 * 32; ++k)
-        sF[k * CELLS + tid] = (valid && k < NI) ? d2bf(f[k < NI ? k : 0]) : (unsigned short)0;
+        sF[k * 64 + lane] = (valid && k < NI) ? d2bf(f[k < NI ? k : 0]) : (unsigned short)0;
     }
-    __syncthreads();
+    wave_sync();
     // ---- stage 1: the MLP on this wave's 64 cells (4 column tiles of 16)
     {
-      const int c0 = wave * 64;
       f32x4 acc[8][4];
       v8s bn[4][4];
 #pragma unroll
       for (int ot = 0; ot < 8; ++ot)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-      // layer 1: B from the feature tile in LDS
 #pragma unroll
       for (int kc = 0; kc < KC1; ++kc) {
         v8s b1[4];
@@ -387,7 +403,7 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
         for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
           for (int j = 0; j < 8; ++j)
-            b1[ct][j] = (short)sF[(kc * 32 + 8 * g + j) * CELLS + c0 + ct * 16 + r16];
+            b1[ct][j] = (short)sF[(kc * 32 + 8 * g + j) * 64 + ct * 16 + r16];
 #pragma unroll
         for (int ot = 0; ot < 8; ++ot) {
           const v8s aw = *reinterpret_cast<const v8s*>(sW1 + (ot * 16 + r16) * (KC1 * 32) + kc * 32 + 8 * g);
@@ -395,7 +411,6 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
           for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = mfma(aw, b1[ct], acc[ot][ct]);
         }
       }
-      // layers 2 and 3: epilogue (bias, SiLU, BF16) straight into the next B operand
 #pragma unroll
       for (int layer = 0; layer < 3; ++layer) {
         const float* bias = sB + layer * HID;
@@ -407,7 +422,7 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
             for (int j = 0; j < 8; ++j) {
               const int ot = 2 * kc + (j >> 2), i = j & 3;
               const float zv = acc[ot][ct][i] + bias[ot * 16 + 4 * g + i];
-              bn[kc][ct][j] = (short)f2bf(silu_f(zv));
+              bn[kc][ct][j] = (short)f2bf(silu_fast(zv));
             }
         if (layer == 2) break;
         const unsigned short* Wl = layer == 0 ? sW2 : sW3;
@@ -424,7 +439,6 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
             for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = mfma(aw, bn[kc][ct], acc[ot][ct]);
           }
       }
-      // output layer
       f32x4 acc4[OT4][4];
 #pragma unroll
       for (int ot = 0; ot < OT4; ++ot)
@@ -445,18 +459,18 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int o = ot * 16 + 4 * g + i;
-            sO[o * CELLS + c0 + ct * 16 + r16] = acc4[ot][ct][i] + sB[3 * HID + o];
+            sO[o * 64 + ct * 16 + r16] = acc4[ot][ct][i] + sB[3 * HID + o];
           }
     }
-    __syncthreads();
-    // ---- stage 2: de-standardise and trust-test this thread's cell (FP64)
+    wave_sync();
+    // ---- stage 2: de-standardise and trust-test this lane's cell (FP64)
     bool fall = false;
     if (valid) {
       double inc[NO];
       bool fin = true;
 #pragma unroll
       for (int k = 0; k < NO; ++k) {
-        const float o = sO[k * CELLS + tid];
+        const float o = sO[k * 64 + lane];
         if (a.out_std) a.out_std[cell * NO + k] = o;
         inc[k] = (double)o * (double)sd_out[k] + (double)mu_out[k];
         fin = fin && isfinite(inc[k]);
@@ -507,7 +521,7 @@ __global__ __launch_bounds__(256) void surr_infer(InferArgs a) {
         if (fall) a.fb_list[base_idx + __popcll(ball & ((1ull << lane) - 1ull))] = (int32_t)cell;
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -546,7 +560,7 @@ hipError_t launch_surr_infer(const surr::InferArgs& a, int grid, hipStream_t s) 
                         (int)S::BYTES);
     attr = true;
   }
-  hipLaunchKernelGGL(surr::surr_infer<M>, dim3(grid), dim3(S::CELLS), S::BYTES, s, a);
+  hipLaunchKernelGGL(surr::surr_infer<M>, dim3(grid), dim3(S::THREADS), S::BYTES, s, a);
   return hipGetLastError();
 }
 
