@@ -43,7 +43,99 @@ def parse():
                     choices=["front", "front_hot_tiled", "amr", "stress9", "stress32", "cells"])
     ap.add_argument("--autotune", action="store_true",
                     help="autotune block/chunk on the workload first (amr always tunes)")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate+fallback leg on the 256^3 evaluation field")
+    ap.add_argument("--surrogate-epochs", type=int, default=12)
     return ap.parse_args()
+
+
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+# algorithmic flops of one surrogate evaluation: 2 (12*128 + 128*128 + 128*128 + 128*10)
+SURROGATE_FLOPS_PER_CELL = 2 * (12 * 128 + 2 * 128 * 128 + 128 * 10)
+
+
+def surrogate_leg(args):
+    """Config-5 comparison: train the surrogate on FP64 trajectory pairs, tune
+    the trust thresholds on held-out trajectories, then time plain FP64 and
+    surrogate+fallback on the 256^3 evaluation field (each timed step restores
+    the pristine field first) and judge the trusted cells against FP64."""
+    import torch
+    from paper_2506_02602_amd import chemgpu as cg, surrogate as sg, workloads as wl
+    m = cg.chem_mech_load(wl.mech_file("mech9"))
+    t0 = time.perf_counter()
+    ds = sg.build_dataset(m)
+    t_data = time.perf_counter() - t0
+    n_pairs = int(ds["X"].shape[0])
+    s = cg.Surrogate(m, seed=11)
+    t0 = time.perf_counter()
+    loss = cg.surrogate_train(s, ds["X"], ds["Y"], epochs=args.surrogate_epochs, batch=4096,
+                              lr=3e-3, seed=2)
+    t_train = time.perf_counter() - t0
+    trust, tstats = sg.tune_trust(s, m, sg.validation_states(ds))
+    if trust is None:
+        trust = (0.0, 1e-6, 1e-7, 0.05)
+    del ds
+    torch.cuda.empty_cache()
+    field, out_mask = sg.inference_field(m)
+    n = field.shape[1]
+    work = torch.empty_like(field)
+    ref = field.clone()
+    cg.chem_integrate(m, ref, wl.DT_FLOW)
+    stream = torch.cuda.current_stream()
+    K = max(1, min(args.steps, 5))
+
+    def timed(fn):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(K)]
+        work.copy_(field)
+        fn()                                   # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a, b in ev:
+            work.copy_(field)
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / K, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    t_plain, k_plain = timed(lambda: cg.chem_integrate(m, work, wl.DT_FLOW))
+    t_surr, k_surr = timed(lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True))
+    t_inf, k_inf = timed(lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=False))
+    tc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    work.copy_(field)
+    n_fb = cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True, trust_code=tc,
+                              want_count=True)
+    ok = tc == 0
+    eT, eY = sg.errors(work[:, ok], ref[:, ok], m.n_species)
+    idx = torch.randperm(int(ok.sum()), device="cuda")[:2000000]
+    q = lambda x: float(torch.quantile(x[idx].float(), 0.999))
+    fb = ~ok
+    fT, fY = sg.errors(work[:, fb], ref[:, fb], m.n_species)
+    achieved = SURROGATE_FLOPS_PER_CELL * n / (k_inf * 1e-3) / 1e12
+    return {
+        "workload": "256^3 = 16,777,216 cells: 90% held-out H2/O2/N2 ignition-trajectory states "
+                    "in smooth 3-D blobs, 10% reacting-front states outside the training hull; "
+                    "dt 1e-7 s; 9-species mechanism",
+        "cells": n,
+        "plain_fp64_cells_per_s": n / t_plain, "surrogate_fallback_cells_per_s": n / t_surr,
+        "speedup": t_plain / t_surr,
+        "ms_plain": 1e3 * t_plain, "ms_surrogate_fallback": 1e3 * t_surr,
+        "ms_inference_only": k_inf,
+        "fallback_fraction": n_fb / n,
+        "trust": {"hull_margin": trust[0], "elem_tol": trust[1], "pos_tol": trust[2],
+                  "energy_tol_K": trust[3], "validation": tstats},
+        "trusted_error_vs_fp64": {"max_rel_T": float(eT.max()), "p999_rel_T": q(eT),
+                                  "max_abs_Y": float(eY.max()), "p999_abs_Y": q(eY)},
+        "fallback_cells_max_diff_vs_plain": {"rel_T": float(fT.max()) if fb.any() else 0.0,
+                                             "abs_Y": float(fY.max()) if fb.any() else 0.0},
+        "train": {"pairs": n_pairs, "epochs": args.surrogate_epochs, "batch": 4096,
+                  "first_loss": float(loss[0]), "final_loss": float(loss[-1]),
+                  "data_s": t_data, "train_s": t_train},
+        "roofline_inference": {"bound": "mfma", "achieved": achieved,
+                               "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                               "frac": achieved / PEAK_BF16_MFMA_TFLOPS},
+    }
 
 
 WORKLOADS = {
@@ -209,6 +301,10 @@ def main():
     if not args.no_cpu:
         threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
         out["cpu_baseline"] = cpu_baseline(hboxes, path, threads)
+    if not args.no_surrogate and args.workload == "front":
+        del boxes, pristine, tboxes
+        torch.cuda.empty_cache()
+        out["surrogate"] = surrogate_leg(args)
     print(json.dumps(out), flush=True)
 
 
