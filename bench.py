@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--tail", type=int, default=0,
+                    help="steps after which a cell moves to the cooperative kernel "
+                         "(0 = default, < 0 = never)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--workload", default="front",
@@ -236,7 +239,7 @@ def main():
     mech = chemgpu.chem_mech_load(path)
     chemgpu.chem_workspace_reserve(mech, n)
     base = chemgpu.make_opts(rtol=wl.RTOL, atol=wl.ATOL, chunk_steps=args.chunk,
-                             block_size=args.block)
+                             block_size=args.block, tail_steps=args.tail)
     stream = torch.cuda.current_stream()
 
     def restore():
@@ -287,7 +290,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
                    "cells": n, "boxes": len(boxes),
-                   "chunk_steps": args.chunk, "block_size": args.block, "autotuned": tuned},
+                   "chunk_steps": args.chunk, "block_size": args.block, "tail_steps": args.tail,
+                   "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                      "traffic": None},

@@ -269,6 +269,129 @@ def gen_aux(m: dict) -> str:
     return "\n".join(L)
 
 
+COOP_TH = 18   # thermo table entries per (range, species), padded to 16-byte rows
+
+
+def coop_group(m: dict) -> int:
+    """Lanes that advance one cell together in the cooperative kernel: enough
+    for one lane per state component and per reaction, 16..64."""
+    need = max(len(m["species"]) + 1, len(m["reactions"]))
+    g = 16
+    while g < need and g < 64:
+        g *= 2
+    return g
+
+
+def gen_coop(m: dict, tag: str) -> tuple[str, str]:
+    """Tables of the cooperative (reaction-parallel) RHS.
+
+    The same rate law as ``gen_rhs`` written as data: per reaction ln A, b,
+    Ea/R, the reactant and product species lists (a species of stoichiometric
+    coefficient nu appears nu times; pad = N, whose concentration slot holds
+    1), the net-stoichiometry terms of the K_c exponent (pad = N, g slot 0),
+    its third-body row; per species the reactions it appears in with their
+    net coefficients, and the NASA-7 Horner coefficients of both ranges.
+    Returns (namespace-scope __constant__ arrays, struct member block)."""
+    sp, rxs = m["species"], m["reactions"]
+    N, J = len(sp), len(rxs)
+    nets = []
+    for r in rxs:
+        nu = {}
+        for k, v in r["reac"].items():
+            nu[k] = nu.get(k, 0) - v
+        for k, v in r["prod"].items():
+            nu[k] = nu.get(k, 0) + v
+        nets.append([(k, v) for k, v in sorted(nu.items()) if v != 0])
+    MR = max(1, max(max(sum(r["reac"].values()), sum(r["prod"].values())) for r in rxs))
+    MG = max(1, max(len(n) for n in nets))
+    occ = [[] for _ in range(N)]
+    for j, n in enumerate(nets):
+        for k, v in n:
+            occ[k].append((j, v))
+    L = max(1, max(len(o) for o in occ))
+    tb_rows = [r["eff"] for r in rxs if r["tb"]]
+    NTB = len(tb_rows)
+
+    D, I = [], []     # flat double and int tables
+    off = {}
+
+    def put_d(name, vals):
+        off[name] = len(D)
+        D.extend(float(x) for x in vals)
+
+    def put_i(name, vals):
+        off[name] = len(I)
+        I.extend(int(x) for x in vals)
+
+    put_d("LNA", [math.log(r["A"]) for r in rxs])
+    put_d("BEXP", [r["b"] for r in rxs])
+    put_d("EAR", [r["Ea"] / R_J for r in rxs])
+    put_d("DNU", [sum(v for _, v in n) for n in nets])
+    gnu = []
+    for n in nets:
+        gnu += [float(v) for _, v in n] + [0.0] * (MG - len(n))
+    put_d("GNU", gnu)
+    tbe = []
+    for row in tb_rows:
+        tbe += row
+    put_d("TBEFF", tbe if tbe else [0.0])
+    slnu = []
+    for o in occ:
+        slnu += [float(v) for _, v in o] + [0.0] * (L - len(o))
+    put_d("SLNU", slnu)
+    put_d("INVW", [1.0 / s["W"] for s in sp])
+    put_d("WK", [s["W"] for s in sp])
+    put_d("TMID", [s["Tmid"] for s in sp])
+    while len(D) % 2:
+        D.append(0.0)
+    th = []
+    for rng in ("lo", "hi"):
+        for s in sp:
+            a = s[rng]
+            row = [a[0], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5, a[5],
+                   a[0], a[1] / 2, a[2] / 6, a[3] / 12, a[4] / 20, a[6],
+                   a[0] - 1.0, a[1], a[2], a[3], a[4], 0.0]
+            assert len(row) == COOP_TH
+            th += row
+    put_d("TH", th)
+    ri, pi_, gk, tbi = [], [], [], []
+    tb_row = 0
+    for r, n in zip(rxs, nets):
+        rs = [k for k, v in sorted(r["reac"].items()) for _ in range(v)]
+        ps = [k for k, v in sorted(r["prod"].items()) for _ in range(v)]
+        ri += rs + [N] * (MR - len(rs))
+        pi_ += ps + [N] * (MR - len(ps))
+        gk += [k for k, _ in n] + [N] * (MG - len(n))
+        if r["tb"]:
+            tbi.append(tb_row)
+            tb_row += 1
+        else:
+            tbi.append(-1)
+    put_i("RI", ri)
+    put_i("PI", pi_)
+    put_i("GK", gk)
+    put_i("TB", tbi)
+    put_i("SLJ", [j for o in occ for j in [jj for jj, _ in o] + [0] * (L - len(o))])
+    while len(I) % 4:
+        I.append(0)
+
+    ns = f"coop_{tag}"
+    glob = [f"namespace {ns} {{",
+            f"__constant__ double D[{len(D)}] = {{" + ", ".join(lit(x) for x in D) + "};",
+            f"__constant__ int I[{len(I)}] = {{" + ", ".join(str(x) for x in I) + "};",
+            "}"]
+    mem = ["  struct Coop {",
+           f"    static constexpr int G = {coop_group(m)};",
+           f"    static constexpr int J = {J}, MR = {MR}, MG = {MG}, L = {L}, NTB = {NTB};",
+           f"    static constexpr int ND = {len(D)}, NI = {len(I)}, TH_ROW = {COOP_TH};",
+           f"    static constexpr double LNPRT0 = {lit(math.log(m['pstd'] / R_CGS))};"]
+    mem.append("    static constexpr int " + ", ".join(f"O_{k} = {v}" for k, v in off.items()) + ";")
+    mem.append(f"    __device__ static const double* dtab() {{ return {ns}::D; }}")
+    mem.append(f"    __device__ static const int* itab() {{ return {ns}::I; }}")
+    mem.append("  };")
+    return "\n".join(glob), "\n".join(mem)
+
+
 def op_counts(m: dict) -> dict:
     """Algorithmic FP64 operation counts of one RHS evaluation as generated.
 
@@ -332,8 +455,10 @@ def gen_header(path: str) -> tuple[str, dict]:
     m = parse(path)
     N = len(m["species"])
     tag = f"{m['name']}_{m['hash']:016x}"
+    coop_glob, coop_mem = gen_coop(m, tag)
     body = [
         f"// Generated from {os.path.basename(path)} -- do not edit.",
+        coop_glob,
         f"struct Mech_{tag} {{",
         f"  static constexpr int NS = {N};",
         f"  static constexpr int NR = {len(m['reactions'])};",
@@ -341,6 +466,7 @@ def gen_header(path: str) -> tuple[str, dict]:
         f"  static constexpr const char* NAME = \"{m['name']}\";",
         gen_rhs(m),
         gen_aux(m),
+        coop_mem,
         "};",
     ]
     return "\n".join(body) + "\n", dict(tag=tag, hash=m["hash"], ns=N, nr=len(m["reactions"]),

@@ -30,6 +30,7 @@
 
 #include "chemgpu.h"
 #include "lsrk.hip.h"
+#include "lsrk_coop.hip.h"
 
 using namespace chemgpu;
 
@@ -50,6 +51,20 @@ struct BoxDesc {
   const int32_t* index;  // NULL, or the cell index of each of this block's pool items
 };
 
+// Cells handed from the per-lane kernel to the cooperative one, as
+// structure-of-arrays records; the cell's (T, Y) and step hint at time t are
+// in its own state rows.
+struct TailBuf {
+  int32_t* item;          // pool index
+  double* t;              // time reached within the current sub-call
+  int32_t* nacc;
+  int32_t* nrej;
+  int32_t* sub;           // current sub-call
+  int32_t* base;          // steps taken before the current sub-call
+  unsigned int* count;    // records written (zeroed before launch)
+  unsigned int* next;     // records claimed by the cooperative kernel (zeroed before launch)
+};
+
 struct PoolArgs {
   BoxDesc one;                 // used when boxes == nullptr
   const BoxDesc* boxes;        // device table, sorted by start
@@ -60,6 +75,8 @@ struct PoolArgs {
   Control c;
   int chunk;
   int fixed_steps;
+  int tail_steps;              // > 0: a cell that has taken this many steps moves to the tail
+  TailBuf tail;
 };
 
 __device__ __forceinline__ int find_box(const PoolArgs& a, int64_t g) {
@@ -145,7 +162,12 @@ struct Slots {
   static size_t bytes(int block) { return (size_t)block * (ND * sizeof(double) + NI * sizeof(int)); }
 };
 
-__global__ void pool_reset(unsigned long long* next) { *next = 0ull; }
+__global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
+                           unsigned int* tail_next) {
+  *next = 0ull;
+  if (tail_count) *tail_count = 0u;
+  if (tail_next) *tail_next = 0u;
+}
 
 template <class M, int LB>
 __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
@@ -207,6 +229,9 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
       const BoxDesc& bd = box_ref(a, bx);
       const double inv_rho = 1.0 / rho;
       int budget = a.chunk;
+      // a cell stops exactly at tail_steps, whatever the chunk length, so
+      // the hand-off point (and so the result) does not depend on tuning
+      if (a.tail_steps > 0) budget = min(budget, a.tail_steps - (nacc + nrej));
       Control c = a.c;
       for (;;) {
         c.max_steps = base + a.c.max_steps;  // per sub-call step budget
@@ -223,6 +248,23 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
         store_cell<M>(bd, cell_index(bd, item), u, h, st, nacc, nrej);
         item = -1;
         break;
+      }
+      if (item >= 0 && a.tail_steps > 0 && nacc + nrej >= a.tail_steps) {
+        // hand the cell to the cooperative kernel: state and hint go to its
+        // own rows, progress to a tail record
+        const int64_t i = cell_index(bd, item);
+        double* s = bd.state;
+#pragma unroll
+        for (int v = 0; v < N1; ++v) s[v * bd.ld + i] = u[v];
+        s[(N1 + 1) * bd.ld + i] = h;
+        const unsigned int r = atomicAdd(a.tail.count, 1u);
+        a.tail.item[r] = (int32_t)item;
+        a.tail.t[r] = t;
+        a.tail.nacc[r] = nacc;
+        a.tail.nrej[r] = nrej;
+        a.tail.sub[r] = sub;
+        a.tail.base[r] = base;
+        item = -1;
       }
     }
     // ---- pack active lanes to the front through LDS
@@ -290,6 +332,90 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   }
 }
 
+// ------------------------------------------------------- cooperative kernel
+// Finishes the cells the persistent kernel handed over: each group of
+// Coop::G lanes claims tail records one at a time and integrates that cell
+// to the end of its flow step (all remaining sub-calls).  Grid-size
+// independent: a group exits once the records are used up.
+template <class M>
+size_t coop_lds_bytes(int block) {
+  using C = typename M::Coop;
+  return (size_t)C::ND * sizeof(double) + (size_t)C::NI * sizeof(int) +
+         (size_t)(block / C::G) * CoopScratch<M>::SIZE * sizeof(double);
+}
+
+template <class M>
+__global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
+  using C = typename M::Coop;
+  constexpr int G = C::G, N = M::NS, N1 = N + 1;
+  static_assert(C::NI % 4 == 0 && C::ND % 2 == 0, "table padding");
+  extern __shared__ double smem[];
+  double* D = smem;
+  int* I = reinterpret_cast<int*>(smem + C::ND);
+  double* scr = smem + C::ND + C::NI / 2;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < C::ND; i += blockDim.x) D[i] = C::dtab()[i];
+  for (int i = tid; i < C::NI; i += blockDim.x) I[i] = C::itab()[i];
+  const int gl = tid % G;
+  double* sgrp = scr + (tid / G) * CoopScratch<M>::SIZE;
+  if (gl == 0) { sgrp[N] = 1.0; sgrp[N1 + N] = 0.0; }
+  __syncthreads();
+  const CoopCtx<M> x{D, I, sgrp, gl};
+  const unsigned int count = *a.tail.count;
+  // One step per iteration; a group whose cell finishes claims the next
+  // record at once instead of waiting for the other groups of its wave.
+  bool have = false;
+  double* st = nullptr;
+  int32_t* status = nullptr;
+  int32_t* counts = nullptr;
+  int64_t ld = 0, nbox = 0, i = 0;
+  double dt = 0.0;
+  int n_sub = 1;
+  double uv = 0.0, rho = 1.0, inv_rho = 1.0, h = 0.0, t = 0.0;
+  int nacc = 0, nrej = 0, sub = 0, base = 0;
+#pragma unroll 1
+  for (;;) {
+    if (!have) {
+      unsigned int r = 0;
+      if (gl == 0) r = atomicAdd(a.tail.next, 1u);
+      r = __shfl(r, 0, G);
+      if (r >= count) break;
+      const int64_t item = a.tail.item[r];
+      {
+        const BoxDesc& bd = box_ref(a, find_box(a, item));
+        i = cell_index(bd, item);
+        st = bd.state; ld = bd.ld; nbox = bd.n; dt = bd.dt; n_sub = bd.n_sub;
+        status = bd.status; counts = bd.counts;
+      }
+      uv = gl < N1 ? st[gl * ld + i] : 0.0;
+      rho = st[(N + 1) * ld + i];
+      inv_rho = 1.0 / rho;
+      h = st[(N + 2) * ld + i];
+      t = a.tail.t[r];
+      nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
+      sub = a.tail.sub[r]; base = a.tail.base[r];
+      have = true;
+    }
+    Control c = a.c;
+    c.max_steps = base + a.c.max_steps;
+    int code = coop_try_step<M, G>(uv, rho, inv_rho, dt, t, h, nacc, nrej, c, x);
+    if (code == CELL_OK && sub + 1 < n_sub) {
+      ++sub; t = 0.0; base = nacc + nrej;
+      h = initial_h(h, dt);
+      code = CELL_RUNNING;
+    }
+    if (code != CELL_RUNNING) {
+      if (gl < N1) st[gl * ld + i] = uv;
+      if (gl == 0) {
+        st[(N + 2) * ld + i] = h;
+        if (status) status[i] = code;
+        if (counts) { counts[i] = nacc; counts[nbox + i] = nrej; }
+      }
+      have = false;
+    }
+  }
+}
+
 }  // namespace
 
 #include "surrogate_kernels.hip.h"
@@ -303,6 +429,7 @@ struct MechEntry {
   const char* name;
   hipError_t (*launch_direct)(const PoolArgs&, int block, hipStream_t);
   hipError_t (*launch_persistent)(const PoolArgs&, int block, int grid, hipStream_t);
+  hipError_t (*launch_coop)(const PoolArgs&, int n_cu, hipStream_t);
   int (*max_blocks_per_cu)(int block);
   size_t (*lds_per_lane)();
   hipError_t (*launch_surr_infer)(const surr::InferArgs&, int grid, hipStream_t);
@@ -325,13 +452,26 @@ hipError_t launch_direct(const PoolArgs& a, int block, hipStream_t s) {
 
 template <class M>
 hipError_t launch_persistent(const PoolArgs& a, int block, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(pool_reset, dim3(1), dim3(1), 0, s, a.next);
+  hipLaunchKernelGGL(pool_reset, dim3(1), dim3(1), 0, s, a.next,
+                     a.tail_steps > 0 ? a.tail.count : nullptr,
+                     a.tail_steps > 0 ? a.tail.next : nullptr);
   if (block <= 256)
     hipLaunchKernelGGL((lsrk_persistent<M, 256>), dim3(grid), dim3(block),
                        Slots<M>::bytes(block), s, a);
   else
     hipLaunchKernelGGL((lsrk_persistent<M, 512>), dim3(grid), dim3(block),
                        Slots<M>::bytes(block), s, a);
+  return hipGetLastError();
+}
+
+// The cooperative kernel after the persistent one: enough 256-lane blocks to
+// put one group on every SIMD several times over; surplus groups exit at once.
+template <class M>
+hipError_t launch_coop(const PoolArgs& a, int n_cu, hipStream_t s) {
+  constexpr int kBlock = 256;
+  const size_t lds = coop_lds_bytes<M>(kBlock);
+  if (lds > 65536) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(lsrk_coop<M>, dim3(4 * n_cu), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
@@ -355,6 +495,7 @@ size_t lds_per_lane() {
 }
 
 #define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, &launch_direct<M>, &launch_persistent<M>, \
+                       &launch_coop<M>, \
                        &max_blocks_per_cu<M>, &lds_per_lane<M>, \
                        &launch_surr_infer<M>, &launch_make_pairs<M>},
 const MechEntry g_registry[] = {CHEM_FOR_EACH_MECH(CHEM_ENTRY)};
@@ -379,8 +520,28 @@ uint64_t fnv1a64(const std::vector<char>& d) {
 
 }  // namespace
 
+// Device storage of the tail records (see TailBuf): one allocation holding
+// cap records and the two counters.
+struct TailStore {
+  void* mem = nullptr;
+  int64_t cap = 0;
+  TailBuf view() const {
+    TailBuf b{};
+    char* p = static_cast<char*>(mem);
+    b.t = reinterpret_cast<double*>(p);
+    p += sizeof(double) * cap;
+    int32_t* q = reinterpret_cast<int32_t*>(p);
+    b.item = q; b.nacc = q + cap; b.nrej = q + 2 * cap; b.sub = q + 3 * cap; b.base = q + 4 * cap;
+    b.count = reinterpret_cast<unsigned int*>(q + 5 * cap);
+    b.next = b.count + 1;
+    return b;
+  }
+  static size_t bytes(int64_t cap) { return (size_t)cap * (sizeof(double) + 5 * sizeof(int32_t)) + 16; }
+};
+
 struct chem_mech_s {
   const MechEntry* entry;
+  TailStore tail;
   std::map<int, std::pair<int, int>> tuned;  // size bucket -> (block, chunk)
   unsigned long long* d_next = nullptr;
   BoxDesc* d_boxes = nullptr;
@@ -393,6 +554,7 @@ struct chem_mech_s {
 };
 
 struct chem_graph_s {
+  TailStore tail;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   BoxDesc* d_boxes = nullptr;
@@ -405,6 +567,21 @@ int ensure_pool(chem_mech m) {
   if (m->d_next) return CHEM_OK;
   hipError_t e = hipMalloc(&m->d_next, sizeof(unsigned long long));
   if (e != hipSuccess) { m->d_next = nullptr; return hip_fail(e, "hipMalloc(pool counter)"); }
+  return CHEM_OK;
+}
+
+int ensure_tail(TailStore& ts, int64_t cap) {
+  if (cap <= ts.cap) return CHEM_OK;
+  if (ts.mem) {
+    hipError_t e = hipDeviceSynchronize();  // a queued call may still use the old records
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(tail records)");
+    hipFree(ts.mem);
+  }
+  ts.mem = nullptr;
+  ts.cap = 0;
+  hipError_t e = hipMalloc(&ts.mem, TailStore::bytes(cap));
+  if (e != hipSuccess) { ts.mem = nullptr; return hip_fail(e, "hipMalloc(tail records)"); }
+  ts.cap = cap;
   return CHEM_OK;
 }
 
@@ -445,11 +622,18 @@ int check_opts(const chem_opts* o) {
 
 constexpr int kDefaultBlock = 128;
 constexpr int kDefaultChunk = 8;
+constexpr int kDefaultTail = 32;
 
 int size_bucket(int64_t total) {
   int b = 0;
   while (b < 62 && (int64_t(1) << b) < total) ++b;
   return b;
+}
+
+int pick_tail(const chem_opts* o) {
+  if (o && o->fixed_steps > 0) return 0;
+  if (o && o->tail_steps < 0) return 0;
+  return (o && o->tail_steps > 0) ? o->tail_steps : kDefaultTail;
 }
 
 void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int* chunk) {
@@ -476,8 +660,18 @@ int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
   if (rc) return rc;
   a.next = m->d_next;
   a.chunk = chunk > 0 ? chunk : kDefaultChunk;
+  a.tail_steps = pick_tail(o);
+  if (a.tail_steps > 0) {
+    rc = ensure_tail(m->tail, std::max<int64_t>(a.total, m->reserved));
+    if (rc) return rc;
+    a.tail = m->tail.view();
+  }
   hipError_t e = m->entry->launch_persistent(a, block, grid_for(m, block, a.total), s);
   if (e != hipSuccess) return hip_fail(e, "launch lsrk_persistent");
+  if (a.tail_steps > 0) {
+    e = m->entry->launch_coop(a, m->n_cu, s);
+    if (e != hipSuccess) return hip_fail(e, "launch lsrk_coop");
+  }
   return CHEM_OK;
 }
 
@@ -628,6 +822,7 @@ void chem_mech_free(chem_mech m) {
   if (!m) return;
   if (m->boxes_copied) { hipEventSynchronize(m->boxes_copied); hipEventDestroy(m->boxes_copied); }
   if (m->d_next) hipFree(m->d_next);
+  if (m->tail.mem) hipFree(m->tail.mem);
   if (m->d_boxes) hipFree(m->d_boxes);
   if (m->h_boxes) hipHostFree(m->h_boxes);
   delete m;
@@ -638,7 +833,7 @@ int chem_workspace_reserve(chem_mech m, int64_t max_cells) {
   int rc = ensure_pool(m);
   if (rc) return rc;
   m->reserved = std::max(m->reserved, max_cells);
-  return CHEM_OK;
+  return ensure_tail(m->tail, m->reserved);
 }
 
 int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, double dt,
@@ -726,6 +921,11 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   if (e != hipSuccess) return bail(e, "hipMalloc(graph box table)");
   e = hipMalloc(&g->d_next, sizeof(unsigned long long));
   if (e != hipSuccess) return bail(e, "hipMalloc(graph pool counter)");
+  const int tail_steps = pick_tail(opts);
+  if (tail_steps > 0) {
+    rc = ensure_tail(g->tail, total);
+    if (rc) { chem_graph_destroy(g); return rc; }
+  }
   e = hipMemcpy(g->d_boxes, table.data(), sizeof(BoxDesc) * table.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(e, "hipMemcpy(graph box table)");
   if (stream) {
@@ -741,6 +941,8 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   a.c = make_control(opts);
   a.chunk = chunk > 0 ? chunk : kDefaultChunk;
   a.fixed_steps = opts ? opts->fixed_steps : 0;
+  a.tail_steps = tail_steps;
+  if (tail_steps > 0) a.tail = g->tail.view();
   const int grid = grid_for(m, block, total);
   hipStream_t cs;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -748,6 +950,7 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) { hipStreamDestroy(cs); return bail(e, "hipStreamBeginCapture"); }
   hipError_t le = m->entry->launch_persistent(a, block, grid, cs);
+  if (le == hipSuccess && tail_steps > 0) le = m->entry->launch_coop(a, m->n_cu, cs);
   e = hipStreamEndCapture(cs, &g->graph);
   hipStreamDestroy(cs);
   if (le != hipSuccess) return bail(le, "launch lsrk_persistent (capture)");
@@ -772,6 +975,7 @@ void chem_graph_destroy(chem_graph g) {
   if (g->graph) hipGraphDestroy(g->graph);
   if (g->d_boxes) hipFree(g->d_boxes);
   if (g->d_next) hipFree(g->d_next);
+  if (g->tail.mem) hipFree(g->tail.mem);
   delete g;
 }
 
@@ -791,7 +995,7 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   char key[160];
   snprintf(key, sizeof key, "%016llx:%d:%s", (unsigned long long)m->entry->hash, bucket,
            arch_name(m->device).c_str());
-  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0};
+  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0};
   std::vector<TuneEntry> cache;
   if (cache_path) {
     cache = read_cache(cache_path);

@@ -66,11 +66,14 @@ def small_hierarchy(path, seed=13):
     return wl.amr_hierarchy(path, seed=seed, boxes_per_level=(2, 3, 4), edges=(8, 12, 16))
 
 
-def test_batched_matches_oracle_subcycling(cg, gm9, omech9, mech9_path):
+@pytest.mark.parametrize("tail", [0, 3])
+def test_batched_matches_oracle_subcycling(cg, gm9, omech9, mech9_path, tail):
+    """tail = 3 hands nearly every hot cell to the cooperative kernel, most of
+    them with sub-calls still to run."""
     import torch
     hier = small_hierarchy(mech9_path)
     boxes = gpu_boxes(hier)
-    cg.chem_integrate_batched(gm9, boxes)
+    cg.chem_integrate_batched(gm9, boxes, cg.make_opts(tail_steps=tail))
     torch.cuda.synchronize()
     flagged = total = 0
     for hb, gb in zip(hier, boxes):
@@ -86,7 +89,8 @@ def test_batched_matches_oracle_subcycling(cg, gm9, omech9, mech9_path):
             tight = np.ascontiguousarray(hb["state"][:, idx])
             gt = to_gpu(tight)
             cg.chem_integrate_batched(gm9, [dict(state=gt, dt=hb["dt"], n_sub=hb["n_sub"])],
-                                      cg.make_opts(rtol=1e-11, atol=1e-14, max_steps=2000000))
+                                      cg.make_opts(rtol=1e-11, atol=1e-14, max_steps=2000000,
+                                                   tail_steps=tail))
             c2, _, _ = oracle_subcalls(omech9, tight, hb["dt"], hb["n_sub"], rtol=1e-11,
                                        atol=1e-14, max_steps=2000000)
             assert not parity_violations(gt.cpu().numpy(), c2, 9).any()
@@ -94,39 +98,45 @@ def test_batched_matches_oracle_subcycling(cg, gm9, omech9, mech9_path):
             assert np.array_equal(gcn, ccn)
         flagged += int(bad.sum())
         total += len(bad)
-    print(f"[parity] small AMR batch: {total} cells, {flagged} flagged", flush=True)
+    print(f"[parity] small AMR batch (tail {tail}): {total} cells, {flagged} flagged", flush=True)
     assert flagged <= 0.02 * total
 
 
 def test_batched_equals_per_box_calls(cg, gm9, mech9_path):
-    """One batched launch == host-driven per-box sub-calls of chem_integrate, bitwise."""
+    """One batched launch == host-driven per-box sub-calls of chem_integrate,
+    bitwise (per-lane kernel only: the cooperative hand-off counts steps over
+    all sub-calls of a batched cell, but per call here)."""
     import torch
     hier = small_hierarchy(mech9_path, seed=14)
     boxes = gpu_boxes(hier)
-    cg.chem_integrate_batched(gm9, boxes)
+    off = cg.make_opts(tail_steps=-1)
+    cg.chem_integrate_batched(gm9, boxes, off)
     for hb, gb in zip(hier, boxes):
         t = to_gpu(hb["state"])
         tot = torch.zeros(2 * t.shape[1], dtype=torch.int32, device="cuda")
         cn = torch.zeros_like(tot)
         for _ in range(hb["n_sub"]):
-            cg.chem_integrate(gm9, t, hb["dt"], counts=cn)
+            cg.chem_integrate(gm9, t, hb["dt"], off, counts=cn)
             tot += cn
         torch.cuda.synchronize()
         assert torch.equal(t, gb["state"])
         assert torch.equal(tot, gb["counts"])
 
 
-def test_graph_replay_matches_eager(cg, gm9, mech9_path):
-    """Replays of a captured graph, with eager work and syncs between them,
-    each reproduce the eager batched result exactly."""
+@pytest.mark.parametrize("tail", [0, 3])
+def test_graph_replay_matches_eager(cg, gm9, mech9_path, tail):
+    """Replays of a captured graph (per-lane and cooperative kernels), with
+    eager work and syncs between them, each reproduce the eager batched
+    result exactly."""
     import torch
     hier = small_hierarchy(mech9_path, seed=15)
+    opts = cg.make_opts(tail_steps=tail)
     eager = gpu_boxes(hier)
-    cg.chem_integrate_batched(gm9, eager)
+    cg.chem_integrate_batched(gm9, eager, opts)
     torch.cuda.synchronize()
     boxes = gpu_boxes(hier)
     pristine = [b["state"].clone() for b in boxes]
-    g = cg.chem_graph_capture_batched(gm9, boxes)
+    g = cg.chem_graph_capture_batched(gm9, boxes, opts)
     other = to_gpu(wl.cells_uniform(mech9_path, n=3000, seed=3))
     for rep in range(4):
         for b, p in zip(boxes, pristine):

@@ -190,19 +190,67 @@ def test_stress_mech9_sampled(gmech9, omech9, mech9_path):
     assert_parity(gmech9, omech9, s0, wl.DT_FLOW, idx=idx, label="stress mech9 sampled")
 
 
-def test_chunk_and_block_invariance(gmech9, mech9_path):
-    """Compaction only moves cells between lanes: for a given kernel build the
-    results are bitwise identical for any chunk length or block size; the
-    uncompacted kernel agrees to rounding."""
+@pytest.mark.parametrize("tail", [-1, 0, 5])
+def test_chunk_and_block_invariance(gmech9, mech9_path, tail):
+    """Compaction only moves cells between lanes, and a cell moves to the
+    cooperative kernel after exactly tail_steps steps: for a given kernel
+    build the results are bitwise identical for any chunk length or block
+    size.  Without the cooperative kernel the uncompacted kernel agrees to
+    rounding."""
     s0 = _hot_cells(mech9_path, 2000, seed=34)
-    ref, rst, rcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=8, block_size=128)
-    for chunk, block in [(1, 64), (3, 128), (16, 256), (64, 192)]:
-        g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=chunk, block_size=block)
+    ref, rst, rcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=8, block_size=128, tail_steps=tail)
+    for chunk, block in [(1, 64), (3, 128), (16, 256), (64, 192), (5, 512)]:
+        g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=chunk, block_size=block,
+                              tail_steps=tail)
         assert np.array_equal(g, ref) and np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
-    for chunk, block in [(-1, 256), (5, 512)]:
-        g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=chunk, block_size=block)
+    if tail < 0:
+        g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, chunk_steps=-1, block_size=256)
         assert np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
         assert not parity_violations(g, ref, 9, rtol=1e-12, floor_y=1e-16).any()
+
+
+@pytest.mark.parametrize("tail", [1, 8, 32])
+def test_tail_cells_match_oracle(gmech9, omech9, mech9_path, tail):
+    """Hot front cells finished by the cooperative kernel (several lanes per
+    cell, table-driven rate law) after `tail` per-lane steps."""
+    s0 = _hot_cells(mech9_path, 3000, seed=35)
+    assert_parity(gmech9, omech9, s0, wl.DT_FLOW, label=f"hot front tail={tail}",
+                  max_flag_frac=0.02, tail_steps=tail)
+
+
+def test_tail_mech32(gmech32, omech32, mech32_path):
+    """32 species / 150 reactions through the cooperative kernel (a full wave
+    per cell, three reaction rounds per lane)."""
+    s0 = wl.stress_3d(mech32_path, shape=(32, 32, 1), seed=6)
+    assert_parity(gmech32, omech32, s0, wl.DT_FLOW, label="stress mech32 tail=2",
+                  tail_steps=2)
+
+
+def test_tail_status_paths_and_isomer(chemgpu, gmech9, omech9, mech9_path, isomer_path):
+    """Step budget exhausted inside the cooperative kernel; non-finite cells
+    never reach it; the isomer closed form through it."""
+    s0 = _hot_cells(mech9_path, 70, seed=36)
+    s0[3, 5] = np.nan
+    g, gst, gcn = run_gpu(gmech9, s0, wl.DT_FLOW, max_steps=6, tail_steps=2)
+    c, cst, ccn = _oracle_run(omech9, s0, wl.DT_FLOW, max_steps=6)
+    assert np.array_equal(gst, cst) and gst[5] == 2 and (gst == 1).sum() > 10
+    ok = np.ones(70, bool)
+    ok[5] = False
+    assert np.array_equal(gcn[:, ok], ccn[:, ok])
+    assert not parity_violations(g[:, ok], c[:, ok], 9).any()
+    m = chemgpu.chem_mech_load(isomer_path)
+    rng = np.random.Generator(np.random.PCG64(6))
+    n = 200
+    YA = rng.uniform(0.0, 1.0, n)
+    T = rng.uniform(800.0, 2000.0, n)
+    names, W = wl.read_species(isomer_path)
+    Y = np.stack([YA, 1.0 - YA])
+    s1 = wl.pack(T, Y, wl.density(T, np.full(n, wl.P_ATM), Y, W))
+    g1, gst1, gcn1 = run_gpu(m, s1, 1e-7, rtol=1e-12, atol=1e-16, tail_steps=1)
+    assert (gst1 == 0).all() and (gcn1[0] > 1).all()
+    expect = (Y[0] - Y[1]) * np.exp(-2 * 2.0e7 * 1e-7)
+    assert np.abs((g1[1] - g1[2]) - expect).max() < 2e-11
+    assert np.allclose(g1[0], T, rtol=1e-13)
 
 
 def test_every_cell_of_a_large_field_is_integrated(gmech9, omech9, mech9_path):
