@@ -44,8 +44,8 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--workload", default="front",
                     choices=["front", "front_hot_tiled", "amr", "stress9", "stress32", "cells"])
-    ap.add_argument("--autotune", action="store_true",
-                    help="autotune block/chunk on the workload first (amr always tunes)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (block/chunk/hand-off from the library defaults)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate+fallback leg on the 256^3 evaluation field")
     ap.add_argument("--surrogate-epochs", type=int, default=12)
@@ -247,9 +247,10 @@ def main():
             b["state"].copy_(p)
 
     tuned = None
-    if (args.autotune or args.workload == "amr") and not (args.chunk or args.block):
+    if not args.no_autotune and not (args.chunk or args.block):
         tb = chemgpu.chem_autotune(mech, boxes, base, reps=1)
-        tuned = {"block_size": tb.block_size, "chunk_steps": tb.chunk_steps}
+        tuned = {"block_size": tb.block_size, "chunk_steps": tb.chunk_steps,
+                 "tail_steps": tb.tail_steps}
     # one untimed pass with per-cell counters for the flop count
     restore()
     chemgpu.chem_integrate_batched(mech, boxes, base)

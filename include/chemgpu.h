@@ -151,14 +151,16 @@ int chem_graph_launch(chem_graph g, void *stream);
 void chem_graph_destroy(chem_graph g);
 
 /*
- * Autotune block size and chunk length for these boxes: every candidate
- * (block in {64, 128, 192, 256, 384, 512} that fits the LDS compaction slots,
- * chunk in {1, 2, 4, 8, 16, 32, 64}) is timed with HIP events on `stream`
- * (median of `reps` launches) on the caller's boxes; the boxes' states are
- * snapshotted first and restored after every trial and at the end, so the
- * caller's data is left unchanged.  The winner is stored in the handle for
- * the size bucket of these boxes (total cells rounded to a power of two):
- * later calls whose chunk_steps and block_size are 0 use it.  If cache_path
+ * Autotune block size, chunk length and cooperative hand-off for these
+ * boxes: every (block in {64, 128, 192, 256, 384, 512} that fits the LDS
+ * compaction slots, chunk in {1, 2, 4, 8, 16, 32, 64}) is timed with HIP
+ * events on `stream` (median of `reps` launches) on the caller's boxes, then,
+ * if base->tail_steps is 0, tail_steps in {8, 16, 32, 64, 128, never} for the
+ * best pair; the boxes' states are snapshotted first and restored after
+ * every trial and at the end, so the caller's data is left unchanged.  The
+ * winner is stored in the handle for the size bucket of these boxes (total
+ * cells rounded to a power of two): later calls whose chunk_steps,
+ * block_size or tail_steps are 0 use it.  If cache_path
  * is not NULL the result is also looked up in / written to that JSON file,
  * keyed by mechanism hash, size bucket and GPU architecture name; a cache hit
  * skips the sweep.  best (may be NULL) receives the chosen options.

@@ -347,7 +347,7 @@ size_t coop_lds_bytes(int block) {
 template <class M>
 __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   using C = typename M::Coop;
-  constexpr int G = C::G, N = M::NS, N1 = N + 1;
+  constexpr int G = C::G, N = M::NS;
   static_assert(C::NI % 4 == 0 && C::ND % 2 == 0, "table padding");
   extern __shared__ double smem[];
   double* D = smem;
@@ -358,9 +358,14 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   for (int i = tid; i < C::NI; i += blockDim.x) I[i] = C::itab()[i];
   const int gl = tid % G;
   double* sgrp = scr + (tid / G) * CoopScratch<M>::SIZE;
-  if (gl == 0) { sgrp[N] = 1.0; sgrp[N1 + N] = 0.0; }
+  if (gl == 0) {
+    sgrp[CoopScratch<M>::SC + N] = 1.0;
+    sgrp[CoopScratch<M>::SG + N] = 0.0;
+  }
   __syncthreads();
   const CoopCtx<M> x{D, I, sgrp, gl};
+  CoopLane<M, G> ln;
+  ln.load(D, I, gl);
   const unsigned int count = *a.tail.count;
   // One step per iteration; a group whose cell finishes claims the next
   // record at once instead of waiting for the other groups of its wave.
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   int64_t ld = 0, nbox = 0, i = 0;
   double dt = 0.0;
   int n_sub = 1;
-  double uv = 0.0, rho = 1.0, inv_rho = 1.0, h = 0.0, t = 0.0;
+  double uT = 0.0, uk = 0.0, rho = 1.0, inv_rho = 1.0, h = 0.0, t = 0.0;
   int nacc = 0, nrej = 0, sub = 0, base = 0;
 #pragma unroll 1
   for (;;) {
@@ -387,7 +392,8 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
         st = bd.state; ld = bd.ld; nbox = bd.n; dt = bd.dt; n_sub = bd.n_sub;
         status = bd.status; counts = bd.counts;
       }
-      uv = gl < N1 ? st[gl * ld + i] : 0.0;
+      uT = st[i];
+      uk = gl < N ? st[(gl + 1) * ld + i] : 0.0;
       rho = st[(N + 1) * ld + i];
       inv_rho = 1.0 / rho;
       h = st[(N + 2) * ld + i];
@@ -398,15 +404,16 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
     }
     Control c = a.c;
     c.max_steps = base + a.c.max_steps;
-    int code = coop_try_step<M, G>(uv, rho, inv_rho, dt, t, h, nacc, nrej, c, x);
+    int code = coop_try_step<M, G>(uT, uk, rho, inv_rho, dt, t, h, nacc, nrej, c, x, ln);
     if (code == CELL_OK && sub + 1 < n_sub) {
       ++sub; t = 0.0; base = nacc + nrej;
       h = initial_h(h, dt);
       code = CELL_RUNNING;
     }
     if (code != CELL_RUNNING) {
-      if (gl < N1) st[gl * ld + i] = uv;
+      if (gl < N) st[(gl + 1) * ld + i] = uk;
       if (gl == 0) {
+        st[i] = uT;
         st[(N + 2) * ld + i] = h;
         if (status) status[i] = code;
         if (counts) { counts[i] = nacc; counts[nbox + i] = nrej; }
@@ -542,7 +549,8 @@ struct TailStore {
 struct chem_mech_s {
   const MechEntry* entry;
   TailStore tail;
-  std::map<int, std::pair<int, int>> tuned;  // size bucket -> (block, chunk)
+  struct Tuned { int block, chunk, tail; };
+  std::map<int, Tuned> tuned;  // size bucket -> tuned launch
   unsigned long long* d_next = nullptr;
   BoxDesc* d_boxes = nullptr;
   BoxDesc* h_boxes = nullptr;      // pinned staging for the box table
@@ -630,10 +638,14 @@ int size_bucket(int64_t total) {
   return b;
 }
 
-int pick_tail(const chem_opts* o) {
+int pick_tail(chem_mech m, int64_t total, const chem_opts* o) {
   if (o && o->fixed_steps > 0) return 0;
-  if (o && o->tail_steps < 0) return 0;
-  return (o && o->tail_steps > 0) ? o->tail_steps : kDefaultTail;
+  int t = o ? o->tail_steps : 0;
+  if (t == 0) {
+    auto it = m->tuned.find(size_bucket(total));
+    t = (it != m->tuned.end() && it->second.tail != 0) ? it->second.tail : kDefaultTail;
+  }
+  return t > 0 ? t : 0;
 }
 
 void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int* chunk) {
@@ -641,8 +653,8 @@ void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int
   *chunk = (o && o->chunk_steps) ? o->chunk_steps : 0;
   auto it = m->tuned.find(size_bucket(total));
   if (it != m->tuned.end()) {
-    if (!*block) *block = it->second.first;
-    if (!*chunk) *chunk = it->second.second;
+    if (!*block) *block = it->second.block;
+    if (!*chunk) *chunk = it->second.chunk;
   }
   if (!*block) *block = kDefaultBlock;
   if (!*chunk) *chunk = kDefaultChunk;
@@ -660,7 +672,7 @@ int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
   if (rc) return rc;
   a.next = m->d_next;
   a.chunk = chunk > 0 ? chunk : kDefaultChunk;
-  a.tail_steps = pick_tail(o);
+  a.tail_steps = pick_tail(m, a.total, o);
   if (a.tail_steps > 0) {
     rc = ensure_tail(m->tail, std::max<int64_t>(a.total, m->reserved));
     if (rc) return rc;
@@ -714,7 +726,7 @@ std::string arch_name(int device) {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-struct TuneEntry { std::string key; int block, chunk; double ms; };
+struct TuneEntry { std::string key; int block, chunk, tail; double ms; };
 
 std::vector<TuneEntry> read_cache(const char* path) {
   std::vector<TuneEntry> v;
@@ -731,12 +743,14 @@ std::vector<TuneEntry> read_cache(const char* path) {
     pos += tag.size();
     const size_t end = txt.find('"', pos);
     if (end == std::string::npos) break;
-    TuneEntry e{txt.substr(pos, end - pos), 0, 0, 0.0};
+    TuneEntry e{txt.substr(pos, end - pos), 0, 0, 0, 0.0};
     const size_t close = txt.find('}', end);
     const std::string rec = txt.substr(end, close == std::string::npos ? std::string::npos : close - end);
     const size_t pb = rec.find("\"block\":"), pc = rec.find("\"chunk\":"), pm = rec.find("\"ms\":");
+    const size_t pt = rec.find("\"tail\":");
     if (pb != std::string::npos) e.block = atoi(rec.c_str() + pb + 8);
     if (pc != std::string::npos) e.chunk = atoi(rec.c_str() + pc + 8);
+    if (pt != std::string::npos) e.tail = atoi(rec.c_str() + pt + 7);
     if (pm != std::string::npos) e.ms = atof(rec.c_str() + pm + 5);
     if (e.block > 0 && e.chunk != 0) v.push_back(e);
     pos = end;
@@ -750,8 +764,9 @@ int write_cache(const char* path, const std::vector<TuneEntry>& v) {
   if (!f) return fail(CHEM_EINVAL, std::string("cannot write ") + path);
   fprintf(f, "{\"version\": 1, \"entries\": [\n");
   for (size_t i = 0; i < v.size(); ++i)
-    fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"chunk\": %d, \"ms\": %.6f}%s\n",
-            v[i].key.c_str(), v[i].block, v[i].chunk, v[i].ms, i + 1 < v.size() ? "," : "");
+    fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"chunk\": %d, \"tail\": %d, \"ms\": %.6f}%s\n",
+            v[i].key.c_str(), v[i].block, v[i].chunk, v[i].tail, v[i].ms,
+            i + 1 < v.size() ? "," : "");
   fprintf(f, "]}\n");
   fclose(f);
   if (rename(tmp.c_str(), path) != 0) return fail(CHEM_EINVAL, std::string("cannot replace ") + path);
@@ -921,7 +936,7 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   if (e != hipSuccess) return bail(e, "hipMalloc(graph box table)");
   e = hipMalloc(&g->d_next, sizeof(unsigned long long));
   if (e != hipSuccess) return bail(e, "hipMalloc(graph pool counter)");
-  const int tail_steps = pick_tail(opts);
+  const int tail_steps = pick_tail(m, total, opts);
   if (tail_steps > 0) {
     rc = ensure_tail(g->tail, total);
     if (rc) { chem_graph_destroy(g); return rc; }
@@ -1001,8 +1016,11 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     cache = read_cache(cache_path);
     for (const auto& en : cache)
       if (en.key == key) {
-        m->tuned[bucket] = {en.block, en.chunk};
-        if (best) { *best = o; best->block_size = en.block; best->chunk_steps = en.chunk; }
+        m->tuned[bucket] = {en.block, en.chunk, en.tail};
+        if (best) {
+          *best = o; best->block_size = en.block; best->chunk_steps = en.chunk;
+          best->tail_steps = en.tail;
+        }
         return CHEM_OK;
       }
   }
@@ -1028,10 +1046,32 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
+  // median time of `reps` calls of one configuration (after one untimed call)
+  auto trial = [&](const chem_opts& t, double* med) -> int {
+    std::vector<float> ms;
+    for (int r = 0; r <= reps; ++r) {
+      if ((e = restore()) != hipSuccess) return hip_fail(e, "restore");
+      hipEventRecord(e0, s);
+      int trc = chem_integrate_batched(m, boxes, n_boxes, &t, stream);
+      if (trc != CHEM_OK) return trc;
+      hipEventRecord(e1, s);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "trial");
+      float el = 0;
+      hipEventElapsedTime(&el, e0, e1);
+      if (r > 0) ms.push_back(el);
+    }
+    std::sort(ms.begin(), ms.end());
+    *med = ms[ms.size() / 2];
+    return CHEM_OK;
+  };
+  // block x chunk with the caller's (or the default) hand-off, then the
+  // hand-off point for the best pair
   const int blocks[] = {64, 128, 192, 256, 384, 512};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
+  const int tails[] = {8, 16, 32, 64, 128, -1};
   double best_ms = 1e300;
   int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
+  int best_tail = o.tail_steps != 0 ? o.tail_steps : kDefaultTail;
   rc = CHEM_OK;
   for (int b : blocks) {
     if (m->entry->lds_per_lane() * b > 65536) continue;
@@ -1039,23 +1079,22 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
       chem_opts t = o;
       t.block_size = b;
       t.chunk_steps = c;
-      std::vector<float> ms;
-      for (int r = 0; r <= reps && rc == CHEM_OK; ++r) {
-        if ((e = restore()) != hipSuccess) { rc = hip_fail(e, "restore"); break; }
-        hipEventRecord(e0, s);
-        rc = chem_integrate_batched(m, boxes, n_boxes, &t, stream);
-        hipEventRecord(e1, s);
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) { rc = hip_fail(e, "trial"); break; }
-        float el = 0;
-        hipEventElapsedTime(&el, e0, e1);
-        if (r > 0) ms.push_back(el);
-      }
-      if (rc != CHEM_OK) break;
-      std::sort(ms.begin(), ms.end());
-      const double med = ms[ms.size() / 2];
+      double med = 0;
+      if ((rc = trial(t, &med)) != CHEM_OK) break;
       if (med < best_ms) { best_ms = med; best_block = b; best_chunk = c; }
     }
     if (rc != CHEM_OK) break;
+  }
+  if (rc == CHEM_OK && o.tail_steps == 0 && o.fixed_steps == 0) {
+    for (int tl : tails) {
+      chem_opts t = o;
+      t.block_size = best_block;
+      t.chunk_steps = best_chunk;
+      t.tail_steps = tl;
+      double med = 0;
+      if ((rc = trial(t, &med)) != CHEM_OK) break;
+      if (med < best_ms) { best_ms = med; best_tail = tl; }
+    }
   }
   if ((e = restore()) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "restore");
   hipStreamSynchronize(s);
@@ -1063,10 +1102,13 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   hipEventDestroy(e1);
   cleanup();
   if (rc != CHEM_OK) return rc;
-  m->tuned[bucket] = {best_block, best_chunk};
-  if (best) { *best = o; best->block_size = best_block; best->chunk_steps = best_chunk; }
+  m->tuned[bucket] = {best_block, best_chunk, best_tail};
+  if (best) {
+    *best = o; best->block_size = best_block; best->chunk_steps = best_chunk;
+    best->tail_steps = best_tail;
+  }
   if (cache_path) {
-    cache.push_back(TuneEntry{key, best_block, best_chunk, best_ms});
+    cache.push_back(TuneEntry{key, best_block, best_chunk, best_tail, best_ms});
     rc = write_cache(cache_path, cache);
   }
   return rc;
