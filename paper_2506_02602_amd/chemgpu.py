@@ -357,6 +357,18 @@ def chem_autotune(mech: Mechanism, boxes, base: chem_opts | None = None, reps: i
     return best
 
 
+_lib.chem_eval_exp.argtypes = [_P, _P, C.c_int64, _P]
+
+
+def chem_eval_exp(x, stream=None):
+    """e^x on the device with the exponential the rate evaluation uses."""
+    import torch
+    y = torch.empty_like(x)
+    _check(_lib.chem_eval_exp(x.data_ptr(), y.data_ptr(), x.numel(), _stream(stream)),
+           "chem_eval_exp")
+    return y
+
+
 def exported_symbols():
     """Names declared in include/chemgpu.h that this library must export."""
     return ["chem_mech_load", "chem_mech_query", "chem_mech_free", "chem_workspace_reserve",
@@ -365,4 +377,4 @@ def exported_symbols():
             "chem_last_error", "surrogate_create", "surrogate_query", "surrogate_get_params",
             "surrogate_set_params", "surrogate_make_pairs", "surrogate_train", "surrogate_forward",
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
-            "surrogate_free"]
+            "surrogate_free", "chem_eval_exp"]

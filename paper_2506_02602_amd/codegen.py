@@ -9,7 +9,8 @@ parameter and NASA-7 coefficient is a literal:
 * thermo (Eq. 10 fits): per species cp/R, h/RT and g/RT = h/RT - s/R in Horner
   form, with a wave-coherent branch on T < Tmid (one branch per distinct Tmid);
 * forward rate k_f = exp(ln A + b ln T - Ea/(R T)), reverse rate
-  k_r = k_f / K_c computed as exp(ln k_f + sum_k nu_k g_k/RT - dnu ln(P/(R T)));
+  k_r = k_f / K_c computed as exp(ln k_f + sum_k nu_k g_k/RT - dnu ln(P/(R T)))
+  (the exponential is the device's own ``exp_cw``, within 1 ulp);
 * progress q_j = [M]_j (k_f prod c^nu' - k_r prod c^nu''), integer powers as
   products; production rates accumulated straight into N registers;
 * dY_k/dt = W_k wdot_k / rho and the constant-volume adiabatic dT/dt.
@@ -189,7 +190,7 @@ def gen_rhs(m: dict) -> str:
         if rx["Ea"] != 0.0:
             e.append(f"- {lit(rx['Ea'] / R_J)} * invT")
         L.append(f"      const double lkf = {' + '.join(e).replace('+ -', '-')};")
-        L.append("      const double kf = exp(lkf);")
+        L.append("      const double kf = exp_cw(lkf);")
         nu = {}
         for k, v in rx["reac"].items():
             nu[k] = nu.get(k, 0) - v
@@ -207,7 +208,7 @@ def gen_rhs(m: dict) -> str:
             sign = "-" if dnu > 0 else "+"
             mag = abs(dnu)
             gterms.append(f" {sign} {'' if mag == 1 else lit(float(mag)) + ' * '}lnPRT")
-        L.append(f"      const double kr = exp(lkf{''.join(gterms)});")
+        L.append(f"      const double kr = exp_cw(lkf{''.join(gterms)});")
         q = f"{_prod_expr('kf', rx['reac'])} - {_prod_expr('kr', rx['prod'])}"
         if rx["tb"]:
             mt = " + ".join(f"{lit(a)} * c{k}" for k, a in enumerate(rx["eff"]))
@@ -274,8 +275,8 @@ COOP_TH = 18   # thermo table entries per (range, species), padded to 16-byte ro
 
 def coop_group(m: dict) -> int:
     """Lanes that advance one cell together in the cooperative kernel: enough
-    for one lane per state component and per reaction, 16..64."""
-    need = max(len(m["species"]) + 1, len(m["reactions"]))
+    for one lane per species and per reaction, 16..64."""
+    need = max(len(m["species"]), len(m["reactions"]))
     g = 16
     while g < need and g < 64:
         g *= 2
@@ -334,7 +335,7 @@ def gen_coop(m: dict, tag: str) -> tuple[str, str]:
     tbe = []
     for row in tb_rows:
         tbe += row
-    put_d("TBEFF", tbe if tbe else [0.0])
+    put_d("TBEFF", tbe if tbe else [0.0] * N)    # row 0 is read (and discarded) by non-third-body lanes
     slnu = []
     for o in occ:
         slnu += [float(v) for _, v in o] + [0.0] * (L - len(o))
@@ -427,10 +428,11 @@ def op_counts(m: dict) -> dict:
 
 # Algorithmic FP64 cost assigned to each non-polynomial operation, in flops
 # (FMA = 2): exp = range reduction (1 mul, 2 FMA) + degree-11 polynomial
-# (11 FMA) = 27; log similar = 30; a correctly rounded divide or square root
-# = reciprocal seed + 2 Newton refinements + correction = 10; pow(e, -1/4) =
-# log + exp = 57.
-FLOP_EXP, FLOP_LOG, FLOP_DIV, FLOP_SQRT, FLOP_POW = 27, 30, 10, 10, 57
+# (11 FMA) = 27 (the conventional cost; the device exponential spends a
+# little more); log similar = 30; a correctly rounded divide or square root
+# = reciprocal seed + 2 Newton refinements + correction = 10.  The step
+# factor err^(-1/4) is two square roots and a divide.
+FLOP_EXP, FLOP_LOG, FLOP_DIV, FLOP_SQRT = 27, 30, 10, 10
 
 
 def rhs_flops(m: dict) -> int:
@@ -444,11 +446,12 @@ def step_flops(m: dict) -> int:
     Stage updates: E, U, X each one FMA per component for stages 1-4, E and X
     for stage 5: 14 FMA = 28 flops per component.  WRMS: weight (FMA), divide,
     square-accumulate (FMA) per component, then a scale, a sqrt and the
-    factor's pow, plus 4 scalar flops of control."""
+    factor err^(-1/4) (two square roots and a divide), plus 4 scalar flops
+    of control."""
     n1 = len(m["species"]) + 1
     upd = 28 * n1
     wrms = n1 * (2 + FLOP_DIV + 2) + 1 + FLOP_SQRT
-    return 5 * rhs_flops(m) + upd + wrms + FLOP_POW + 4
+    return 5 * rhs_flops(m) + upd + wrms + 2 * FLOP_SQRT + FLOP_DIV + 4
 
 
 def gen_header(path: str) -> tuple[str, dict]:
@@ -456,6 +459,7 @@ def gen_header(path: str) -> tuple[str, dict]:
     N = len(m["species"])
     tag = f"{m['name']}_{m['hash']:016x}"
     coop_glob, coop_mem = gen_coop(m, tag)
+    rhs = gen_rhs(m)
     body = [
         f"// Generated from {os.path.basename(path)} -- do not edit.",
         coop_glob,
@@ -464,7 +468,7 @@ def gen_header(path: str) -> tuple[str, dict]:
         f"  static constexpr int NR = {len(m['reactions'])};",
         f"  static constexpr unsigned long long HASH = 0x{m['hash']:016x}ULL;",
         f"  static constexpr const char* NAME = \"{m['name']}\";",
-        gen_rhs(m),
+        rhs,
         gen_aux(m),
         coop_mem,
         "};",

@@ -162,6 +162,11 @@ struct Slots {
   static size_t bytes(int block) { return (size_t)block * (ND * sizeof(double) + NI * sizeof(int)); }
 };
 
+__global__ void eval_exp_kernel(const double* x, double* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = exp_cw(x[i]);
+}
+
 __global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
                            unsigned int* tail_next) {
   *next = 0ull;
@@ -791,6 +796,17 @@ const char* chem_strerror(int code) {
 }
 
 const char* chem_last_error(void) { return g_err.c_str(); }
+
+int chem_eval_exp(const double* x, double* y, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !y))) return fail(CHEM_EINVAL, "chem_eval_exp: bad argument");
+  if (n == 0) return CHEM_OK;
+  const int64_t grid = (n + 255) / 256;
+  if (grid > 0x7fffffff) return fail(CHEM_EINVAL, "chem_eval_exp: n too large");
+  hipLaunchKernelGGL(eval_exp_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                     x, y, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CHEM_OK : hip_fail(e, "launch eval_exp");
+}
 
 int chem_mech_load(const char* path, chem_mech* out) {
   if (!path || !out) return fail(CHEM_EINVAL, "chem_mech_load: null argument");

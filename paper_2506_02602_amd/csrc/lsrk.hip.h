@@ -91,6 +91,40 @@ __device__ __forceinline__ double lsrk_step(const double (&u)[M::NS + 1], double
   return sqrt(sum * (1.0 / N1));
 }
 
+// e^x for the rate constants: Cody-Waite reduction x = n ln2 + r, |r| <=
+// ln2/2, with ln 2 split into its correctly rounded double and the
+// remainder (both products applied with FMAs), then the degree-13 Taylor
+// polynomial of e^r in Horner form (truncation error below 5e-18 relative
+// on that interval) scaled by 2^n with ldexp.  Within 1 ulp of a correctly
+// rounded exponential; overflow gives inf and underflow 0 or a subnormal
+// through ldexp, NaN propagates (n is clamped so the conversion to int is
+// defined; a NaN x still reaches r).  Fewer instructions than the library
+// exponential, which also tests for the out-of-range cases.
+__device__ __forceinline__ double exp_cw(double x) {
+  constexpr double LOG2E = 1.4426950408889634;
+  constexpr double LN2_HI = 0.6931471805599453;
+  constexpr double LN2_LO = 2.3190468138462996e-17;
+  double n = rint(x * LOG2E);
+  n = fmax(fmin(n, 2100.0), -2100.0);
+  double r = fma(-n, LN2_HI, x);
+  r = fma(-n, LN2_LO, r);
+  double p = 1.0 / 6227020800.0;            // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);         // 1/12!
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)n);
+}
+
 __device__ __forceinline__ double step_factor(double err) {
   if (err != err) return 0.2;
   if (err == 0.0) return 5.0;

