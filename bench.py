@@ -30,6 +30,11 @@ METRIC = "chem-integrated cells/s per flow step: plain FP64 vs surrogate+fallbac
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
 
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,17 +73,20 @@ def surrogate_leg(args):
     t0 = time.perf_counter()
     ds = sg.build_dataset(m)
     t_data = time.perf_counter() - t0
+    log(f"surrogate: {int(ds['X'].shape[0])} training pairs in {t_data:.1f} s; training")
     n_pairs = int(ds["X"].shape[0])
     s = cg.Surrogate(m, seed=11)
     t0 = time.perf_counter()
     loss = cg.surrogate_train(s, ds["X"], ds["Y"], epochs=args.surrogate_epochs, batch=4096,
                               lr=3e-3, seed=2)
     t_train = time.perf_counter() - t0
+    log("surrogate: tuning trust thresholds")
     trust, tstats = sg.tune_trust(s, m, sg.validation_states(ds))
     if trust is None:
         trust = (0.0, 1e-6, 1e-7, 0.05)
     del ds
     torch.cuda.empty_cache()
+    log("surrogate: building the 256^3 evaluation field")
     field, out_mask = sg.inference_field(m)
     n = field.shape[1]
     work = torch.empty_like(field)
@@ -247,10 +255,14 @@ def main():
             b["state"].copy_(p)
 
     tuned = None
+    log(f"workload {args.workload}: {n} cells in {len(boxes)} boxes")
     if not args.no_autotune and not (args.chunk or args.block):
-        tb = chemgpu.chem_autotune(mech, boxes, base, reps=1)
+        log("autotuning block, chunk and hand-off")
+        # small workloads launch in milliseconds: time each candidate 3 times
+        tb = chemgpu.chem_autotune(mech, boxes, base, reps=3 if n <= 2_000_000 else 1)
         tuned = {"block_size": tb.block_size, "chunk_steps": tb.chunk_steps,
                  "tail_steps": tb.tail_steps}
+    log(f"launch {tuned}; untimed pass with per-cell counters")
     # one untimed pass with per-cell counters for the flop count
     restore()
     chemgpu.chem_integrate_batched(mech, boxes, base)
@@ -270,6 +282,7 @@ def main():
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
     t0 = time.perf_counter()
     for k in range(args.steps):
         restore()
@@ -305,10 +318,12 @@ def main():
     }
     if not args.no_cpu:
         threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        log(f"oracle on {threads} host threads")
         out["cpu_baseline"] = cpu_baseline(hboxes, path, threads)
     if not args.no_surrogate and args.workload == "front":
         del boxes, pristine, tboxes
         torch.cuda.empty_cache()
+        log("surrogate leg")
         out["surrogate"] = surrogate_leg(args)
     print(json.dumps(out), flush=True)
 

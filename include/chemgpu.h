@@ -152,12 +152,14 @@ void chem_graph_destroy(chem_graph g);
 
 /*
  * Autotune block size, chunk length and cooperative hand-off for these
- * boxes: every (block in {64, 128, 192, 256, 384, 512} that fits the LDS
- * compaction slots, chunk in {1, 2, 4, 8, 16, 32, 64}) is timed with HIP
- * events on `stream` (median of `reps` launches) on the caller's boxes, then,
- * if base->tail_steps is 0, tail_steps in {8, 16, 32, 64, 128, never} for the
- * best pair; the boxes' states are snapshotted first and restored after
- * every trial and at the end, so the caller's data is left unchanged.  The
+ * boxes by coordinate descent: chunk in {1, 2, 4, 8, 16, 32, 64} at the
+ * default block, then block in {64, 128, 192, 256, 384, 512} (those that fit
+ * the LDS compaction slots) at the best chunk, chunk again at the best
+ * block, then, if base->tail_steps is 0, tail_steps in {8, 16, 32, 64, 128,
+ * never} for the best pair.  Each candidate is timed with HIP events on
+ * `stream` (median of `reps` launches after one untimed launch) on the
+ * caller's boxes; the boxes' states are snapshotted first and restored
+ * after every trial and at the end, so the caller's data is left unchanged.  The
  * winner is stored in the handle for the size bucket of these boxes (total
  * cells rounded to a power of two): later calls whose chunk_steps,
  * block_size or tail_steps are 0 use it.  If cache_path

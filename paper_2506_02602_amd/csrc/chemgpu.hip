@@ -1080,37 +1080,42 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     *med = ms[ms.size() / 2];
     return CHEM_OK;
   };
-  // block x chunk with the caller's (or the default) hand-off, then the
-  // hand-off point for the best pair
+  // Coordinate descent: chunk at the default block, block at the best
+  // chunk, chunk again at the best block, then the hand-off point for the
+  // best pair (each sweep keeps the incumbent unless a candidate is faster).
   const int blocks[] = {64, 128, 192, 256, 384, 512};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
   const int tails[] = {8, 16, 32, 64, 128, -1};
   double best_ms = 1e300;
   int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
   int best_tail = o.tail_steps != 0 ? o.tail_steps : kDefaultTail;
+  const bool tune_tail = o.tail_steps == 0 && o.fixed_steps == 0;
+  auto consider = [&](int b, int c, int tl) -> int {
+    if (m->entry->lds_per_lane() * b > 65536) return CHEM_OK;
+    chem_opts t = o;
+    t.block_size = b;
+    t.chunk_steps = c;
+    t.tail_steps = tl;
+    double med = 0;
+    const int trc = trial(t, &med);
+    if (trc != CHEM_OK) return trc;
+    if (med < best_ms) { best_ms = med; best_block = b; best_chunk = c; best_tail = tl; }
+    return CHEM_OK;
+  };
   rc = CHEM_OK;
-  for (int b : blocks) {
-    if (m->entry->lds_per_lane() * b > 65536) continue;
-    for (int c : chunks) {
-      chem_opts t = o;
-      t.block_size = b;
-      t.chunk_steps = c;
-      double med = 0;
-      if ((rc = trial(t, &med)) != CHEM_OK) break;
-      if (med < best_ms) { best_ms = med; best_block = b; best_chunk = c; }
-    }
-    if (rc != CHEM_OK) break;
+  for (int c : chunks)
+    if (rc == CHEM_OK) rc = consider(best_block, c, best_tail);
+  for (int b : blocks)
+    if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail);
+  {
+    const int b0 = best_block;
+    for (int c : chunks)
+      if (rc == CHEM_OK && c != best_chunk) rc = consider(b0, c, best_tail);
   }
-  if (rc == CHEM_OK && o.tail_steps == 0 && o.fixed_steps == 0) {
-    for (int tl : tails) {
-      chem_opts t = o;
-      t.block_size = best_block;
-      t.chunk_steps = best_chunk;
-      t.tail_steps = tl;
-      double med = 0;
-      if ((rc = trial(t, &med)) != CHEM_OK) break;
-      if (med < best_ms) { best_ms = med; best_tail = tl; }
-    }
+  if (tune_tail) {
+    const int b0 = best_block, c0 = best_chunk, t0 = best_tail;
+    for (int tl : tails)
+      if (rc == CHEM_OK && tl != t0) rc = consider(b0, c0, tl);
   }
   if ((e = restore()) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "restore");
   hipStreamSynchronize(s);
