@@ -56,9 +56,11 @@ typedef struct {
     int32_t block_size;  /* threads per block, multiple of 64 up to 512 (0 = tuned default) */
     int32_t fixed_steps; /* > 0: test mode, exactly this many steps of dt/fixed_steps, no control */
     int32_t tail_steps;  /* a cell still stepping after this many steps (accepted + rejected,
-                            over all sub-calls) is finished by the cooperative kernel, several
-                            lanes per cell; 0 = tuned default, < 0 = never.  The hand-off
-                            point depends only on the cell, so results do not depend on
+                            over all sub-calls) is handed over; if at most 64 cells per CU
+                            are handed over they are finished by the cooperative kernel,
+                            several lanes per cell, otherwise one cell per lane as before.
+                            0 = tuned default, < 0 = never.  The hand-off point and that
+                            choice depend only on the input, so results do not depend on
                             block_size or chunk_steps */
 } chem_opts;
 

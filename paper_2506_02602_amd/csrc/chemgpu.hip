@@ -62,7 +62,10 @@ struct TailBuf {
   int32_t* sub;           // current sub-call
   int32_t* base;          // steps taken before the current sub-call
   unsigned int* count;    // records written (zeroed before launch)
-  unsigned int* next;     // records claimed by the cooperative kernel (zeroed before launch)
+  unsigned long long* next;  // records claimed by whichever kernel finishes them (zeroed)
+  int cap;                // at most this many records go to the cooperative kernel; more
+                          // are resumed one per lane (the count decides, so the choice is
+                          // a function of the input only)
 };
 
 struct PoolArgs {
@@ -77,6 +80,7 @@ struct PoolArgs {
   int fixed_steps;
   int tail_steps;              // > 0: a cell that has taken this many steps moves to the tail
   TailBuf tail;
+  int resume;                  // 1: the work items are tail records, resumed one per lane
 };
 
 __device__ __forceinline__ int find_box(const PoolArgs& a, int64_t g) {
@@ -168,10 +172,10 @@ __global__ void eval_exp_kernel(const double* x, double* y, int64_t n) {
 }
 
 __global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
-                           unsigned int* tail_next) {
+                           unsigned long long* tail_next) {
   *next = 0ull;
   if (tail_count) *tail_count = 0u;
-  if (tail_next) *tail_next = 0u;
+  if (tail_next) *tail_next = 0ull;
 }
 
 template <class M, int LB>
@@ -193,7 +197,12 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   double u[N1], t = 0.0, h = 0.0, rho = 1.0;
   int nacc = 0, nrej = 0, sub = 0, base = 0;
   int bx = 0;
-  const int64_t total = a.total_dev ? (int64_t)*a.total_dev : a.total;
+  int64_t total = a.total_dev ? (int64_t)*a.total_dev : a.total;
+  if (a.resume) {
+    // resume tail records only when there are too many for the cooperative kernel
+    const unsigned int cnt = *a.tail.count;
+    total = cnt > (unsigned int)a.tail.cap ? (int64_t)cnt : 0;
+  }
 
   // claim the first B items
   if (tid == 0) {
@@ -207,7 +216,17 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
     if (tid >= free_from) {
       const int64_t g = s_base + (tid - free_from);
       item = -1;
-      if (g < total) {
+      if (g < total && a.resume) {
+        // a cell handed over at tail_steps: its state and hint are in its
+        // rows, its progress in record g
+        item = a.tail.item[g];
+        bx = find_box(a, item);
+        const BoxDesc& bd = box_ref(a, bx);
+        load_cell<M>(bd, cell_index(bd, item), u, rho, h);
+        t = a.tail.t[g];
+        nacc = a.tail.nacc[g]; nrej = a.tail.nrej[g];
+        sub = a.tail.sub[g]; base = a.tail.base[g];
+      } else if (g < total) {
         item = g;
         bx = find_box(a, g);
         const BoxDesc& bd = box_ref(a, bx);
@@ -358,6 +377,8 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   double* D = smem;
   int* I = reinterpret_cast<int*>(smem + C::ND);
   double* scr = smem + C::ND + C::NI / 2;
+  const unsigned int count = *a.tail.count;
+  if (count > (unsigned int)a.tail.cap) return;  // resumed one per lane instead
   const int tid = threadIdx.x;
   for (int i = tid; i < C::ND; i += blockDim.x) D[i] = C::dtab()[i];
   for (int i = tid; i < C::NI; i += blockDim.x) I[i] = C::itab()[i];
@@ -371,7 +392,6 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   const CoopCtx<M> x{D, I, sgrp, gl};
   CoopLane<M, G> ln;
   ln.load(D, I, gl);
-  const unsigned int count = *a.tail.count;
   // One step per iteration; a group whose cell finishes claims the next
   // record at once instead of waiting for the other groups of its wave.
   bool have = false;
@@ -387,7 +407,7 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   for (;;) {
     if (!have) {
       unsigned int r = 0;
-      if (gl == 0) r = atomicAdd(a.tail.next, 1u);
+      if (gl == 0) r = (unsigned int)atomicAdd(a.tail.next, 1ull);
       r = __shfl(r, 0, G);
       if (r >= count) break;
       const int64_t item = a.tail.item[r];
@@ -537,18 +557,18 @@ uint64_t fnv1a64(const std::vector<char>& d) {
 struct TailStore {
   void* mem = nullptr;
   int64_t cap = 0;
+  // [next u64][count u32][pad][t: cap doubles][item, nacc, nrej, sub, base: cap int32 each]
   TailBuf view() const {
     TailBuf b{};
     char* p = static_cast<char*>(mem);
-    b.t = reinterpret_cast<double*>(p);
-    p += sizeof(double) * cap;
-    int32_t* q = reinterpret_cast<int32_t*>(p);
+    b.next = reinterpret_cast<unsigned long long*>(p);
+    b.count = reinterpret_cast<unsigned int*>(p + 8);
+    b.t = reinterpret_cast<double*>(p + 16);
+    int32_t* q = reinterpret_cast<int32_t*>(p + 16 + sizeof(double) * cap);
     b.item = q; b.nacc = q + cap; b.nrej = q + 2 * cap; b.sub = q + 3 * cap; b.base = q + 4 * cap;
-    b.count = reinterpret_cast<unsigned int*>(q + 5 * cap);
-    b.next = b.count + 1;
     return b;
   }
-  static size_t bytes(int64_t cap) { return (size_t)cap * (sizeof(double) + 5 * sizeof(int32_t)) + 16; }
+  static size_t bytes(int64_t cap) { return 16 + (size_t)cap * (sizeof(double) + 5 * sizeof(int32_t)); }
 };
 
 struct chem_mech_s {
@@ -667,6 +687,28 @@ void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int
 
 int grid_for(chem_mech m, int block, int64_t total);
 
+// At most this many handed-over cells per CU are finished cooperatively; a
+// longer tail list is resumed one cell per lane (several lanes per cell only
+// pay while the tail is short next to the chip).
+constexpr int kTailCellsPerCU = 64;
+
+// The flow step's launches: pool reset + persistent kernel, then, with a
+// hand-off point, the cooperative kernel and the per-lane resumption of the
+// tail list (exactly one of the two does work, chosen by the list's length).
+hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_t s) {
+  if (a.tail_steps > 0) a.tail.cap = kTailCellsPerCU * m->n_cu;
+  hipError_t e = m->entry->launch_persistent(a, block, grid, s);
+  if (e != hipSuccess || a.tail_steps <= 0) return e;
+  e = m->entry->launch_coop(a, m->n_cu, s);
+  if (e != hipSuccess) return e;
+  PoolArgs r = a;
+  r.resume = 1;
+  r.tail_steps = 0;
+  r.next = a.tail.next;
+  r.total_dev = nullptr;
+  return m->entry->launch_persistent(r, block, grid, s);
+}
+
 int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
   int block, chunk;
   pick_launch(m, a.total, o, &block, &chunk);
@@ -683,12 +725,8 @@ int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
     if (rc) return rc;
     a.tail = m->tail.view();
   }
-  hipError_t e = m->entry->launch_persistent(a, block, grid_for(m, block, a.total), s);
-  if (e != hipSuccess) return hip_fail(e, "launch lsrk_persistent");
-  if (a.tail_steps > 0) {
-    e = m->entry->launch_coop(a, m->n_cu, s);
-    if (e != hipSuccess) return hip_fail(e, "launch lsrk_coop");
-  }
+  hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total), s);
+  if (e != hipSuccess) return hip_fail(e, "launch integrator kernels");
   return CHEM_OK;
 }
 
@@ -980,11 +1018,10 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   if (e != hipSuccess) return bail(e, "hipStreamCreate(capture)");
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) { hipStreamDestroy(cs); return bail(e, "hipStreamBeginCapture"); }
-  hipError_t le = m->entry->launch_persistent(a, block, grid, cs);
-  if (le == hipSuccess && tail_steps > 0) le = m->entry->launch_coop(a, m->n_cu, cs);
+  hipError_t le = launch_step(m, a, block, grid, cs);
   e = hipStreamEndCapture(cs, &g->graph);
   hipStreamDestroy(cs);
-  if (le != hipSuccess) return bail(le, "launch lsrk_persistent (capture)");
+  if (le != hipSuccess) return bail(le, "launch integrator kernels (capture)");
   if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return bail(e, "hipGraphInstantiate");

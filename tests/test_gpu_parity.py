@@ -218,6 +218,17 @@ def test_tail_cells_match_oracle(gmech9, omech9, mech9_path, tail):
                   max_flag_frac=0.02, tail_steps=tail)
 
 
+def test_long_tail_list_resumes_per_lane(gmech9, mech9_path):
+    """More handed-over cells than the cooperative kernel takes (64 per CU):
+    the list is resumed one cell per lane, bitwise the result of never
+    handing over."""
+    s0, hot = wl.front_2d(mech9_path, nx=1024, ny=1024, seed=37)
+    s1 = np.ascontiguousarray(np.tile(s0[:, hot], (1, 2)))       # ~42,000 stiff cells
+    ref, rst, rcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=-1)
+    g, gst, gcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=1)
+    assert np.array_equal(g, ref) and np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
+
+
 def test_tail_mech32(gmech32, omech32, mech32_path):
     """32 species / 150 reactions through the cooperative kernel (a full wave
     per cell, three reaction rounds per lane)."""
