@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--workload", default="front",
-                    choices=["front", "front_hot_tiled", "amr", "stress9", "stress32", "cells"])
+                    choices=["front", "front_hot_tiled", "amr", "stress9", "stress32", "cells",
+                             "diverge_a1", "diverge_a01"])
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2506_02602_amd",
                                                          "tuning_gfx950.json"),
                     help="autotuner cache (JSON, keyed by mechanism hash, size bucket, GPU "
@@ -192,6 +193,11 @@ WORKLOADS = {
     "stress32": "256x256x64 cells (4,194,304), T ~ U[900,2800] K, p ~ U[1,40] atm i.i.d.; "
                 "seeded 32-species 150-reaction C/H/O/N mechanism",
     "cells": "4096 independent cells, T ~ U[1000,1600] K, 1 atm, stoichiometric H2/O2/N2",
+    "diverge_a1": "thread-coherence field: 16x256x16 = 65,536 cells, T(y) of the paper's Eq. 27-28 with "
+                  "alpha = 1.0 (T_low 1000 K, T_high 1600 K), H2:O2:N2 = 1:2:7, 1 atm; 100 calls of "
+                  "dt = 1e-5 s in one batched launch (one flow step = the 100 calls)",
+    "diverge_a01": "thread-divergence field: as diverge_a1 with alpha = 0.1 (T from 515 to 2068 K in "
+                   "40 oscillations along y); 100 calls of dt = 1e-5 s in one batched launch",
 }
 
 
@@ -212,6 +218,10 @@ def load_workload(name):
     if name == "amr":
         return path, [dict(state=b["state"], dt=b["dt"], n_sub=b["n_sub"], level=b["level"])
                       for b in wl.amr_hierarchy(path)]
+    if name in ("diverge_a1", "diverge_a01"):
+        alpha = 1.0 if name == "diverge_a1" else 0.1
+        return path, [dict(state=wl.diverge_box(path, alpha), dt=wl.DIVERGE_DT,
+                           n_sub=wl.DIVERGE_CALLS)]
     if name in ("stress9", "stress32"):
         return path, [dict(state=wl.stress_3d(path), dt=wl.DT_FLOW, n_sub=1)]
     return path, [dict(state=wl.cells_uniform(path), dt=wl.DT_FLOW, n_sub=1)]
@@ -351,6 +361,9 @@ def main():
                                 "status_nonzero": int((st != 0).sum())},
         "flops_per_rk_step": codegen.step_flops(m),
     }
+    sub_calls = int(sum(b["state"].shape[1] * b.get("n_sub", 1) for b in hboxes))
+    if sub_calls != n:
+        out["cell_subcalls_per_s"] = sub_calls * args.steps / elapsed
     if not args.no_cpu:
         threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
         log(f"oracle on {threads} host threads")

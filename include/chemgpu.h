@@ -158,7 +158,7 @@ void chem_graph_destroy(chem_graph g);
  * default block, then block in {64, 128, 192, 256, 384, 512} (those that fit
  * the LDS compaction slots) at the best chunk, chunk again at the best
  * block, then, if base->tail_steps is 0, tail_steps in {8, 16, 32, 64, 128,
- * never} for the best pair.  Each candidate is timed with HIP events on
+ * 256, 512, never} for the best pair.  Each candidate is timed with HIP events on
  * `stream` (median of `reps` launches after one untimed launch) on the
  * caller's boxes; the boxes' states are snapshotted first and restored
  * after every trial and at the end, so the caller's data is left unchanged.  The

@@ -1122,7 +1122,7 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   // best pair (each sweep keeps the incumbent unless a candidate is faster).
   const int blocks[] = {64, 128, 192, 256, 384, 512};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
-  const int tails[] = {8, 16, 32, 64, 128, -1};
+  const int tails[] = {8, 16, 32, 64, 128, 256, 512, -1};
   double best_ms = 1e300;
   int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
   int best_tail = o.tail_steps != 0 ? o.tail_steps : kDefaultTail;

@@ -177,5 +177,46 @@ def stress_3d(mech_path, shape=(256, 256, 64), seed=4):
     return pack(T, Y, density(T, p, Y, W))
 
 
+def diverge_temperature(y, L, alpha, T_low=1000.0, T_high=1600.0, y_m=None):
+    """The paper's test temperature profile (Sec. 4.2.2, Eq. 27) with the
+    parameters of Eq. 28: T_b + T_r tanh(k (y - y_m)/L) +
+    A exp(-8 ((y - y_m)/L)^2) cos(2 pi f y / L), k = 6/alpha, f = 4/alpha,
+    A = 50/alpha.  T_low, T_high and y_m are not given there; the readings
+    are 1000 K, 1600 K and L/2."""
+    y = np.asarray(y, dtype=np.float64)
+    y_m = 0.5 * L if y_m is None else y_m
+    k, f, A = 6.0 / alpha, 4.0 / alpha, 50.0 / alpha
+    T_b, T_r = 0.5 * (T_high + T_low), 0.5 * (T_high - T_low)
+    z = (y - y_m) / L
+    return T_b + T_r * np.tanh(k * z) + A * np.exp(-8.0 * z * z) * np.cos(2.0 * np.pi * f * y / L)
+
+
+def diverge_box(mech_path, alpha, shape=(16, 256, 16), p=P_ATM):
+    """The thread-coherence (alpha = 1) / thread-divergence (alpha = 0.1)
+    workload of Sec. 4.2.2: 16 x 256 x 16 = 65,536 cells on a unit box, T
+    varying in y only (cell centres, Eq. 27-28), uniform composition
+    H2 : O2 : N2 = 1 : 2 : 7 by mole, 1 atm (the pressure is not given).
+    Cells are ordered x fastest, then y, then z.  Integrated as 100 calls of
+    dt = 1e-5 s (Tables 4-5)."""
+    names, W = read_species(mech_path)
+    nx, ny, nz = shape
+    L = 1.0
+    y = (np.arange(ny) + 0.5) * (L / ny)
+    Ty = diverge_temperature(y, L, alpha)
+    T = np.broadcast_to(Ty[None, :, None], (nz, ny, nx)).reshape(-1).copy()
+    n = T.size
+    X = np.zeros(len(names))
+    for sp, x in (("H2", 1.0), ("O2", 2.0), ("N2", 7.0)):
+        X[names.index(sp)] = x
+    Y1 = X * W / np.sum(X * W)
+    Y = np.repeat(Y1[:, None], n, axis=1)
+    rho = density(T, np.full(n, p), Y, W)
+    return pack(T, Y, rho)
+
+
+DIVERGE_DT = 1.0e-5
+DIVERGE_CALLS = 100
+
+
 def mech_file(name: str) -> str:
     return os.path.join(os.path.dirname(os.path.abspath(__file__)), "mech", name + ".mech")

@@ -88,3 +88,23 @@ def assert_parity(gmech, omech, s_full, dt, idx=None, max_flag_frac=0.15, label=
           flush=True)
     assert frac <= max_flag_frac
     return int(bad.sum())
+
+
+def oracle_subcalls(om, state, dt, n_sub, **kw):
+    """n_sub oracle calls of dt on a copy of `state`; a cell stops at its
+    first non-OK sub-call.  Returns (state, status, counts)."""
+    s = state.copy()
+    n = s.shape[1]
+    status = np.zeros(n, np.int32)
+    counts = np.zeros((2, n), np.int32)
+    live = np.arange(n)
+    for _ in range(n_sub):
+        if len(live) == 0:
+            break
+        sub = np.ascontiguousarray(s[:, live])
+        st, cn = om.integrate(sub, dt, **kw)
+        s[:, live] = sub
+        counts[:, live] += cn
+        status[live] = st
+        live = live[st == 0]
+    return s, status, counts

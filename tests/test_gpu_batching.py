@@ -13,7 +13,7 @@ import pytest
 
 from paper_2506_02602_amd import workloads as wl
 
-from gpu_common import parity_violations, to_gpu
+from gpu_common import oracle_subcalls, parity_violations, to_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -27,26 +27,6 @@ def cg():
 @pytest.fixture(scope="module")
 def gm9(cg, mech9_path):
     return cg.chem_mech_load(mech9_path)
-
-
-def oracle_subcalls(om, state, dt, n_sub, **kw):
-    """n_sub oracle calls of dt on a copy of `state`; a cell stops at its
-    first non-OK sub-call.  Returns (state, status, counts)."""
-    s = state.copy()
-    n = s.shape[1]
-    status = np.zeros(n, np.int32)
-    counts = np.zeros((2, n), np.int32)
-    live = np.arange(n)
-    for _ in range(n_sub):
-        if len(live) == 0:
-            break
-        sub = np.ascontiguousarray(s[:, live])
-        st, cn = om.integrate(sub, dt, **kw)
-        s[:, live] = sub
-        counts[:, live] += cn
-        status[live] = st
-        live = live[st == 0]
-    return s, status, counts
 
 
 def gpu_boxes(hier, with_out=True):

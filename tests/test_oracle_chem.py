@@ -319,3 +319,27 @@ def test_h_row_is_next_step_hint(mech9_path, omech9):
     st, cnt = omech9.integrate(s, 1e-7)
     N = omech9.ns
     assert (s[N + 2] > 0).all() and (s[N + 2] <= 5 * 1e-7).all()
+
+
+def test_divergence_workload_profile(mech9_path):
+    """Eq. 27-28 at the midpoint reduce to T_b + A cos(2 pi f y_m / L); the
+    far ends approach T_b -+ T_r (tanh saturates, the Gaussian vanishes); the
+    field is uniform in x and z with mole fractions H2:O2:N2 = 1:2:7."""
+    import math
+    from paper_2506_02602_amd import workloads as wl
+    for alpha in (1.0, 0.1):
+        A, f = 50.0 / alpha, 4.0 / alpha
+        assert wl.diverge_temperature(0.5, 1.0, alpha) == pytest.approx(
+            1300.0 + A * math.cos(2 * math.pi * f * 0.5), rel=1e-14)
+        lo, hi = wl.diverge_temperature(np.array([0.0, 1.0]), 1.0, alpha)
+        assert abs(lo - (1300.0 - 300.0 * math.tanh(3.0 / alpha))) < A * math.exp(-2.0) + 1e-9
+        assert abs(hi - (1300.0 + 300.0 * math.tanh(3.0 / alpha))) < A * math.exp(-2.0) + 1e-9
+    s = wl.diverge_box(mech9_path, 0.1)
+    names, W = wl.read_species(mech9_path)
+    T = s[0].reshape(16, 256, 16)
+    assert (T == T[:1, :, :1]).all() and s.shape[1] == 65536
+    X = s[1:10, 0] / W
+    X /= X.sum()
+    k = {n: i for i, n in enumerate(names)}
+    assert X[k["O2"]] / X[k["H2"]] == pytest.approx(2.0, rel=1e-12)
+    assert X[k["N2"]] / X[k["H2"]] == pytest.approx(7.0, rel=1e-12)
