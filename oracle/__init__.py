@@ -61,6 +61,13 @@ def lib():
         L.or_integrate_linear.argtypes = [I, P, P, D, D, D, I, I, C.POINTER(D), C.POINTER(I),
                                           C.POINTER(I), P, I, C.POINTER(I)]
         L.or_integrate_linear.restype = I
+        L.or_rkf45_coeffs.argtypes = [P, P, P]
+        L.or_integrate_cell_scheme.argtypes = [I] + L.or_integrate_cell.argtypes
+        L.or_integrate_cell_scheme.restype = I
+        L.or_integrate_scheme.argtypes = [I] + L.or_integrate.argtypes
+        L.or_integrate_scheme.restype = I
+        L.or_integrate_linear_scheme.argtypes = [I] + L.or_integrate_linear.argtypes
+        L.or_integrate_linear_scheme.restype = I
         _lib = L
     return _lib
 
@@ -73,6 +80,16 @@ def lsrk_coeffs():
     a, b, bh = np.zeros(4), np.zeros(5), np.zeros(5)
     lib().or_lsrk_coeffs(_ptr(a), _ptr(b), _ptr(bh))
     return a, b, bh
+
+
+SCHEMES = {"lsrk": 0, "rkf45": 1}
+
+
+def rkf45_coeffs():
+    """Fehlberg 4(5): A[6][5] (row i: a_i1..a_i5), fourth- and fifth-order weights."""
+    a, b4, b5 = np.zeros(30), np.zeros(6), np.zeros(6)
+    lib().or_rkf45_coeffs(_ptr(a), _ptr(b4), _ptr(b5))
+    return a.reshape(6, 5), b4, b5
 
 
 class Mech:
@@ -120,12 +137,13 @@ class Mech:
         return f
 
     def integrate_cell(self, rho, u, dt, rtol=1e-8, atol=1e-10, max_steps=100000,
-                       fixed_steps=0, h0=0.0, trace_cap=0):
+                       fixed_steps=0, h0=0.0, trace_cap=0, scheme="lsrk"):
         u = np.array(u, dtype=np.float64)
         h = C.c_double(h0)
         na, nr, tl = C.c_int(), C.c_int(), C.c_int()
         tr = np.zeros(4 * max(trace_cap, 1)) if trace_cap else None
-        st = lib().or_integrate_cell(self._h, float(rho), _ptr(u), float(dt), float(rtol),
+        st = lib().or_integrate_cell_scheme(SCHEMES[scheme], self._h, float(rho), _ptr(u),
+                                     float(dt), float(rtol),
                                      float(atol), int(max_steps), int(fixed_steps), C.byref(h),
                                      C.byref(na), C.byref(nr),
                                      _ptr(tr) if tr is not None else None, int(trace_cap),
@@ -136,7 +154,7 @@ class Mech:
         return out
 
     def integrate(self, state: np.ndarray, dt: float, rtol=1e-8, atol=1e-10,
-                  max_steps=100000, fixed_steps=0, nthreads=None):
+                  max_steps=100000, fixed_steps=0, nthreads=None, scheme="lsrk"):
         """In-place on an SoA block state[(N+3), n] (rows T, Y.., rho, h).
 
         Returns (status[n], counts[2, n]) with counts = (n_acc, n_rej)."""
@@ -147,14 +165,14 @@ class Mech:
         counts = np.zeros((2, n), dtype=np.int32)
         if nthreads is None:
             nthreads = os.cpu_count() or 1
-        lib().or_integrate(self._h, _ptr(state), n, n, float(dt), float(rtol), float(atol),
-                           int(max_steps), int(fixed_steps), int(nthreads), _ptr(status),
-                           _ptr(counts))
+        lib().or_integrate_scheme(SCHEMES[scheme], self._h, _ptr(state), n, n, float(dt),
+                                  float(rtol), float(atol), int(max_steps), int(fixed_steps),
+                                  int(nthreads), _ptr(status), _ptr(counts))
         return status, counts
 
 
 def integrate_linear(A, u0, dt, rtol=1e-8, atol=1e-10, max_steps=100000, fixed_steps=0,
-                     h0=0.0, trace_cap=0):
+                     h0=0.0, trace_cap=0, scheme="lsrk"):
     """u' = A u through the oracle's own step/controller/driver."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     n = A.shape[0]
@@ -162,7 +180,8 @@ def integrate_linear(A, u0, dt, rtol=1e-8, atol=1e-10, max_steps=100000, fixed_s
     h = C.c_double(h0)
     na, nr, tl = C.c_int(), C.c_int(), C.c_int()
     tr = np.zeros(4 * max(trace_cap, 1)) if trace_cap else None
-    st = lib().or_integrate_linear(n, _ptr(A), _ptr(u), float(dt), float(rtol), float(atol),
+    st = lib().or_integrate_linear_scheme(SCHEMES[scheme], n, _ptr(A), _ptr(u), float(dt),
+                                   float(rtol), float(atol),
                                    int(max_steps), int(fixed_steps), C.byref(h), C.byref(na),
                                    C.byref(nr), _ptr(tr) if tr is not None else None,
                                    int(trace_cap), C.byref(tl))

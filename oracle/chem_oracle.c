@@ -16,7 +16,9 @@
  *     (constant-volume adiabatic closure for dT/dt);
  *   - one step of the two-register low-storage RK (Eq. 21) with the embedded
  *     error register, and the WRMS step-size controller of Eq. 22;
- *   - a per-cell driver over one flow time step.
+ *   - a per-cell driver over one flow time step;
+ *   - for comparison, a full-storage Runge-Kutta-Fehlberg 4(5) step under the
+ *     same controller (exponent 1/5 for its fourth-order error estimate).
  *
  * Readings where the paper is silent or garbled (each also listed in the
  * design notes of the repository):
@@ -366,6 +368,54 @@ static void lsrk_step(or_rhs_fn f, const void *ctx, int n, double h, const doubl
     }
 }
 
+/* The full-storage comparison scheme (the paper's Sec. 4.2.2 compares the
+ * low-storage scheme with a Runge-Kutta-Fehlberg integrator): Fehlberg's
+ * six-stage 4(5) pair, advancing with the fourth-order weights and
+ * estimating the error as the difference to the fifth-order ones.  All
+ * stages are kept (k_1..k_6), which is the storage the low-storage scheme
+ * avoids.  Coefficients as exact rationals. */
+static const double RKF_A[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 4.0, 0, 0, 0, 0},
+    {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+static const double RKF_B4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+static const double RKF_B5[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0,
+                                 2.0 / 55.0};
+
+void or_rkf45_coeffs(double *a, double *b4, double *b5) {
+    for (int i = 0; i < 6; i++) {
+        for (int j = 0; j < 5; j++) a[5 * i + j] = RKF_A[i][j];
+        b4[i] = RKF_B4[i];
+        b5[i] = RKF_B5[i];
+    }
+}
+
+/* One RKF45 step: k_i = f(u_n + h sum_{j<i} a_ij k_j), unew = u_n + h sum b4_i k_i,
+ * err = h sum (b5_i - b4_i) k_i.  K holds the six stage vectors. */
+static void rkf45_step(or_rhs_fn f, const void *ctx, int n, double h, const double *un,
+                       double *unew, double *err_vec, double *U, double *K) {
+    for (int s = 0; s < 6; s++) {
+        for (int i = 0; i < n; i++) {
+            double acc = 0.0;
+            for (int j = 0; j < s; j++) acc += RKF_A[s][j] * K[j * n + i];
+            U[i] = un[i] + h * acc;
+        }
+        f(ctx, U, K + s * n);
+    }
+    for (int i = 0; i < n; i++) {
+        double y4 = 0.0, e = 0.0;
+        for (int s = 0; s < 6; s++) {
+            y4 += RKF_B4[s] * K[s * n + i];
+            e += (RKF_B5[s] - RKF_B4[s]) * K[s * n + i];
+        }
+        unew[i] = un[i] + h * y4;
+        err_vec[i] = h * e;
+    }
+}
+
 /* Eq. 22: WRMS norm of the error with weights from the state at step start. */
 static double wrms(int n, const double *e, const double *un, double rtol, double atol) {
     double sum = 0.0;
@@ -376,11 +426,13 @@ static double wrms(int n, const double *e, const double *un, double rtol, double
     return sqrt(sum / n);
 }
 
-/* Eq. 22's step factor with the [1/5, 5] clamp and beta = 0.9. */
-static double step_factor(double err) {
+/* Eq. 22's step factor with the [1/5, 5] clamp and beta = 0.9; the exponent
+ * is 1/(q+1) for an error estimate of order q: 1/4 for the low-storage
+ * scheme's third-order estimate, 1/5 for Fehlberg's fourth-order one. */
+static double step_factor(double err, double expo) {
     if (err != err) return 0.2;
     if (err == 0.0) return 5.0;
-    double fac = 0.9 * pow(err, -0.25);
+    double fac = 0.9 * pow(err, -expo);
     if (fac < 0.2) fac = 0.2;
     if (fac > 5.0) fac = 5.0;
     return fac;
@@ -390,18 +442,27 @@ typedef struct { double t, h, err; int accepted; } or_trace;
 
 /* Integrate u over [0, dt]; returns a status code.  h_inout: initial step
  * hint (<= 0 => dt) and, on return, the proposed next step. */
-static int drive(or_rhs_fn f, const void *ctx, int n, double *u, double dt, double rtol,
-                 double atol, int max_steps, int fixed_steps, double *h_inout, int *nacc,
-                 int *nrej, or_trace *trace, int trace_cap, int *trace_len) {
+enum { OR_SCHEME_LSRK = 0, OR_SCHEME_RKF45 = 1 };
+
+static void scheme_step(int scheme, or_rhs_fn f, const void *ctx, int n, double h,
+                        const double *un, double *unew, double *e, double *U, double *F) {
+    if (scheme == OR_SCHEME_RKF45) rkf45_step(f, ctx, n, h, un, unew, e, U, F);
+    else lsrk_step(f, ctx, n, h, un, unew, e, U, F);
+}
+
+static int drive(int scheme, or_rhs_fn f, const void *ctx, int n, double *u, double dt,
+                 double rtol, double atol, int max_steps, int fixed_steps, double *h_inout,
+                 int *nacc, int *nrej, or_trace *trace, int trace_cap, int *trace_len) {
     double *unew = malloc(sizeof(double) * n), *e = malloc(sizeof(double) * n);
-    double *U = malloc(sizeof(double) * n), *F = malloc(sizeof(double) * n);
+    double *U = malloc(sizeof(double) * n), *F = malloc(sizeof(double) * n * 6);
+    const double expo = scheme == OR_SCHEME_RKF45 ? 0.2 : 0.25;
     int status = OR_OK;
     *nacc = 0; *nrej = 0;
     if (trace_len) *trace_len = 0;
     if (fixed_steps > 0) {
         double h = dt / fixed_steps;
         for (int s = 0; s < fixed_steps; s++) {
-            lsrk_step(f, ctx, n, h, u, unew, e, U, F);
+            scheme_step(scheme, f, ctx, n, h, u, unew, e, U, F);
             for (int i = 0; i < n; i++) u[i] = unew[i];
             (*nacc)++;
         }
@@ -414,9 +475,9 @@ static int drive(or_rhs_fn f, const void *ctx, int n, double *u, double dt, doub
     for (;;) {
         int last = 0;
         if (h >= dt - t) { h = dt - t; last = 1; }
-        lsrk_step(f, ctx, n, h, u, unew, e, U, F);
+        scheme_step(scheme, f, ctx, n, h, u, unew, e, U, F);
         double err = wrms(n, e, u, rtol, atol);
-        double fac = step_factor(err);
+        double fac = step_factor(err, expo);
         int ok = (err <= 1.0);
         if (trace && *trace_len < trace_cap) {
             trace[*trace_len].t = t; trace[*trace_len].h = h;
@@ -449,16 +510,17 @@ static void chem_rhs_cb(const void *ctx, const double *u, double *f) {
 }
 
 /* One cell: u (N+1) in/out.  Returns status. */
-int or_integrate_cell(const or_mech *m, double rho, double *u, double dt, double rtol,
-                      double atol, int max_steps, int fixed_steps, double *h_inout,
-                      int *nacc, int *nrej, double *trace_out, int trace_cap, int *trace_len) {
+int or_integrate_cell_scheme(int scheme, const or_mech *m, double rho, double *u, double dt,
+                             double rtol, double atol, int max_steps, int fixed_steps,
+                             double *h_inout, int *nacc, int *nrej, double *trace_out,
+                             int trace_cap, int *trace_len) {
     int n = m->ns + 1;
     for (int i = 0; i < n; i++) if (!isfinite(u[i])) { *nacc = *nrej = 0; return OR_NONFINITE; }
     if (!isfinite(rho)) { *nacc = *nrej = 0; return OR_NONFINITE; }
     chem_ctx ctx = {m, rho};
     or_trace *tr = trace_out ? malloc(sizeof(or_trace) * (trace_cap > 0 ? trace_cap : 1)) : NULL;
-    int st = drive(chem_rhs_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps, h_inout,
-                   nacc, nrej, tr, trace_cap, trace_len);
+    int st = drive(scheme, chem_rhs_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps,
+                   h_inout, nacc, nrej, tr, trace_cap, trace_len);
     if (tr) {
         for (int i = 0; i < *trace_len; i++) {
             trace_out[4 * i + 0] = tr[i].t; trace_out[4 * i + 1] = tr[i].h;
@@ -469,12 +531,20 @@ int or_integrate_cell(const or_mech *m, double rho, double *u, double dt, double
     return st;
 }
 
+int or_integrate_cell(const or_mech *m, double rho, double *u, double dt, double rtol,
+                      double atol, int max_steps, int fixed_steps, double *h_inout,
+                      int *nacc, int *nrej, double *trace_out, int trace_cap, int *trace_len) {
+    return or_integrate_cell_scheme(OR_SCHEME_LSRK, m, rho, u, dt, rtol, atol, max_steps,
+                                    fixed_steps, h_inout, nacc, nrej, trace_out, trace_cap,
+                                    trace_len);
+}
+
 /* All cells of an SoA state block: state[v*ld + i], rows v = 0 T, 1..N Y_k,
  * N+1 rho (read only), N+2 h (in: step hint, <= 0 => dt; out: next step).
  * counts (may be NULL) receives n_acc in [i] and n_rej in [n + i]. */
-int or_integrate(const or_mech *m, double *state, int64_t ld, int64_t n, double dt,
-                 double rtol, double atol, int max_steps, int fixed_steps, int nthreads,
-                 int32_t *status, int32_t *counts) {
+int or_integrate_scheme(int scheme, const or_mech *m, double *state, int64_t ld, int64_t n,
+                        double dt, double rtol, double atol, int max_steps, int fixed_steps,
+                        int nthreads, int32_t *status, int32_t *counts) {
     int N = m->ns;
     if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
@@ -484,8 +554,8 @@ int or_integrate(const or_mech *m, double *state, int64_t ld, int64_t n, double 
         double rho = state[(N + 1) * ld + i];
         double h = state[(N + 2) * ld + i];
         int na = 0, nr = 0;
-        int st = or_integrate_cell(m, rho, u, dt, rtol, atol, max_steps, fixed_steps, &h, &na, &nr,
-                                   NULL, 0, NULL);
+        int st = or_integrate_cell_scheme(scheme, m, rho, u, dt, rtol, atol, max_steps,
+                                          fixed_steps, &h, &na, &nr, NULL, 0, NULL);
         if (st != OR_NONFINITE) {
             for (int v = 0; v <= N; v++) state[v * ld + i] = u[v];
             state[(N + 2) * ld + i] = h;
@@ -494,6 +564,13 @@ int or_integrate(const or_mech *m, double *state, int64_t ld, int64_t n, double 
         if (counts) { counts[i] = na; counts[n + i] = nr; }
     }
     return 0;
+}
+
+int or_integrate(const or_mech *m, double *state, int64_t ld, int64_t n, double dt,
+                 double rtol, double atol, int max_steps, int fixed_steps, int nthreads,
+                 int32_t *status, int32_t *counts) {
+    return or_integrate_scheme(OR_SCHEME_LSRK, m, state, ld, n, dt, rtol, atol, max_steps,
+                               fixed_steps, nthreads, status, counts);
 }
 
 /* ---------------------------------------------- linear test problems */
@@ -509,13 +586,14 @@ static void lin_rhs_cb(const void *ctx, const double *u, double *f) {
 }
 
 /* u' = A u with the same step, controller and driver as the chemistry path. */
-int or_integrate_linear(int n, const double *A, double *u, double dt, double rtol, double atol,
-                        int max_steps, int fixed_steps, double *h_inout, int *nacc, int *nrej,
-                        double *trace_out, int trace_cap, int *trace_len) {
+int or_integrate_linear_scheme(int scheme, int n, const double *A, double *u, double dt,
+                               double rtol, double atol, int max_steps, int fixed_steps,
+                               double *h_inout, int *nacc, int *nrej, double *trace_out,
+                               int trace_cap, int *trace_len) {
     lin_ctx ctx = {n, A};
     or_trace *tr = trace_out ? malloc(sizeof(or_trace) * (trace_cap > 0 ? trace_cap : 1)) : NULL;
-    int st = drive(lin_rhs_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps, h_inout, nacc,
-                   nrej, tr, trace_cap, trace_len);
+    int st = drive(scheme, lin_rhs_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps,
+                   h_inout, nacc, nrej, tr, trace_cap, trace_len);
     if (tr) {
         for (int i = 0; i < *trace_len; i++) {
             trace_out[4 * i + 0] = tr[i].t; trace_out[4 * i + 1] = tr[i].h;
@@ -524,4 +602,12 @@ int or_integrate_linear(int n, const double *A, double *u, double dt, double rto
         free(tr);
     }
     return st;
+}
+
+int or_integrate_linear(int n, const double *A, double *u, double dt, double rtol, double atol,
+                        int max_steps, int fixed_steps, double *h_inout, int *nacc, int *nrej,
+                        double *trace_out, int trace_cap, int *trace_len) {
+    return or_integrate_linear_scheme(OR_SCHEME_LSRK, n, A, u, dt, rtol, atol, max_steps,
+                                      fixed_steps, h_inout, nacc, nrej, trace_out, trace_cap,
+                                      trace_len);
 }

@@ -244,16 +244,21 @@ def test_energy_conservation_scales_with_tolerance(mech9_path, omech9):
     assert drifts[2] < drifts[0]
 
 
-def test_fourth_order_convergence_fixed_steps(mech9_path, omech9):
+@pytest.mark.parametrize("scheme", ["lsrk", "rkf45"])
+def test_fourth_order_convergence_fixed_steps(mech9_path, omech9, scheme):
     """Fixed-step error in Y vs a fine reference falls ~16x per halving (order 4)
-    on an igniting 1 atm cell over 0.1 ms (smooth, not stability-limited)."""
+    on an igniting 1 atm cell over 0.1 ms (smooth, not stability-limited);
+    both the low-storage scheme and the full-storage comparison scheme (whose
+    smaller stability region needs at least 1024 steps on the 1600 K cell)."""
+    ns = (512, 1024, 2048) if scheme == "lsrk" else (1024, 2048)
     for T0 in (1500.0, 1600.0):
         rho, u = _cell(mech9_path, T0, 1.0)
-        ref = omech9.integrate_cell(rho, u, 1e-4, fixed_steps=16384)["u"]
-        errs = [np.abs(omech9.integrate_cell(rho, u, 1e-4, fixed_steps=n)["u"] - ref)[1:].max()
-                for n in (512, 1024, 2048)]
-        r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
-        assert 14 < r1 < 18 and 14 < r2 < 18
+        ref = omech9.integrate_cell(rho, u, 1e-4, fixed_steps=16384, scheme=scheme)["u"]
+        errs = [np.abs(omech9.integrate_cell(rho, u, 1e-4, fixed_steps=n, scheme=scheme)["u"]
+                       - ref)[1:].max()
+                for n in ns]
+        for e0, e1 in zip(errs, errs[1:]):
+            assert 14 < e0 / e1 < 18
 
 
 def _rk4_bruteforce(m, rho, u0, dt, n):

@@ -219,3 +219,87 @@ def test_embedded_local_error_order():
         e.append(r["trace"][0, 2])
     assert e[0] / e[1] == pytest.approx(16.0, rel=0.05)
     assert e[1] / e[2] == pytest.approx(16.0, rel=0.03)
+
+
+# ------------------------------------------- full-storage comparison scheme
+
+def _load_rkf45():
+    vals = {}
+    with open(os.path.join(GOLD, "rkf45_fehlberg.txt")) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            name, num, den = ln.split()
+            vals[name] = Fr(int(num), int(den))
+    A = [[vals.get(f"a{i}{j}", Fr(0)) for j in range(1, 7)] for i in range(1, 7)]
+    b4 = [vals[f"b4_{i}"] for i in range(1, 7)]
+    b5 = [vals[f"b5_{i}"] for i in range(1, 7)]
+    return A, b4, b5
+
+
+def _order5_residuals(A, w):
+    one = [Fr(1)] * len(w)
+    c = _mv(A, one)
+    Ac = _mv(A, c)
+    c2 = [x * x for x in c]
+    return [
+        _dot(w, [x ** 4 for x in c]) - Fr(1, 5),
+        _dot(w, [ci * ci * y for ci, y in zip(c, Ac)]) - Fr(1, 10),
+        _dot(w, [ci * y for ci, y in zip(c, _mv(A, c2))]) - Fr(1, 15),
+        _dot(w, [ci * y for ci, y in zip(c, _mv(A, Ac))]) - Fr(1, 30),
+        _dot(w, [y * y for y in Ac]) - Fr(1, 20),
+        _dot(w, _mv(A, [x ** 3 for x in c])) - Fr(1, 20),
+        _dot(w, _mv(A, [ci * y for ci, y in zip(c, Ac)])) - Fr(1, 40),
+        _dot(w, _mv(A, _mv(A, c2))) - Fr(1, 60),
+        _dot(w, _mv(A, _mv(A, Ac))) - Fr(1, 120),
+    ]
+
+
+def test_rkf45_order_conditions_exact():
+    """Fourth-order weights satisfy the 8 order-4 conditions exactly, the
+    fifth-order ones also the 9 order-5 conditions; the fourth-order weights
+    do not."""
+    A, b4, b5 = _load_rkf45()
+    assert all(r == 0 for r in _order_residuals(A, b4))
+    assert all(r == 0 for r in _order_residuals(A, b5))
+    assert all(r == 0 for r in _order5_residuals(A, b5))
+    assert any(r != 0 for r in _order5_residuals(A, b4))
+
+
+def test_rkf45_oracle_coefficients_are_correctly_rounded():
+    A, b4, b5 = _load_rkf45()
+    oa, ob4, ob5 = oracle.rkf45_coeffs()
+    for i in range(6):
+        for j in range(i):
+            assert oa[i, j] == float(A[i][j])
+    assert list(ob4) == [float(x) for x in b4]
+    assert list(ob5) == [float(x) for x in b5]
+
+
+@pytest.mark.parametrize("lam,h,n", [(-3.0, 0.1, 10), (-1.0, 1.0, 7), (2.0, 0.05, 20)])
+def test_rkf45_dahlquist_fixed_steps(lam, h, n):
+    """y' = lam y with the full-storage scheme: R4(h lam)^n from its tableau."""
+    A, b4, _ = _load_rkf45()
+    gam = _stab_coeffs(A, b4)
+    mp.mp.dps = 40
+    expect = float(_R(gam, mp.mpf(lam) * mp.mpf(h)) ** n)
+    r = oracle.integrate_linear(np.array([[lam]]), [1.0], h * n, fixed_steps=n, scheme="rkf45")
+    assert r["u"][0] == pytest.approx(expect, rel=1e-13)
+
+
+def test_rkf45_error_estimate_and_exponent():
+    """First-step error = |R5(z) - R4(z)| |y0| / (rtol |y0| + atol); the next
+    step is h * clamp(0.9 err^(-1/5), 1/5, 5) (fourth-order estimate)."""
+    A, b4, b5 = _load_rkf45()
+    g4, g5 = _stab_coeffs(A, b4), _stab_coeffs(A, b5)
+    mp.mp.dps = 40
+    lam, y0, dt, rtol, atol = -2.0, 3.0, 0.3, 1e-6, 1e-10
+    z = mp.mpf(lam) * mp.mpf(dt)
+    est = float(abs(_R(g5, z) - _R(g4, z)) * y0 / (rtol * y0 + atol))
+    r = oracle.integrate_linear(np.array([[lam]]), [y0], dt, rtol=rtol, atol=atol,
+                                trace_cap=50, scheme="rkf45")
+    tr = r["trace"]
+    assert tr[0, 2] == pytest.approx(est, rel=1e-9)
+    assert tr[0, 3] == 0                                   # rejected (err >> 1)
+    fac = min(max(0.9 * est ** -0.2, 0.2), 5.0)
+    assert tr[1, 1] == pytest.approx(dt * fac, rel=1e-12)
