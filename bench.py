@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--scheme", default="lsrk", choices=["lsrk", "rkf45"],
+                    help="lsrk: the paper's two-register LSRK4(3)5; rkf45: the full-storage "
+                         "Runge-Kutta-Fehlberg 4(5) comparison scheme")
     ap.add_argument("--tail", type=int, default=0,
                     help="steps after which a cell moves to the cooperative kernel "
                          "(0 = default, < 0 = never)")
@@ -286,7 +289,7 @@ def main():
     mech = chemgpu.chem_mech_load(path)
     chemgpu.chem_workspace_reserve(mech, n)
     base = chemgpu.make_opts(rtol=wl.RTOL, atol=wl.ATOL, chunk_steps=args.chunk,
-                             block_size=args.block, tail_steps=args.tail)
+                             block_size=args.block, tail_steps=args.tail, scheme=args.scheme)
     stream = torch.cuda.current_stream()
 
     def restore():
@@ -312,7 +315,8 @@ def main():
     cn = np.concatenate([b["counts"].cpu().numpy().reshape(2, -1) for b in boxes], axis=1)
     total_steps = int(cn.sum())
     m = codegen.parse(path)
-    flops_per_launch = total_steps * codegen.step_flops(m)
+    flops_per_step = codegen.step_flops(m, args.scheme)
+    flops_per_launch = total_steps * flops_per_step
 
     # the timed launches: one graph holding the whole batched call
     tboxes = [dict(b, status=None, counts=None) for b in boxes]
@@ -337,7 +341,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed
     achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
-    rec = TRAFFIC.get(args.workload)
+    rec = TRAFFIC.get(args.workload) if args.scheme == "lsrk" else None
     traffic = rec[1] if rec and rec[0] == kernel_digest() else None
     nv = mech.n_species + 1
     out = {
@@ -347,6 +351,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
                    "cells": n, "boxes": len(boxes),
+                   "scheme": args.scheme,
                    "chunk_steps": args.chunk, "block_size": args.block, "tail_steps": args.tail,
                    "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
@@ -359,7 +364,7 @@ def main():
                                 "rejected": int(cn[1].sum()),
                                 "max_per_cell": int(cn.sum(axis=0).max()),
                                 "status_nonzero": int((st != 0).sum())},
-        "flops_per_rk_step": codegen.step_flops(m),
+        "flops_per_rk_step": flops_per_step,
     }
     sub_calls = int(sum(b["state"].shape[1] * b.get("n_sub", 1) for b in hboxes))
     if sub_calls != n:

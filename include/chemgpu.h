@@ -62,6 +62,10 @@ typedef struct {
                             0 = tuned default, < 0 = never.  The hand-off point and that
                             choice depend only on the input, so results do not depend on
                             block_size or chunk_steps */
+    int32_t scheme;      /* 0: the paper's low-storage LSRK4(3)5 two-register scheme (Eq. 21);
+                            1: the full-storage Runge-Kutta-Fehlberg 4(5) comparison scheme
+                            (six stages, all stage vectors kept; same controller with
+                            exponent 1/5; no cooperative tail) */
 } chem_opts;
 
 /*

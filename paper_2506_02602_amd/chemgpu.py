@@ -32,7 +32,8 @@ class chem_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
                 ("chunk_steps", C.c_int32), ("block_size", C.c_int32),
                 ("fixed_steps", C.c_int32),
-                ("tail_steps", C.c_int32)]
+                ("tail_steps", C.c_int32),
+                ("scheme", C.c_int32)]
 
 
 class chem_box(C.Structure):
@@ -97,9 +98,13 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
+SCHEMES = {"lsrk": 0, "rkf45": 1}
+
+
 def make_opts(rtol=0.0, atol=0.0, max_steps=0, chunk_steps=0, block_size=0, fixed_steps=0,
-              tail_steps=0):
-    return chem_opts(rtol, atol, max_steps, chunk_steps, block_size, fixed_steps, tail_steps)
+              tail_steps=0, scheme="lsrk"):
+    return chem_opts(rtol, atol, max_steps, chunk_steps, block_size, fixed_steps, tail_steps,
+                     SCHEMES[scheme] if isinstance(scheme, str) else int(scheme))
 
 
 class Mechanism:

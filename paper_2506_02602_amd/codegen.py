@@ -440,8 +440,13 @@ def rhs_flops(m: dict) -> int:
     return c["flops"] + FLOP_EXP * c["exp"] + FLOP_LOG * c["log"] + FLOP_DIV * c["div"]
 
 
-def step_flops(m: dict) -> int:
+def step_flops(m: dict, scheme: str = "lsrk") -> int:
     """Flops of one LSRK step: 5 RHS + stage updates + WRMS norm + control.
+
+    For the full-storage Fehlberg 4(5) scheme: 6 RHS; stage inputs
+    u + h sum_j a_ij K_j (1, 2, 3, 4, 5 FMA per component for stages 2-6),
+    X and E accumulated with one FMA each per stage, one multiply per
+    coefficient by h; the factor err^(-1/5) through pow.
 
     Stage updates: E, U, X each one FMA per component for stages 1-4, E and X
     for stage 5: 14 FMA = 28 flops per component.  WRMS: weight (FMA), divide,
@@ -449,8 +454,11 @@ def step_flops(m: dict) -> int:
     factor err^(-1/4) (two square roots and a divide), plus 4 scalar flops
     of control."""
     n1 = len(m["species"]) + 1
-    upd = 28 * n1
     wrms = n1 * (2 + FLOP_DIV + 2) + 1 + FLOP_SQRT
+    if scheme == "rkf45":
+        upd = 2 * (1 + 2 + 3 + 4 + 5) * n1 + 2 * 2 * 6 * n1 + 6 * 7
+        return 6 * rhs_flops(m) + upd + wrms + FLOP_LOG + FLOP_EXP + 4
+    upd = 28 * n1
     return 5 * rhs_flops(m) + upd + wrms + 2 * FLOP_SQRT + FLOP_DIV + 4
 
 

@@ -29,7 +29,7 @@
 #include <vector>
 
 #include "chemgpu.h"
-#include "lsrk.hip.h"
+#include "advance.hip.h"
 #include "lsrk_coop.hip.h"
 
 using namespace chemgpu;
@@ -81,6 +81,7 @@ struct PoolArgs {
   int tail_steps;              // > 0: a cell that has taken this many steps moves to the tail
   TailBuf tail;
   int resume;                  // 1: the work items are tail records, resumed one per lane
+  int scheme;                  // SCHEME_LSRK or SCHEME_RKF45
 };
 
 __device__ __forceinline__ int find_box(const PoolArgs& a, int64_t g) {
@@ -130,7 +131,7 @@ __device__ __forceinline__ double initial_h(double h, double dt) {
 }
 
 // ------------------------------------------------------------ direct kernel
-template <class M, int LB>
+template <class M, int LB, int S>
 __global__ __launch_bounds__(LB) void lsrk_direct(PoolArgs a) {
   constexpr int N1 = M::NS + 1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,12 +145,12 @@ __global__ __launch_bounds__(LB) void lsrk_direct(PoolArgs a) {
   } else {
     const double inv_rho = 1.0 / rho;
     if (a.fixed_steps > 0) {
-      advance_fixed<M>(u, rho, inv_rho, bd.dt, a.fixed_steps, h, nacc, a.c);
+      advance_fixed<M, S>(u, rho, inv_rho, bd.dt, a.fixed_steps, h, nacc, a.c);
       st = CELL_OK;
     } else {
       double t = 0.0;
       h = initial_h(h, bd.dt);
-      st = advance<M>(u, rho, inv_rho, bd.dt, t, h, nacc, nrej, a.c, a.c.max_steps);
+      st = advance<M, S>(u, rho, inv_rho, bd.dt, t, h, nacc, nrej, a.c, a.c.max_steps);
     }
   }
   store_cell<M>(bd, i, u, h, st, nacc, nrej);
@@ -178,7 +179,7 @@ __global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
   if (tail_next) *tail_next = 0ull;
 }
 
-template <class M, int LB>
+template <class M, int LB, int S>
 __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   constexpr int N1 = M::NS + 1;
   constexpr int ND = Slots<M>::ND;
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
         } else if (a.fixed_steps > 0) {
           const double inv_rho = 1.0 / rho;
           for (int s = 0; s < bd.n_sub; ++s)
-            advance_fixed<M>(u, rho, inv_rho, bd.dt, a.fixed_steps, h, nacc, a.c);
+            advance_fixed<M, S>(u, rho, inv_rho, bd.dt, a.fixed_steps, h, nacc, a.c);
           nacc = a.fixed_steps * bd.n_sub;
           store_cell<M>(bd, i, u, h, CELL_OK, nacc, 0);
           item = -1;
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
       for (;;) {
         c.max_steps = base + a.c.max_steps;  // per sub-call step budget
         const int before = nacc + nrej;
-        int st = advance<M>(u, rho, inv_rho, bd.dt, t, h, nacc, nrej, c, budget);
+        int st = advance<M, S>(u, rho, inv_rho, bd.dt, t, h, nacc, nrej, c, budget);
         budget -= (nacc + nrej) - before;
         if (st == CELL_RUNNING) break;
         if (st == CELL_OK && sub + 1 < bd.n_sub) {
@@ -462,7 +463,7 @@ struct MechEntry {
   hipError_t (*launch_direct)(const PoolArgs&, int block, hipStream_t);
   hipError_t (*launch_persistent)(const PoolArgs&, int block, int grid, hipStream_t);
   hipError_t (*launch_coop)(const PoolArgs&, int n_cu, hipStream_t);
-  int (*max_blocks_per_cu)(int block);
+  int (*max_blocks_per_cu)(int block, int scheme);
   size_t (*lds_per_lane)();
   hipError_t (*launch_surr_infer)(const surr::InferArgs&, int grid, hipStream_t);
   hipError_t (*launch_make_pairs)(const double*, const double*, long, long, double, const double*,
@@ -471,14 +472,31 @@ struct MechEntry {
 
 // Kernels are instantiated for launch bounds 256 (blocks of 64..256 threads)
 // and 512; the bound caps the registers the compiler may give a lane.
-template <class M>
-hipError_t launch_direct(const PoolArgs& a, int block, hipStream_t s) {
+template <class M, int S>
+hipError_t launch_direct_s(const PoolArgs& a, int block, hipStream_t s) {
   const int64_t grid = (a.one.n + block - 1) / block;
   if (grid == 0) return hipSuccess;
   if (block <= 256)
-    hipLaunchKernelGGL((lsrk_direct<M, 256>), dim3((unsigned)grid), dim3(block), 0, s, a);
+    hipLaunchKernelGGL((lsrk_direct<M, 256, S>), dim3((unsigned)grid), dim3(block), 0, s, a);
   else
-    hipLaunchKernelGGL((lsrk_direct<M, 512>), dim3((unsigned)grid), dim3(block), 0, s, a);
+    hipLaunchKernelGGL((lsrk_direct<M, 512, S>), dim3((unsigned)grid), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class M>
+hipError_t launch_direct(const PoolArgs& a, int block, hipStream_t s) {
+  return a.scheme == SCHEME_RKF45 ? launch_direct_s<M, SCHEME_RKF45>(a, block, s)
+                                  : launch_direct_s<M, SCHEME_LSRK>(a, block, s);
+}
+
+template <class M, int S>
+hipError_t launch_persistent_s(const PoolArgs& a, int block, int grid, hipStream_t s) {
+  if (block <= 256)
+    hipLaunchKernelGGL((lsrk_persistent<M, 256, S>), dim3(grid), dim3(block),
+                       Slots<M>::bytes(block), s, a);
+  else
+    hipLaunchKernelGGL((lsrk_persistent<M, 512, S>), dim3(grid), dim3(block),
+                       Slots<M>::bytes(block), s, a);
   return hipGetLastError();
 }
 
@@ -487,13 +505,8 @@ hipError_t launch_persistent(const PoolArgs& a, int block, int grid, hipStream_t
   hipLaunchKernelGGL(pool_reset, dim3(1), dim3(1), 0, s, a.next,
                      a.tail_steps > 0 ? a.tail.count : nullptr,
                      a.tail_steps > 0 ? a.tail.next : nullptr);
-  if (block <= 256)
-    hipLaunchKernelGGL((lsrk_persistent<M, 256>), dim3(grid), dim3(block),
-                       Slots<M>::bytes(block), s, a);
-  else
-    hipLaunchKernelGGL((lsrk_persistent<M, 512>), dim3(grid), dim3(block),
-                       Slots<M>::bytes(block), s, a);
-  return hipGetLastError();
+  return a.scheme == SCHEME_RKF45 ? launch_persistent_s<M, SCHEME_RKF45>(a, block, grid, s)
+                                  : launch_persistent_s<M, SCHEME_LSRK>(a, block, grid, s);
 }
 
 // The cooperative kernel after the persistent one: enough 256-lane blocks to
@@ -507,18 +520,24 @@ hipError_t launch_coop(const PoolArgs& a, int n_cu, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <class M>
-int max_blocks_per_cu(int block) {
+template <class M, int S>
+int max_blocks_per_cu_s(int block) {
   int nb = 0;
   hipError_t e;
   if (block <= 256)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 256>, block,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 256, S>, block,
                                                      Slots<M>::bytes(block));
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 512>, block,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 512, S>, block,
                                                      Slots<M>::bytes(block));
   if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
+}
+
+template <class M>
+int max_blocks_per_cu(int block, int scheme) {
+  return scheme == SCHEME_RKF45 ? max_blocks_per_cu_s<M, SCHEME_RKF45>(block)
+                                : max_blocks_per_cu_s<M, SCHEME_LSRK>(block);
 }
 
 template <class M>
@@ -575,7 +594,7 @@ struct chem_mech_s {
   const MechEntry* entry;
   TailStore tail;
   struct Tuned { int block, chunk, tail; };
-  std::map<int, Tuned> tuned;  // size bucket -> tuned launch
+  std::map<int, Tuned> tuned;  // (size bucket, scheme) -> tuned launch
   unsigned long long* d_next = nullptr;
   BoxDesc* d_boxes = nullptr;
   BoxDesc* h_boxes = nullptr;      // pinned staging for the box table
@@ -648,6 +667,8 @@ int check_opts(const chem_opts* o) {
   if (!o) return CHEM_OK;
   if (!(o->rtol >= 0) || !(o->atol >= 0) || o->max_steps < 0 || o->fixed_steps < 0)
     return fail(CHEM_EINVAL, "chem_opts: negative or NaN field");
+  if (o->scheme != SCHEME_LSRK && o->scheme != SCHEME_RKF45)
+    return fail(CHEM_EINVAL, "chem_opts.scheme must be 0 (LSRK4(3)5) or 1 (RKF45)");
   if (o->block_size != 0 && (o->block_size % 64 != 0 || o->block_size > 512 || o->block_size < 64))
     return fail(CHEM_EINVAL, "chem_opts.block_size must be a multiple of 64 in [64, 512]");
   return CHEM_OK;
@@ -663,11 +684,17 @@ int size_bucket(int64_t total) {
   return b;
 }
 
+// Tuned launches are kept per (size bucket, scheme).
+int tuned_key(int64_t total, const chem_opts* o) {
+  return size_bucket(total) * 2 + ((o && o->scheme == SCHEME_RKF45) ? 1 : 0);
+}
+
 int pick_tail(chem_mech m, int64_t total, const chem_opts* o) {
   if (o && o->fixed_steps > 0) return 0;
+  if (o && o->scheme != SCHEME_LSRK) return 0;  // the cooperative kernel runs the LSRK scheme
   int t = o ? o->tail_steps : 0;
   if (t == 0) {
-    auto it = m->tuned.find(size_bucket(total));
+    auto it = m->tuned.find(tuned_key(total, o));
     t = (it != m->tuned.end() && it->second.tail != 0) ? it->second.tail : kDefaultTail;
   }
   return t > 0 ? t : 0;
@@ -676,7 +703,7 @@ int pick_tail(chem_mech m, int64_t total, const chem_opts* o) {
 void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int* chunk) {
   *block = (o && o->block_size) ? o->block_size : 0;
   *chunk = (o && o->chunk_steps) ? o->chunk_steps : 0;
-  auto it = m->tuned.find(size_bucket(total));
+  auto it = m->tuned.find(tuned_key(total, o));
   if (it != m->tuned.end()) {
     if (!*block) *block = it->second.block;
     if (!*chunk) *chunk = it->second.chunk;
@@ -685,7 +712,7 @@ void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int
   if (!*chunk) *chunk = kDefaultChunk;
 }
 
-int grid_for(chem_mech m, int block, int64_t total);
+int grid_for(chem_mech m, int block, int64_t total, int scheme);
 
 // At most this many handed-over cells per CU are finished cooperatively; a
 // longer tail list is resumed one cell per lane (several lanes per cell only
@@ -725,13 +752,13 @@ int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
     if (rc) return rc;
     a.tail = m->tail.view();
   }
-  hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total), s);
+  hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s);
   if (e != hipSuccess) return hip_fail(e, "launch integrator kernels");
   return CHEM_OK;
 }
 
-int grid_for(chem_mech m, int block, int64_t total) {
-  const int per_cu = m->entry->max_blocks_per_cu(block);
+int grid_for(chem_mech m, int block, int64_t total, int scheme) {
+  const int per_cu = m->entry->max_blocks_per_cu(block, scheme);
   const int64_t need = (total + block - 1) / block;
   return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * m->n_cu));
 }
@@ -922,6 +949,7 @@ int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, doub
   a.total = n_cells;
   a.c = make_control(opts);
   a.fixed_steps = opts ? opts->fixed_steps : 0;
+  a.scheme = opts ? opts->scheme : SCHEME_LSRK;
   int block, chunk;
   pick_launch(m, n_cells, opts, &block, &chunk);
   if (chunk < 0) {
@@ -961,6 +989,7 @@ int chem_integrate_batched(chem_mech m, const chem_box* boxes, int32_t n_boxes,
   a.total = total;
   a.c = make_control(opts);
   a.fixed_steps = opts ? opts->fixed_steps : 0;
+  a.scheme = opts ? opts->scheme : SCHEME_LSRK;
   return run_pool(m, a, opts, s);
 }
 
@@ -1010,9 +1039,10 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   a.c = make_control(opts);
   a.chunk = chunk > 0 ? chunk : kDefaultChunk;
   a.fixed_steps = opts ? opts->fixed_steps : 0;
+  a.scheme = opts ? opts->scheme : SCHEME_LSRK;
   a.tail_steps = tail_steps;
   if (tail_steps > 0) a.tail = g->tail.view();
-  const int grid = grid_for(m, block, total);
+  const int grid = grid_for(m, block, total, a.scheme);
   hipStream_t cs;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(e, "hipStreamCreate(capture)");
@@ -1060,16 +1090,18 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   if (reps < 1) reps = 3;
   hipStream_t s = (hipStream_t)stream;
   const int bucket = size_bucket(total);
+  const int tkey = tuned_key(total, base);
   char key[160];
-  snprintf(key, sizeof key, "%016llx:%d:%s", (unsigned long long)m->entry->hash, bucket,
-           arch_name(m->device).c_str());
-  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0};
+  snprintf(key, sizeof key, "%016llx:%d:%s%s", (unsigned long long)m->entry->hash, bucket,
+           arch_name(m->device).c_str(),
+           (base && base->scheme == SCHEME_RKF45) ? ":rkf45" : "");
+  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<TuneEntry> cache;
   if (cache_path) {
     cache = read_cache(cache_path);
     for (const auto& en : cache)
       if (en.key == key) {
-        m->tuned[bucket] = {en.block, en.chunk, en.tail};
+        m->tuned[tkey] = {en.block, en.chunk, en.tail};
         if (best) {
           *best = o; best->block_size = en.block; best->chunk_steps = en.chunk;
           best->tail_steps = en.tail;
@@ -1160,7 +1192,7 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   hipEventDestroy(e1);
   cleanup();
   if (rc != CHEM_OK) return rc;
-  m->tuned[bucket] = {best_block, best_chunk, best_tail};
+  m->tuned[tkey] = {best_block, best_chunk, best_tail};
   if (best) {
     *best = o; best->block_size = best_block; best->chunk_steps = best_chunk;
     best->tail_steps = best_tail;

@@ -136,55 +136,6 @@ __device__ __forceinline__ double step_factor(double err) {
   return fac;
 }
 
-// Advance one cell by at most `budget` steps towards dt.  (t, h, nacc, nrej)
-// carry the cell's progress.  Returns CELL_RUNNING or a final CELL_* code.
-template <class M>
-__device__ __forceinline__ int advance(double (&u)[M::NS + 1], double rho, double inv_rho,
-                                       double dt, double& t, double& h, int& nacc, int& nrej,
-                                       const Control& c, int budget) {
-  constexpr int N1 = M::NS + 1;
-#pragma unroll 1
-  for (int s = 0; s < budget; ++s) {
-    bool last = false;
-    double hh = h;
-    if (hh >= dt - t) { hh = dt - t; last = true; }
-    double X[N1];
-    const double err = lsrk_step<M>(u, rho, inv_rho, hh, X, c);
-    const double fac = step_factor(err);
-    if (err <= 1.0) {
-#pragma unroll
-      for (int i = 0; i < N1; ++i) u[i] = X[i];
-      ++nacc;
-      if (last) { h = hh * fac; return CELL_OK; }
-      t = t + hh;
-    } else {
-      ++nrej;
-    }
-    h = hh * fac;
-    if (nacc + nrej >= c.max_steps) return CELL_MAXSTEPS;
-    if (h < 1e-14 * dt) return CELL_H_UNDERFLOW;
-  }
-  return CELL_RUNNING;
-}
-
-// Test mode: exactly n steps of dt/n, every step accepted.
-template <class M>
-__device__ __forceinline__ void advance_fixed(double (&u)[M::NS + 1], double rho, double inv_rho,
-                                              double dt, int n, double& h, int& nacc,
-                                              const Control& c) {
-  constexpr int N1 = M::NS + 1;
-  const double hh = dt / n;
-#pragma unroll 1
-  for (int s = 0; s < n; ++s) {
-    double X[N1];
-    (void)lsrk_step<M>(u, rho, inv_rho, hh, X, c);
-#pragma unroll
-    for (int i = 0; i < N1; ++i) u[i] = X[i];
-  }
-  nacc = n;
-  h = hh;
-}
-
 template <int N1>
 __device__ __forceinline__ bool all_finite(const double (&u)[N1], double rho) {
   bool ok = isfinite(rho);

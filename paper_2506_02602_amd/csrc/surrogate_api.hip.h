@@ -457,6 +457,7 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
       pa.total_dev = s->fb_count;
       pa.c = make_control(opts);
       pa.fixed_steps = opts ? opts->fixed_steps : 0;
+      pa.scheme = opts ? opts->scheme : SCHEME_LSRK;
       rc = run_pool(m, pa, opts, st);
       if (rc) return rc;
     }

@@ -62,7 +62,8 @@ def assert_parity(gmech, omech, s_full, dt, idx=None, max_flag_frac=0.15, label=
     g, gst, gcn = run_gpu(gmech, s_full, dt, **opt)
     sub = np.ascontiguousarray(s_full[:, idx])
     c = sub.copy()
-    kw = {k: v for k, v in opt.items() if k in ("rtol", "atol", "max_steps", "fixed_steps")}
+    kw = {k: v for k, v in opt.items() if k in ("rtol", "atol", "max_steps", "fixed_steps",
+                                                 "scheme")}
     cst, ccn = omech.integrate(c, dt, **kw)
     gsub = np.ascontiguousarray(g[:, idx])
     assert np.array_equal(gst[idx], cst), "per-cell status differs"
@@ -79,7 +80,8 @@ def assert_parity(gmech, omech, s_full, dt, idx=None, max_flag_frac=0.15, label=
         o2 = dict(opt, rtol=1e-11, atol=1e-14, max_steps=2000000)
         g2, _, _ = run_gpu(gmech, tight, dt, **o2)
         c2 = tight.copy()
-        omech.integrate(c2, dt, rtol=1e-11, atol=1e-14, max_steps=2000000)
+        omech.integrate(c2, dt, rtol=1e-11, atol=1e-14, max_steps=2000000,
+                        scheme=opt.get("scheme", "lsrk"))
         tb = parity_violations(g2, c2, ns)
         assert not tb.any(), f"{label}: {tb.sum()} flagged cells still differ at rtol 1e-11"
     frac = bad.mean() if len(bad) else 0.0
