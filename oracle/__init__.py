@@ -62,6 +62,11 @@ def lib():
                                           C.POINTER(I), P, I, C.POINTER(I)]
         L.or_integrate_linear.restype = I
         L.or_rkf45_coeffs.argtypes = [P, P, P]
+        L.or_energy.argtypes = [P, D, P, C.POINTER(D), C.POINTER(D)]
+        L.or_calculate_T.argtypes = [P, P, D, D, C.POINTER(D)]
+        L.or_calculate_T.restype = I
+        L.or_react_conserved.argtypes = [P, P, C.c_int64, C.c_int64, D, D, D, I, P, P]
+        L.or_react_conserved.restype = I
         L.or_integrate_cell_scheme.argtypes = [I] + L.or_integrate_cell.argtypes
         L.or_integrate_cell_scheme.restype = I
         L.or_integrate_scheme.argtypes = [I] + L.or_integrate.argtypes
@@ -169,6 +174,40 @@ class Mech:
                                   float(rtol), float(atol), int(max_steps), int(fixed_steps),
                                   int(nthreads), _ptr(status), _ptr(counts))
         return status, counts
+
+
+def _mech_energy(self, T, Y):
+    """(e [erg/g], c_v [erg/(g K)]) of a mixture."""
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    e, cv = C.c_double(), C.c_double()
+    lib().or_energy(self._h, float(T), _ptr(Y), C.byref(e), C.byref(cv))
+    return e.value, cv.value
+
+
+def _mech_calculate_T(self, Y, e, T0=0.0):
+    """Newton temperature for internal energy e; returns (T, iterations or -1)."""
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    T = C.c_double()
+    it = lib().or_calculate_T(self._h, _ptr(Y), float(e), float(T0), C.byref(T))
+    return T.value, it
+
+
+def _mech_react_conserved(self, cons, dt, rtol=1e-8, atol=1e-10, nthreads=None):
+    """In place on conserved SoA rows (rho, rho u, rho v, rho w, rho E,
+    rho Y_1..rho Y_N, T, h); returns (status, counts[2, n])."""
+    assert cons.dtype == np.float64 and cons.flags.c_contiguous
+    assert cons.shape[0] == self.ns + 7
+    n = cons.shape[1]
+    status = np.zeros(n, dtype=np.int32)
+    counts = np.zeros((2, n), dtype=np.int32)
+    lib().or_react_conserved(self._h, _ptr(cons), n, n, float(dt), float(rtol), float(atol),
+                             int(nthreads or os.cpu_count() or 1), _ptr(status), _ptr(counts))
+    return status, counts
+
+
+Mech.energy = _mech_energy
+Mech.calculate_T = _mech_calculate_T
+Mech.react_conserved = _mech_react_conserved
 
 
 def integrate_linear(A, u0, dt, rtol=1e-8, atol=1e-10, max_steps=100000, fixed_steps=0,

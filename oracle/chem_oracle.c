@@ -573,6 +573,80 @@ int or_integrate(const or_mech *m, double *state, int64_t ld, int64_t n, double 
                                fixed_steps, nthreads, status, counts);
 }
 
+/* ------------------------------------- coupling to the flow (Sec. 2.2.1) */
+/* Mixture internal energy e = sum_k Y_k (h_k - R T / W_k) [erg/g] and
+ * c_v = sum_k Y_k (cp_k - R / W_k) [erg/(g K)] from the NASA-7 fits. */
+void or_energy(const or_mech *m, double T, const double *Y, double *e, double *cv) {
+    int N = m->ns;
+    double cp[64], h[64], sR[64];
+    or_thermo(m, T, cp, h, sR);
+    double se = 0.0, sc = 0.0;
+    for (int k = 0; k < N; k++) {
+        se += Y[k] * (h[k] - 1.0) / m->W[k];
+        sc += Y[k] * (cp[k] - 1.0) / m->W[k];
+    }
+    *e = OR_R_CGS * T * se;
+    *cv = OR_R_CGS * sc;
+}
+
+/* Temperature from conserved quantities: Newton iteration on
+ * e(T, Y) = e_target from T0 (<= 0: 1000 K), T <- T - (e(T) - e_target)/c_v(T),
+ * until |dT| <= 1e-12 T; returns the iterations taken, or -1 if 50 were not
+ * enough or T left (0, inf). */
+int or_calculate_T(const or_mech *m, const double *Y, double e_target, double T0, double *T) {
+    double t = T0 > 0.0 ? T0 : 1000.0;
+    for (int it = 1; it <= 50; it++) {
+        double e, cv;
+        or_energy(m, t, Y, &e, &cv);
+        double dT = (e - e_target) / cv;
+        t -= dT;
+        if (!(t > 0.0) || !isfinite(t)) return -1;
+        if (fabs(dT) <= 1e-12 * t) { *T = t; return it; }
+    }
+    *T = t;
+    return -1;
+}
+
+/* One reaction step of the split scheme on conserved variables (SoA rows:
+ * rho, rho u, rho v, rho w, rho E, rho Y_1..rho Y_N, T, h): T from
+ * e = E - |u|^2/2 by Newton (the T row is the initial guess), the chemistry
+ * ODE over dt at constant rho and e, then rho Y_k and the T and h rows
+ * written back; rho, momentum and rho E are unchanged.  Status 4 marks a
+ * cell whose Newton iteration failed (left unchanged). */
+int or_react_conserved(const or_mech *m, double *cons, int64_t ld, int64_t n, double dt,
+                       double rtol, double atol, int nthreads, int32_t *status, int32_t *counts) {
+    int N = m->ns;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+    for (int64_t i = 0; i < n; i++) {
+        double rho = cons[i];
+        double mu = cons[1 * ld + i], mv = cons[2 * ld + i], mw = cons[3 * ld + i];
+        double E = cons[4 * ld + i] / rho;
+        double e = E - 0.5 * (mu * mu + mv * mv + mw * mw) / (rho * rho);
+        double u[1 + 64];
+        for (int k = 0; k < N; k++) u[1 + k] = cons[(5 + k) * ld + i] / rho;
+        double T;
+        int it = or_calculate_T(m, u + 1, e, cons[(5 + N) * ld + i], &T);
+        int na = 0, nr = 0, st;
+        if (it < 0) {
+            st = 4;
+        } else {
+            u[0] = T;
+            double h = cons[(6 + N) * ld + i];
+            st = or_integrate_cell(m, rho, u, dt, rtol, atol, 100000, 0, &h, &na, &nr, NULL, 0,
+                                   NULL);
+            if (st != OR_NONFINITE) {
+                for (int k = 0; k < N; k++) cons[(5 + k) * ld + i] = rho * u[1 + k];
+                cons[(5 + N) * ld + i] = u[0];
+                cons[(6 + N) * ld + i] = h;
+            }
+        }
+        if (status) status[i] = st;
+        if (counts) { counts[i] = na; counts[n + i] = nr; }
+    }
+    return 0;
+}
+
 /* ---------------------------------------------- linear test problems */
 typedef struct { int n; const double *A; } lin_ctx;
 

@@ -348,3 +348,85 @@ def test_divergence_workload_profile(mech9_path):
     k = {n: i for i, n in enumerate(names)}
     assert X[k["O2"]] / X[k["H2"]] == pytest.approx(2.0, rel=1e-12)
     assert X[k["N2"]] / X[k["H2"]] == pytest.approx(7.0, rel=1e-12)
+
+
+# ------------------------------------------------ split-scheme coupling
+
+def _mixtures(path, n, seed):
+    """Cells with T in [300, 3500] K and random compositions incl. radicals."""
+    names, W = wl.read_species(path)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Y = rng.dirichlet(np.ones(len(names)), size=n).T
+    T = rng.uniform(300.0, 3500.0, n)
+    return T, Y
+
+
+def test_cv_is_the_temperature_derivative_of_e(mech9_path, omech9):
+    T, Y = _mixtures(mech9_path, 20, 51)
+    for t, y in zip(T, Y.T):
+        if abs(t - 1000.0) < 5.0:
+            continue                          # the fits' range change at Tmid
+        e1, _ = omech9.energy(t - 1e-3, y)
+        e2, _ = omech9.energy(t + 1e-3, y)
+        _, cv = omech9.energy(t, y)
+        assert (e2 - e1) / 2e-3 == pytest.approx(cv, rel=1e-7)
+
+
+def test_calculate_T_round_trip(mech9_path, omech9):
+    """Newton recovers the temperature that produced e, from poor guesses."""
+    T, Y = _mixtures(mech9_path, 200, 52)
+    for t, y in zip(T, Y.T):
+        e, _ = omech9.energy(t, y)
+        for t0 in (0.0, 300.0, 3500.0):
+            tt, it = omech9.calculate_T(y, e, t0)
+            assert it > 0 and tt == pytest.approx(t, rel=1e-11)
+
+
+def _conserved(om, path, state, rng):
+    """Conserved rows from a primitive SoA block, with random velocities."""
+    N = om.ns
+    n = state.shape[1]
+    T, Y, rho, h = state[0], state[1:N + 1], state[N + 1], state[N + 2]
+    vel = rng.uniform(-5e4, 5e4, (3, n))                # cm/s
+    e = np.array([om.energy(T[i], Y[:, i])[0] for i in range(n)])
+    cons = np.empty((N + 7, n))
+    cons[0] = rho
+    cons[1:4] = rho * vel
+    cons[4] = rho * (e + 0.5 * (vel ** 2).sum(axis=0))
+    cons[5:5 + N] = rho * Y
+    cons[5 + N] = 1000.0                                 # initial guess only
+    cons[6 + N] = h
+    return np.ascontiguousarray(cons), e
+
+
+def test_react_conserved_is_newton_then_the_chemistry_step(mech9_path, omech9):
+    """The conserved-variable step equals the primitive step from the Newton
+    temperature, keeps rho, momentum and rho E, conserves mass and (to the
+    integration tolerance) internal energy, and does not depend on the flow
+    velocity except through e."""
+    rng = np.random.Generator(np.random.PCG64(53))
+    s, hot = wl.front_2d(mech9_path, nx=128, ny=128, seed=5, band=6)
+    prim = np.ascontiguousarray(s[:, np.where(hot)[0][:60]])
+    cons, e0 = _conserved(omech9, mech9_path, prim, rng)
+    before = cons.copy()
+    st, cn = omech9.react_conserved(cons, wl.DT_FLOW)
+    assert (st == 0).all()
+    ref = prim.copy()
+    rho = before[0]
+    ref[1:10] = before[5:14] / rho                        # the composition the step sees
+    e_in = before[4] / rho - 0.5 * (before[1:4] ** 2).sum(axis=0) / (rho * rho)
+    ref[0] = [omech9.calculate_T(ref[1:10, i], e_in[i], 1000.0)[0] for i in range(60)]
+    rst, rcn = omech9.integrate(ref, wl.DT_FLOW)
+    assert np.array_equal(cons[5:14], rho * ref[1:10])
+    assert np.array_equal(cons[14], ref[0]) and np.array_equal(cn, rcn)
+    assert np.array_equal(cons[:5], before[:5])
+    assert np.allclose(cons[5:14].sum(axis=0), cons[0], rtol=1e-14)
+    e1 = np.array([omech9.energy(cons[14, i], cons[5:14, i] / cons[0, i])[0] for i in range(60)])
+    cv = np.array([omech9.energy(cons[14, i], cons[5:14, i] / cons[0, i])[1] for i in range(60)])
+    assert np.abs((e1 - e0) / cv).max() < 1e-3            # kelvin, integration error only
+    still = before.copy()
+    still[1:4] = 0.0
+    still[4] = cons[0] * e0                               # same e, no motion
+    omech9.react_conserved(still, wl.DT_FLOW)
+    # equal up to the rounding of E - |u|^2/2 carried through one flow step
+    assert np.allclose(still[5:15], cons[5:15], rtol=1e-8, atol=1e-16)
