@@ -43,6 +43,7 @@ extern "C" {
 #define CHEM_CELL_MAXSTEPS 1    /* step budget (accepted + rejected) exhausted before dt */
 #define CHEM_CELL_NONFINITE 2   /* non-finite input; the cell was left unchanged */
 #define CHEM_CELL_H_UNDERFLOW 3 /* step size fell below 1e-14 * dt */
+#define CHEM_CELL_T_NEWTON 4    /* chem_react_conserved: no temperature for the cell's energy */
 
 typedef struct chem_mech_s *chem_mech; /* opaque, owned by the library */
 
@@ -104,6 +105,28 @@ int chem_workspace_reserve(chem_mech m, int64_t max_cells);
  */
 int chem_integrate(chem_mech m, double *state, int64_t ld, int64_t n_cells, double dt,
                    const chem_opts *opts, void *stream, int32_t *status, int32_t *counts);
+
+/*
+ * The reaction step of an operator-split flow solver (paper Sec. 2.2.1: the
+ * Strang split applies this for dt/2, the hydrodynamic step for dt, and
+ * this for dt/2 again), on the flow solver's conserved variables, in place.
+ * Structure of arrays of doubles, cons[v * ld + i], rows:
+ *   0 rho, 1..3 rho u, rho v, rho w, 4 rho E (total energy per volume,
+ *   internal + kinetic, cgs), 5..4+N rho Y_k, 5+N T [K] (in: Newton initial
+ *   guess, <= 0 => 1000 K; out: temperature after the step), 6+N h (step
+ *   hint, as in chem_integrate).
+ * Per cell: Y = rho Y / rho; T from e = E - |u|^2/2 by Newton iteration on
+ * the mixture internal energy of the NASA-7 fits (|dT| <= 1e-12 T within 50
+ * iterations, else status CHEM_CELL_T_NEWTON and the cell is left unchanged);
+ * the chemistry ODE over dt at constant rho and e (as chem_integrate); then
+ * rho Y_k, T and h are written back.  rho, momentum and rho E are not
+ * touched (the step conserves them).  Uses a primitive work state of
+ * (N+3) doubles per cell owned by the mechanism handle (allocated on the
+ * first call that needs more; reserve with chem_workspace_reserve).
+ * status / counts as in chem_integrate.  Enqueued on `stream`.
+ */
+int chem_react_conserved(chem_mech m, double *cons, int64_t ld, int64_t n_cells, double dt,
+                         const chem_opts *opts, void *stream, int32_t *status, int32_t *counts);
 
 /*
  * One AMR box (block-structured patch) of a batched call.  The box's cells

@@ -362,6 +362,27 @@ def chem_autotune(mech: Mechanism, boxes, base: chem_opts | None = None, reps: i
     return best
 
 
+_lib.chem_react_conserved.argtypes = [_P, _P, C.c_int64, C.c_int64, C.c_double,
+                                      C.POINTER(chem_opts), _P, _P, _P]
+
+
+def chem_react_conserved(mech: Mechanism, cons, dt: float, opts: chem_opts | None = None,
+                         status=None, counts=None, stream=None, n_cells: int | None = None):
+    """Reaction step on conserved rows (rho, rho u, rho v, rho w, rho E,
+    rho Y_1..rho Y_N, T, h) of a [N+7, ld] float64 device tensor, in place."""
+    ld = cons.shape[1]
+    n = ld if n_cells is None else int(n_cells)
+    assert cons.dtype.itemsize == 8 and cons.is_contiguous() and cons.shape[0] == mech.n_species + 7
+    if status is not None:
+        assert status.numel() >= n and status.element_size() == 4
+    if counts is not None:
+        assert counts.numel() >= 2 * n and counts.element_size() == 4
+    o = opts if opts is not None else make_opts()
+    _check(_lib.chem_react_conserved(mech.handle, _ptr(cons), ld, n, float(dt), C.byref(o),
+                                     _stream(stream), _ptr(status), _ptr(counts)),
+           "chem_react_conserved")
+
+
 _lib.chem_eval_exp.argtypes = [_P, _P, C.c_int64, _P]
 
 
@@ -382,4 +403,4 @@ def exported_symbols():
             "chem_last_error", "surrogate_create", "surrogate_query", "surrogate_get_params",
             "surrogate_set_params", "surrogate_make_pairs", "surrogate_train", "surrogate_forward",
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
-            "surrogate_free", "chem_eval_exp"]
+            "surrogate_free", "chem_eval_exp", "chem_react_conserved"]

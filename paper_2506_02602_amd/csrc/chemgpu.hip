@@ -449,6 +449,65 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   }
 }
 
+// ------------------------------------------- split-scheme coupling kernels
+// Conserved rows (paper Sec. 2.2.1, the reaction part of the Strang split):
+// rho, rho u, rho v, rho w, rho E, rho Y_1..rho Y_N, T, h.
+constexpr int CELL_T_NEWTON = 4;
+
+// Primitive state for the integrator: Y = rho Y / rho and T from
+// e = E - |u|^2/2 by Newton on e(T, Y) (the T row is the initial guess,
+// <= 0: 1000 K; |dT| <= 1e-12 T within 50 iterations).  A cell whose
+// iteration fails gets T = NaN (the integrator leaves it alone) and flag 1.
+template <class M>
+__global__ void cons_to_prim(const double* __restrict__ cons, int64_t ld, int64_t n,
+                             double* __restrict__ work, int8_t* __restrict__ flag) {
+  constexpr int N = M::NS;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double rho = cons[i];
+  const double mu = cons[ld + i], mv = cons[2 * ld + i], mw = cons[3 * ld + i];
+  const double e_t = cons[4 * ld + i] / rho - 0.5 * (mu * mu + mv * mv + mw * mw) / (rho * rho);
+  double Y[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) Y[k] = cons[(5 + k) * ld + i] / rho;
+  double T = cons[(5 + N) * ld + i];
+  T = T > 0.0 ? T : 1000.0;
+  bool ok = false;
+  for (int it = 0; it < 50; ++it) {
+    double e, cv;
+    M::energy_cv(T, Y, e, cv);
+    const double dT = (e - e_t) / cv;
+    T -= dT;
+    if (!(T > 0.0) || !isfinite(T)) break;
+    if (fabs(dT) <= 1e-12 * T) { ok = true; break; }
+  }
+  work[i] = ok ? T : __builtin_nan("");
+#pragma unroll
+  for (int k = 0; k < N; ++k) work[(1 + k) * n + i] = Y[k];
+  work[(N + 1) * n + i] = rho;
+  work[(N + 2) * n + i] = cons[(6 + N) * ld + i];
+  flag[i] = ok ? 0 : 1;
+}
+
+// Write back rho Y_k, T and h; rho, momentum and rho E are unchanged.
+template <class M>
+__global__ void prim_to_cons(const double* __restrict__ work, const int8_t* __restrict__ flag,
+                             int64_t n, double* __restrict__ cons, int64_t ld,
+                             int32_t* __restrict__ status) {
+  constexpr int N = M::NS;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (flag[i]) {
+    if (status) status[i] = CELL_T_NEWTON;
+    return;
+  }
+  const double rho = cons[i];
+#pragma unroll
+  for (int k = 0; k < N; ++k) cons[(5 + k) * ld + i] = rho * work[(1 + k) * n + i];
+  cons[(5 + N) * ld + i] = work[i];
+  cons[(6 + N) * ld + i] = work[(N + 2) * n + i];
+}
+
 }  // namespace
 
 #include "surrogate_kernels.hip.h"
@@ -463,6 +522,9 @@ struct MechEntry {
   hipError_t (*launch_direct)(const PoolArgs&, int block, hipStream_t);
   hipError_t (*launch_persistent)(const PoolArgs&, int block, int grid, hipStream_t);
   hipError_t (*launch_coop)(const PoolArgs&, int n_cu, hipStream_t);
+  hipError_t (*launch_cons_to_prim)(const double*, int64_t, int64_t, double*, int8_t*, hipStream_t);
+  hipError_t (*launch_prim_to_cons)(const double*, const int8_t*, int64_t, double*, int64_t,
+                                    int32_t*, hipStream_t);
   int (*max_blocks_per_cu)(int block, int scheme);
   size_t (*lds_per_lane)();
   hipError_t (*launch_surr_infer)(const surr::InferArgs&, int grid, hipStream_t);
@@ -520,6 +582,23 @@ hipError_t launch_coop(const PoolArgs& a, int n_cu, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class M>
+hipError_t launch_cons_to_prim(const double* cons, int64_t ld, int64_t n, double* work,
+                               int8_t* flag, hipStream_t s) {
+  const int64_t grid = (n + 255) / 256;
+  hipLaunchKernelGGL(cons_to_prim<M>, dim3((unsigned)grid), dim3(256), 0, s, cons, ld, n, work, flag);
+  return hipGetLastError();
+}
+
+template <class M>
+hipError_t launch_prim_to_cons(const double* work, const int8_t* flag, int64_t n, double* cons,
+                               int64_t ld, int32_t* status, hipStream_t s) {
+  const int64_t grid = (n + 255) / 256;
+  hipLaunchKernelGGL(prim_to_cons<M>, dim3((unsigned)grid), dim3(256), 0, s, work, flag, n, cons,
+                     ld, status);
+  return hipGetLastError();
+}
+
 template <class M, int S>
 int max_blocks_per_cu_s(int block) {
   int nb = 0;
@@ -546,7 +625,7 @@ size_t lds_per_lane() {
 }
 
 #define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, &launch_direct<M>, &launch_persistent<M>, \
-                       &launch_coop<M>, \
+                       &launch_coop<M>, &launch_cons_to_prim<M>, &launch_prim_to_cons<M>, \
                        &max_blocks_per_cu<M>, &lds_per_lane<M>, \
                        &launch_surr_infer<M>, &launch_make_pairs<M>},
 const MechEntry g_registry[] = {CHEM_FOR_EACH_MECH(CHEM_ENTRY)};
@@ -603,6 +682,9 @@ struct chem_mech_s {
   int64_t reserved = 0;
   int device = 0;
   int n_cu = 0;
+  double* d_prim = nullptr;        // primitive work state of chem_react_conserved
+  int8_t* d_flag = nullptr;
+  int64_t prim_cap = 0;
 };
 
 struct chem_graph_s {
@@ -919,6 +1001,8 @@ void chem_mech_free(chem_mech m) {
   if (m->boxes_copied) { hipEventSynchronize(m->boxes_copied); hipEventDestroy(m->boxes_copied); }
   if (m->d_next) hipFree(m->d_next);
   if (m->tail.mem) hipFree(m->tail.mem);
+  if (m->d_prim) hipFree(m->d_prim);
+  if (m->d_flag) hipFree(m->d_flag);
   if (m->d_boxes) hipFree(m->d_boxes);
   if (m->h_boxes) hipHostFree(m->h_boxes);
   delete m;
@@ -958,6 +1042,43 @@ int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, doub
     return CHEM_OK;
   }
   return run_pool(m, a, opts, s);
+}
+
+int chem_react_conserved(chem_mech m, double* cons, int64_t ld, int64_t n_cells, double dt,
+                         const chem_opts* opts, void* stream, int32_t* status, int32_t* counts) {
+  if (!m) return fail(CHEM_EINVAL, "chem_react_conserved: null mechanism");
+  if (n_cells < 0 || ld < n_cells)
+    return fail(CHEM_EINVAL, "chem_react_conserved: need 0 <= n_cells <= ld");
+  if (!(dt > 0) || !std::isfinite(dt))
+    return fail(CHEM_EINVAL, "chem_react_conserved: dt must be finite and > 0");
+  if (n_cells > 0 && !cons) return fail(CHEM_EINVAL, "chem_react_conserved: null state");
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (n_cells == 0) return CHEM_OK;
+  if (n_cells > 0x7fffffff) return fail(CHEM_EINVAL, "more than 2^31-1 cells in one call");
+  hipStream_t s = (hipStream_t)stream;
+  if (n_cells > m->prim_cap) {
+    if (m->d_prim) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(primitive work state)");
+      hipFree(m->d_prim);
+      hipFree(m->d_flag);
+    }
+    m->d_prim = nullptr; m->d_flag = nullptr; m->prim_cap = 0;
+    const int64_t cap = std::max<int64_t>(n_cells, m->reserved);
+    hipError_t e = hipMalloc(&m->d_prim, sizeof(double) * (size_t)cap * (m->entry->ns + 3));
+    if (e != hipSuccess) { m->d_prim = nullptr; return hip_fail(e, "hipMalloc(primitive state)"); }
+    e = hipMalloc(&m->d_flag, (size_t)cap);
+    if (e != hipSuccess) { m->d_flag = nullptr; return hip_fail(e, "hipMalloc(Newton flags)"); }
+    m->prim_cap = cap;
+  }
+  hipError_t e = m->entry->launch_cons_to_prim(cons, ld, n_cells, m->d_prim, m->d_flag, s);
+  if (e != hipSuccess) return hip_fail(e, "launch cons_to_prim");
+  rc = chem_integrate(m, m->d_prim, n_cells, n_cells, dt, opts, stream, status, counts);
+  if (rc) return rc;
+  e = m->entry->launch_prim_to_cons(m->d_prim, m->d_flag, n_cells, cons, ld, status, s);
+  if (e != hipSuccess) return hip_fail(e, "launch prim_to_cons");
+  return CHEM_OK;
 }
 
 int chem_integrate_batched(chem_mech m, const chem_box* boxes, int32_t n_boxes,
