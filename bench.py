@@ -123,8 +123,15 @@ def surrogate_leg(args):
     field, out_mask = sg.inference_field(m)
     n = field.shape[1]
     work = torch.empty_like(field)
+    # one launch configuration for both paths: the autotuner's choice on the
+    # evaluation field itself (the fallback integrates a subset of it)
+    base = cg.make_opts(rtol=wl.RTOL, atol=wl.ATOL)
+    cache = None if args.tune_cache == "none" else args.tune_cache
+    opts = cg.chem_autotune(m, [dict(state=field, dt=wl.DT_FLOW)], base, reps=1, cache_path=cache)
+    log(f"surrogate: launch block {opts.block_size} chunk {opts.chunk_steps} "
+        f"hand-off {opts.tail_steps}")
     ref = field.clone()
-    cg.chem_integrate(m, ref, wl.DT_FLOW)
+    cg.chem_integrate(m, ref, wl.DT_FLOW, opts)
     stream = torch.cuda.current_stream()
     K = max(1, min(args.steps, 5))
 
@@ -143,13 +150,14 @@ def surrogate_leg(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / K, float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
-    t_plain, k_plain = timed(lambda: cg.chem_integrate(m, work, wl.DT_FLOW))
-    t_surr, k_surr = timed(lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True))
+    t_plain, k_plain = timed(lambda: cg.chem_integrate(m, work, wl.DT_FLOW, opts))
+    t_surr, k_surr = timed(lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True,
+                                                      opts=opts))
     t_inf, k_inf = timed(lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=False))
     tc = torch.zeros(n, dtype=torch.int32, device="cuda")
     work.copy_(field)
     n_fb = cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True, trust_code=tc,
-                              want_count=True)
+                              want_count=True, opts=opts)
     ok = tc == 0
     eT, eY = sg.errors(work[:, ok], ref[:, ok], m.n_species)
     idx = torch.randperm(int(ok.sum()), device="cuda")[:2000000]
@@ -164,6 +172,8 @@ def surrogate_leg(args):
         "cells": n,
         "plain_fp64_cells_per_s": n / t_plain, "surrogate_fallback_cells_per_s": n / t_surr,
         "speedup": t_plain / t_surr,
+        "launch": {"block_size": opts.block_size, "chunk_steps": opts.chunk_steps,
+                   "tail_steps": opts.tail_steps},
         "ms_plain": 1e3 * t_plain, "ms_surrogate_fallback": 1e3 * t_surr,
         "ms_inference_only": k_inf,
         "fallback_fraction": n_fb / n,

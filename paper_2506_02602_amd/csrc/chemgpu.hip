@@ -528,6 +528,7 @@ struct MechEntry {
   int (*max_blocks_per_cu)(int block, int scheme);
   size_t (*lds_per_lane)();
   hipError_t (*launch_surr_infer)(const surr::InferArgs&, int grid, hipStream_t);
+  hipError_t (*launch_surr_hull)(const surr::InferArgs&, int8_t*, int32_t*, unsigned*, hipStream_t);
   hipError_t (*launch_make_pairs)(const double*, const double*, long, long, double, const double*,
                                   float*, float*, hipStream_t);
 };
@@ -627,7 +628,7 @@ size_t lds_per_lane() {
 #define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, &launch_direct<M>, &launch_persistent<M>, \
                        &launch_coop<M>, &launch_cons_to_prim<M>, &launch_prim_to_cons<M>, \
                        &max_blocks_per_cu<M>, &lds_per_lane<M>, \
-                       &launch_surr_infer<M>, &launch_make_pairs<M>},
+                       &launch_surr_infer<M>, &launch_surr_hull<M>, &launch_make_pairs<M>},
 const MechEntry g_registry[] = {CHEM_FOR_EACH_MECH(CHEM_ENTRY)};
 #undef CHEM_ENTRY
 
@@ -818,25 +819,32 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
   return m->entry->launch_persistent(r, block, grid, s);
 }
 
-int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
+// The integrator over a work pool with a given pool counter and tail store
+// (calls that may run concurrently on one mechanism each bring their own).
+int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
+                  unsigned long long* next, TailStore& tail) {
   int block, chunk;
   pick_launch(m, a.total, o, &block, &chunk);
   if (m->entry->lds_per_lane() * block > 65536)
     return fail(CHEM_EINVAL, "block_size too large for this mechanism's LDS compaction slots");
   if (a.total > 0x7fffffff) return fail(CHEM_EINVAL, "more than 2^31-1 work items in one call");
-  int rc = ensure_pool(m);
-  if (rc) return rc;
-  a.next = m->d_next;
+  a.next = next;
   a.chunk = chunk > 0 ? chunk : kDefaultChunk;
   a.tail_steps = pick_tail(m, a.total, o);
   if (a.tail_steps > 0) {
-    rc = ensure_tail(m->tail, std::max<int64_t>(a.total, m->reserved));
+    int rc = ensure_tail(tail, std::max<int64_t>(a.total, m->reserved));
     if (rc) return rc;
-    a.tail = m->tail.view();
+    a.tail = tail.view();
   }
   hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s);
   if (e != hipSuccess) return hip_fail(e, "launch integrator kernels");
   return CHEM_OK;
+}
+
+int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
+  int rc = ensure_pool(m);
+  if (rc) return rc;
+  return run_pool_with(m, a, o, s, m->d_next, m->tail);
 }
 
 int grid_for(chem_mech m, int block, int64_t total, int scheme) {

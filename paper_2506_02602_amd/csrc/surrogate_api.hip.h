@@ -23,10 +23,19 @@ struct chem_surr_s {
   float *Z1 = nullptr, *Z2 = nullptr, *Z3 = nullptr, *out = nullptr, *Yb = nullptr, *dZ = nullptr;
   float* part = nullptr;
   double* sse = nullptr;
-  // inference fallback list
+  // inference fallback lists: cells failing the trust test after the network
+  // (fb_list) and cells outside the training hull found before it (hull_list,
+  // integrated on a side stream while the network runs), with the hull flags
   int32_t* fb_list = nullptr;
   unsigned* fb_count = nullptr;
   long fb_cap = 0;
+  int32_t* hull_list = nullptr;
+  unsigned* hull_count = nullptr;
+  int8_t* hull_flag = nullptr;
+  unsigned long long* side_next = nullptr;  // the side stream's pool counter
+  TailStore side_tail;                      // and tail records
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -232,8 +241,13 @@ void surrogate_free(chem_surr s) {
   surr_free_batch(s);
   for (void* p : {(void*)s->theta, (void*)s->m, (void*)s->v, (void*)s->grad, (void*)s->wbf,
                   (void*)s->norm, (void*)s->wpack, (void*)s->bpack, (void*)s->Xn, (void*)s->Yn,
-                  (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count})
+                  (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count, (void*)s->hull_list,
+                  (void*)s->hull_count, (void*)s->hull_flag, (void*)s->side_next,
+                  s->side_tail.mem})
     if (p) hipFree(p);
+  if (s->ev_fork) hipEventDestroy(s->ev_fork);
+  if (s->ev_join) hipEventDestroy(s->ev_join);
+  if (s->side) hipStreamDestroy(s->side);
   delete s;
 }
 
@@ -429,13 +443,26 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (fallback && n_cells > s->fb_cap) {
-    if (s->fb_list) hipFree(s->fb_list);
-    s->fb_list = nullptr;
+    for (void* p : {(void*)s->fb_list, (void*)s->hull_list, (void*)s->hull_flag})
+      if (p) hipFree(p);
+    s->fb_list = nullptr; s->hull_list = nullptr; s->hull_flag = nullptr;
     s->fb_cap = 0;
     if ((e = dalloc(&s->fb_list, n_cells)) != hipSuccess) return hip_fail(e, "hipMalloc(fallback list)");
+    if ((e = dalloc(&s->hull_list, n_cells)) != hipSuccess) return hip_fail(e, "hipMalloc(hull list)");
+    if ((e = dalloc(&s->hull_flag, n_cells)) != hipSuccess) return hip_fail(e, "hipMalloc(hull flags)");
     s->fb_cap = n_cells;
   }
+  if (fallback && !s->side) {
+    if ((e = dalloc(&s->hull_count, 1)) != hipSuccess) return hip_fail(e, "hipMalloc(hull count)");
+    if ((e = dalloc(&s->side_next, 1)) != hipSuccess) return hip_fail(e, "hipMalloc(pool counter)");
+    if ((e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+    if ((e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "hipStreamCreate(side)");
+  }
   hipLaunchKernelGGL(surr::zero_u32, dim3(1), dim3(1), 0, st, s->fb_count);
+  if (fallback) hipLaunchKernelGGL(surr::zero_u32, dim3(1), dim3(1), 0, st, s->hull_count);
   if (n_cells > 0) {
     surr::InferArgs a{};
     a.state = state; a.ld = ld; a.n = n_cells; a.dt = dt;
@@ -445,28 +472,50 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
     a.fb_count = s->fb_count;
     a.trust_code = trust_code;
     a.out_std = out_std;
+    auto fallback_args = [&](const int32_t* list, const unsigned* count) {
+      PoolArgs pa{};
+      pa.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts, list};
+      pa.boxes = nullptr;
+      pa.n_boxes = 1;
+      pa.total = n_cells;
+      pa.total_dev = count;
+      pa.c = make_control(opts);
+      pa.fixed_steps = opts ? opts->fixed_steps : 0;
+      pa.scheme = opts ? opts->scheme : SCHEME_LSRK;
+      return pa;
+    };
+    if (fallback) {
+      // cells outside the hull go to the FP64 integrator on the side stream
+      // while the network runs on the others (disjoint cells of one state)
+      e = m->entry->launch_surr_hull(a, s->hull_flag, s->hull_list, s->hull_count, st);
+      if (e != hipSuccess) return hip_fail(e, "launch surr_hull");
+      a.skip = s->hull_flag;
+      if ((e = hipEventRecord(s->ev_fork, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      if ((e = hipStreamWaitEvent(s->side, s->ev_fork, 0)) != hipSuccess)
+        return hip_fail(e, "hipStreamWaitEvent");
+      PoolArgs ph = fallback_args(s->hull_list, s->hull_count);
+      rc = run_pool_with(m, ph, opts, s->side, s->side_next, s->side_tail);
+      if (rc) return rc;
+      if ((e = hipEventRecord(s->ev_join, s->side)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
     const int grid = std::max(1, std::min<int>((int)((n_cells + 511) / 512), m->n_cu));
     e = m->entry->launch_surr_infer(a, grid, st);
     if (e != hipSuccess) return hip_fail(e, "launch surr_infer");
     if (fallback) {
-      PoolArgs pa{};
-      pa.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts, s->fb_list};
-      pa.boxes = nullptr;
-      pa.n_boxes = 1;
-      pa.total = n_cells;
-      pa.total_dev = s->fb_count;
-      pa.c = make_control(opts);
-      pa.fixed_steps = opts ? opts->fixed_steps : 0;
-      pa.scheme = opts ? opts->scheme : SCHEME_LSRK;
+      PoolArgs pa = fallback_args(s->fb_list, s->fb_count);
       rc = run_pool(m, pa, opts, st);
       if (rc) return rc;
+      if ((e = hipStreamWaitEvent(st, s->ev_join, 0)) != hipSuccess)
+        return hip_fail(e, "hipStreamWaitEvent");
     }
   }
   if (n_fallback_host) {
-    unsigned cnt = 0;
-    hipMemcpyAsync(&cnt, s->fb_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    unsigned cnt[2] = {0, 0};
+    hipMemcpyAsync(&cnt[0], s->fb_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (fallback && n_cells > 0)
+      hipMemcpyAsync(&cnt[1], s->hull_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "surrogate_infer sync");
-    *n_fallback_host = cnt;
+    *n_fallback_host = (int64_t)cnt[0] + cnt[1];
   }
   return CHEM_OK;
 }

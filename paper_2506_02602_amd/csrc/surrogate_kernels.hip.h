@@ -290,6 +290,7 @@ struct InferArgs {
   double hull_margin, elem_tol, pos_tol, energy_tol;
   int32_t* fb_list; unsigned* fb_count;
   int32_t* trust_code; float* out_std;
+  const int8_t* skip;           // NULL, or 1 for cells the hull pass already sent to FP64
 };
 
 enum { TRUST_HULL = 1, TRUST_ELEM = 2, TRUST_POS = 4, TRUST_ENERGY = 8, TRUST_NONFINITE = 16 };
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
   for (long tile = (long)blockIdx.x * S::WAVES + wave; tile < ntiles;
        tile += (long)gridDim.x * S::WAVES) {
     const long cell = tile * 64 + lane;
-    const bool valid = cell < a.n;
+    const bool valid = cell < a.n && !(a.skip && a.skip[cell]);
     int code = 0;
     // ---- stage 0: this lane's cell features (FP64), standardised, BF16 to LDS
     {
@@ -525,6 +526,54 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
   }
 }
 
+// The trust test's first criterion alone, ahead of the network: a cell whose
+// standardised features leave the training hull (with margin), or are not
+// finite, is flagged and queued for the FP64 integrator at once (ballot +
+// one atomic per wave), so that its integration can overlap the inference
+// of the other cells.  Its trust code is TRUST_HULL.
+template <class M>
+__global__ void surr_hull(InferArgs a, int8_t* flag, int32_t* list, unsigned* count) {
+  constexpr int NS = M::NS, NI = NS + 3;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  bool out = false;
+  if (cell < a.n) {
+    const float* mu_in = a.norm;
+    const float* sd_in = a.norm + NI;
+    const float* zmin = a.norm + 2 * NI + 2 * (NS + 1);
+    const float* zmax = zmin + NI;
+    double f[NI];
+    const double T = a.state[cell];
+    double sy = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const double y = a.state[(k + 1) * a.ld + cell];
+      f[3 + k] = y;
+      sy += y * (1.0 / M::W[k]);
+    }
+    const double rho = a.state[(NS + 1) * a.ld + cell];
+    f[0] = T;
+    f[1] = log(rho * 8.31446261815324e7 * T * sy);
+    f[2] = log(a.dt);
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const double z = sd_in[k] > 0.f ? (f[k] - (double)mu_in[k]) / (double)sd_in[k] : 0.0;
+      if (!(z >= (double)zmin[k] - a.hull_margin && z <= (double)zmax[k] + a.hull_margin))
+        out = true;
+    }
+    flag[cell] = out ? 1 : 0;
+    if (out && a.trust_code) a.trust_code[cell] = TRUST_HULL;
+  }
+  const unsigned long long ball = __ballot(out);
+  if (ball) {
+    const int leader = __ffsll((long long)ball) - 1;
+    unsigned base_idx = 0;
+    if (lane == leader) base_idx = atomicAdd(count, (unsigned)__popcll(ball));
+    base_idx = __shfl(base_idx, leader);
+    if (out) list[base_idx + __popcll(ball & ((1ull << lane) - 1ull))] = (int32_t)cell;
+  }
+}
+
 // raw features and increments of (state_before -> state_after) pairs
 template <class M>
 __global__ void make_pairs(const double* before, const double* after, long ld, long n, double dt,
@@ -561,6 +610,15 @@ hipError_t launch_surr_infer(const surr::InferArgs& a, int grid, hipStream_t s) 
     attr = true;
   }
   hipLaunchKernelGGL(surr::surr_infer<M>, dim3(grid), dim3(S::THREADS), S::BYTES, s, a);
+  return hipGetLastError();
+}
+
+template <class M>
+hipError_t launch_surr_hull(const surr::InferArgs& a, int8_t* flag, int32_t* list, unsigned* count,
+                            hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(surr::surr_hull<M>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a,
+                     flag, list, count);
   return hipGetLastError();
 }
 
