@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--tail", type=int, default=0,
                     help="steps after which a cell moves to the cooperative kernel "
                          "(0 = default, < 0 = never)")
+    ap.add_argument("--tail-cap", type=int, default=0,
+                    help="most handed-over cells per CU the cooperative kernel takes "
+                         "(0 = default, < 0 = no limit)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--workload", default="front",
@@ -299,7 +302,8 @@ def main():
     mech = chemgpu.chem_mech_load(path)
     chemgpu.chem_workspace_reserve(mech, n)
     base = chemgpu.make_opts(rtol=wl.RTOL, atol=wl.ATOL, chunk_steps=args.chunk,
-                             block_size=args.block, tail_steps=args.tail, scheme=args.scheme)
+                             block_size=args.block, tail_steps=args.tail, scheme=args.scheme,
+                             tail_cap=args.tail_cap)
     stream = torch.cuda.current_stream()
 
     def restore():
@@ -315,7 +319,7 @@ def main():
         tb = chemgpu.chem_autotune(mech, boxes, base, reps=3 if n <= 2_000_000 else 1,
                                    cache_path=cache)
         tuned = {"block_size": tb.block_size, "chunk_steps": tb.chunk_steps,
-                 "tail_steps": tb.tail_steps}
+                 "tail_steps": tb.tail_steps, "tail_cap": tb.tail_cap}
     log(f"launch {tuned}; untimed pass with per-cell counters")
     # one untimed pass with per-cell counters for the flop count
     restore()
@@ -363,6 +367,7 @@ def main():
                    "cells": n, "boxes": len(boxes),
                    "scheme": args.scheme,
                    "chunk_steps": args.chunk, "block_size": args.block, "tail_steps": args.tail,
+                   "tail_cap": args.tail_cap,
                    "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,

@@ -57,16 +57,18 @@ typedef struct {
     int32_t block_size;  /* threads per block, multiple of 64 up to 512 (0 = tuned default) */
     int32_t fixed_steps; /* > 0: test mode, exactly this many steps of dt/fixed_steps, no control */
     int32_t tail_steps;  /* a cell still stepping after this many steps (accepted + rejected,
-                            over all sub-calls) is handed over; if at most 64 cells per CU
-                            are handed over they are finished by the cooperative kernel,
-                            several lanes per cell, otherwise one cell per lane as before.
-                            0 = tuned default, < 0 = never.  The hand-off point and that
-                            choice depend only on the input, so results do not depend on
-                            block_size or chunk_steps */
+                            over all sub-calls) is handed over; if at most tail_cap cells
+                            per CU are handed over they are finished by the cooperative
+                            kernel, several lanes per cell, otherwise one cell per lane as
+                            before.  0 = tuned default, < 0 = never.  The hand-off point and
+                            that choice depend only on the input, so results do not depend
+                            on block_size or chunk_steps */
     int32_t scheme;      /* 0: the paper's low-storage LSRK4(3)5 two-register scheme (Eq. 21);
                             1: the full-storage Runge-Kutta-Fehlberg 4(5) comparison scheme
                             (six stages, all stage vectors kept; same controller with
                             exponent 1/5; no cooperative tail) */
+    int32_t tail_cap;    /* most handed-over cells per CU that the cooperative kernel takes
+                            (see tail_steps): 0 = tuned default, else 64; < 0 = no limit */
 } chem_opts;
 
 /*
@@ -185,13 +187,15 @@ void chem_graph_destroy(chem_graph g);
  * default block, then block in {64, 128, 192, 256, 384, 512} (those that fit
  * the LDS compaction slots) at the best chunk, chunk again at the best
  * block, then, if base->tail_steps is 0, tail_steps in {8, 16, 32, 64, 128,
- * 256, 512, never} for the best pair.  Each candidate is timed with HIP events on
+ * 256, 512, never} for the best pair, and, if base->tail_cap is 0 too, the
+ * pairs of tail_steps in {8, 16, 32, 64} and tail_cap in {64, 128, 256, no
+ * limit}.  Each candidate is timed with HIP events on
  * `stream` (median of `reps` launches after one untimed launch) on the
  * caller's boxes; the boxes' states are snapshotted first and restored
  * after every trial and at the end, so the caller's data is left unchanged.  The
  * winner is stored in the handle for the size bucket of these boxes (total
  * cells rounded to a power of two): later calls whose chunk_steps,
- * block_size or tail_steps are 0 use it.  If cache_path
+ * block_size, tail_steps or tail_cap are 0 use it.  If cache_path
  * is not NULL the result is also looked up in / written to that JSON file,
  * keyed by mechanism hash, size bucket and GPU architecture name; a cache hit
  * skips the sweep.  best (may be NULL) receives the chosen options.

@@ -33,7 +33,8 @@ class chem_opts(C.Structure):
                 ("chunk_steps", C.c_int32), ("block_size", C.c_int32),
                 ("fixed_steps", C.c_int32),
                 ("tail_steps", C.c_int32),
-                ("scheme", C.c_int32)]
+                ("scheme", C.c_int32),
+                ("tail_cap", C.c_int32)]
 
 
 class chem_box(C.Structure):
@@ -102,9 +103,9 @@ SCHEMES = {"lsrk": 0, "rkf45": 1}
 
 
 def make_opts(rtol=0.0, atol=0.0, max_steps=0, chunk_steps=0, block_size=0, fixed_steps=0,
-              tail_steps=0, scheme="lsrk"):
+              tail_steps=0, scheme="lsrk", tail_cap=0):
     return chem_opts(rtol, atol, max_steps, chunk_steps, block_size, fixed_steps, tail_steps,
-                     SCHEMES[scheme] if isinstance(scheme, str) else int(scheme))
+                     SCHEMES[scheme] if isinstance(scheme, str) else int(scheme), tail_cap)
 
 
 class Mechanism:

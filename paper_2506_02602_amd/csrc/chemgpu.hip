@@ -61,6 +61,8 @@ struct TailBuf {
   int32_t* nrej;
   int32_t* sub;           // current sub-call
   int32_t* base;          // steps taken before the current sub-call
+  int32_t* key;           // bucket of the cell's estimated remaining steps (tail_key)
+  int32_t* order;         // record indices, largest key first (tail_order)
   unsigned int* count;    // records written (zeroed before launch)
   unsigned long long* next;  // records claimed by whichever kernel finishes them (zeroed)
   int cap;                // at most this many records go to the cooperative kernel; more
@@ -179,6 +181,48 @@ __global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
   if (tail_next) *tail_next = 0ull;
 }
 
+// Order of the tail list.  The cooperative kernel's groups claim handed-over
+// cells one after another, so the flow step ends when the group that claimed
+// the longest remaining integration finishes it; claiming the longest first
+// (the longest-processing-time rule of list scheduling) keeps a long cell
+// from starting late.  A cell's remaining work is estimated from its state at
+// the hand-off, in its current step size: rem/h steps for the time rem left
+// in its flow step (all remaining sub-calls); the key buckets that estimate
+// four to an octave, 0 for fewer than two steps, up to kTailBuckets - 1.
+constexpr int kTailBuckets = 64;
+
+__device__ __forceinline__ int32_t tail_key(double rem, double h) {
+  const double est = rem / h;
+  if (!(est > 1.0)) return 0;
+  const double k = 4.0 * log2(est);
+  return k >= (double)(kTailBuckets - 1) ? kTailBuckets - 1 : (int32_t)k;
+}
+
+// Counting sort of the records by key, largest first, into tb.order (one
+// block).  Cells with equal keys keep no particular order: each cell's
+// integration does not depend on when or by which group it runs.  Does
+// nothing when the list is empty or is resumed one cell per lane.
+__global__ __launch_bounds__(1024) void tail_order(TailBuf tb) {
+  __shared__ unsigned int off[kTailBuckets];
+  const unsigned int count = *tb.count;
+  if (count == 0u || count > (unsigned int)tb.cap) return;
+  for (int k = threadIdx.x; k < kTailBuckets; k += blockDim.x) off[k] = 0u;
+  __syncthreads();
+  for (unsigned int r = threadIdx.x; r < count; r += blockDim.x) atomicAdd(&off[tb.key[r]], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int run = 0u;
+    for (int k = kTailBuckets - 1; k >= 0; --k) {
+      const unsigned int c = off[k];
+      off[k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (unsigned int r = threadIdx.x; r < count; r += blockDim.x)
+    tb.order[atomicAdd(&off[tb.key[r]], 1u)] = (int32_t)r;
+}
+
 template <class M, int LB, int S>
 __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   constexpr int N1 = M::NS + 1;
@@ -289,6 +333,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
         a.tail.nrej[r] = nrej;
         a.tail.sub[r] = sub;
         a.tail.base[r] = base;
+        a.tail.key[r] = tail_key((bd.n_sub - sub) * bd.dt - t, h);
         item = -1;
       }
     }
@@ -411,6 +456,7 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
       if (gl == 0) r = (unsigned int)atomicAdd(a.tail.next, 1ull);
       r = __shfl(r, 0, G);
       if (r >= count) break;
+      r = (unsigned int)a.tail.order[r];
       const int64_t item = a.tail.item[r];
       {
         const BoxDesc& bd = box_ref(a, find_box(a, item));
@@ -656,7 +702,8 @@ uint64_t fnv1a64(const std::vector<char>& d) {
 struct TailStore {
   void* mem = nullptr;
   int64_t cap = 0;
-  // [next u64][count u32][pad][t: cap doubles][item, nacc, nrej, sub, base: cap int32 each]
+  // [next u64][count u32][pad][t: cap doubles]
+  // [item, nacc, nrej, sub, base, key, order: cap int32 each]
   TailBuf view() const {
     TailBuf b{};
     char* p = static_cast<char*>(mem);
@@ -665,15 +712,16 @@ struct TailStore {
     b.t = reinterpret_cast<double*>(p + 16);
     int32_t* q = reinterpret_cast<int32_t*>(p + 16 + sizeof(double) * cap);
     b.item = q; b.nacc = q + cap; b.nrej = q + 2 * cap; b.sub = q + 3 * cap; b.base = q + 4 * cap;
+    b.key = q + 5 * cap; b.order = q + 6 * cap;
     return b;
   }
-  static size_t bytes(int64_t cap) { return 16 + (size_t)cap * (sizeof(double) + 5 * sizeof(int32_t)); }
+  static size_t bytes(int64_t cap) { return 16 + (size_t)cap * (sizeof(double) + 7 * sizeof(int32_t)); }
 };
 
 struct chem_mech_s {
   const MechEntry* entry;
   TailStore tail;
-  struct Tuned { int block, chunk, tail; };
+  struct Tuned { int block, chunk, tail, cap; };
   std::map<int, Tuned> tuned;  // (size bucket, scheme) -> tuned launch
   unsigned long long* d_next = nullptr;
   BoxDesc* d_boxes = nullptr;
@@ -783,6 +831,19 @@ int pick_tail(chem_mech m, int64_t total, const chem_opts* o) {
   return t > 0 ? t : 0;
 }
 
+constexpr int kDefaultTailCap = 64;
+
+// Most handed-over cells the cooperative kernel takes, over the whole chip.
+int pick_cap(chem_mech m, int64_t total, const chem_opts* o) {
+  int c = o ? o->tail_cap : 0;
+  if (c == 0) {
+    auto it = m->tuned.find(tuned_key(total, o));
+    c = (it != m->tuned.end() && it->second.cap != 0) ? it->second.cap : kDefaultTailCap;
+  }
+  if (c < 0) return INT32_MAX;
+  return (int)std::min<int64_t>((int64_t)c * m->n_cu, INT32_MAX);
+}
+
 void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int* chunk) {
   *block = (o && o->block_size) ? o->block_size : 0;
   *chunk = (o && o->chunk_steps) ? o->chunk_steps : 0;
@@ -797,18 +858,16 @@ void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int
 
 int grid_for(chem_mech m, int block, int64_t total, int scheme);
 
-// At most this many handed-over cells per CU are finished cooperatively; a
-// longer tail list is resumed one cell per lane (several lanes per cell only
-// pay while the tail is short next to the chip).
-constexpr int kTailCellsPerCU = 64;
-
 // The flow step's launches: pool reset + persistent kernel, then, with a
-// hand-off point, the cooperative kernel and the per-lane resumption of the
-// tail list (exactly one of the two does work, chosen by the list's length).
+// hand-off point, the ordering of the tail list, the cooperative kernel and
+// the per-lane resumption of the list (exactly one of the last two does
+// work, chosen by the list's length against a.tail.cap: several lanes per
+// cell only pay while the tail is short next to the chip).
 hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_t s) {
-  if (a.tail_steps > 0) a.tail.cap = kTailCellsPerCU * m->n_cu;
   hipError_t e = m->entry->launch_persistent(a, block, grid, s);
   if (e != hipSuccess || a.tail_steps <= 0) return e;
+  hipLaunchKernelGGL(tail_order, dim3(1), dim3(1024), 0, s, a.tail);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   e = m->entry->launch_coop(a, m->n_cu, s);
   if (e != hipSuccess) return e;
   PoolArgs r = a;
@@ -835,6 +894,7 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
     int rc = ensure_tail(tail, std::max<int64_t>(a.total, m->reserved));
     if (rc) return rc;
     a.tail = tail.view();
+    a.tail.cap = pick_cap(m, a.total, o);
   }
   hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s);
   if (e != hipSuccess) return hip_fail(e, "launch integrator kernels");
@@ -886,7 +946,7 @@ std::string arch_name(int device) {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-struct TuneEntry { std::string key; int block, chunk, tail; double ms; };
+struct TuneEntry { std::string key; int block, chunk, tail, cap; double ms; };
 
 std::vector<TuneEntry> read_cache(const char* path) {
   std::vector<TuneEntry> v;
@@ -903,14 +963,15 @@ std::vector<TuneEntry> read_cache(const char* path) {
     pos += tag.size();
     const size_t end = txt.find('"', pos);
     if (end == std::string::npos) break;
-    TuneEntry e{txt.substr(pos, end - pos), 0, 0, 0, 0.0};
+    TuneEntry e{txt.substr(pos, end - pos), 0, 0, 0, 0, 0.0};
     const size_t close = txt.find('}', end);
     const std::string rec = txt.substr(end, close == std::string::npos ? std::string::npos : close - end);
     const size_t pb = rec.find("\"block\":"), pc = rec.find("\"chunk\":"), pm = rec.find("\"ms\":");
-    const size_t pt = rec.find("\"tail\":");
+    const size_t pt = rec.find("\"tail\":"), pk = rec.find("\"cap\":");
     if (pb != std::string::npos) e.block = atoi(rec.c_str() + pb + 8);
     if (pc != std::string::npos) e.chunk = atoi(rec.c_str() + pc + 8);
     if (pt != std::string::npos) e.tail = atoi(rec.c_str() + pt + 7);
+    if (pk != std::string::npos) e.cap = atoi(rec.c_str() + pk + 6);
     if (pm != std::string::npos) e.ms = atof(rec.c_str() + pm + 5);
     if (e.block > 0 && e.chunk != 0) v.push_back(e);
     pos = end;
@@ -924,8 +985,10 @@ int write_cache(const char* path, const std::vector<TuneEntry>& v) {
   if (!f) return fail(CHEM_EINVAL, std::string("cannot write ") + path);
   fprintf(f, "{\"version\": 1, \"entries\": [\n");
   for (size_t i = 0; i < v.size(); ++i)
-    fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"chunk\": %d, \"tail\": %d, \"ms\": %.6f}%s\n",
-            v[i].key.c_str(), v[i].block, v[i].chunk, v[i].tail, v[i].ms,
+    fprintf(f,
+            "  {\"key\": \"%s\", \"block\": %d, \"chunk\": %d, \"tail\": %d, \"cap\": %d, "
+            "\"ms\": %.6f}%s\n",
+            v[i].key.c_str(), v[i].block, v[i].chunk, v[i].tail, v[i].cap, v[i].ms,
             i + 1 < v.size() ? "," : "");
   fprintf(f, "]}\n");
   fclose(f);
@@ -1170,7 +1233,10 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   a.fixed_steps = opts ? opts->fixed_steps : 0;
   a.scheme = opts ? opts->scheme : SCHEME_LSRK;
   a.tail_steps = tail_steps;
-  if (tail_steps > 0) a.tail = g->tail.view();
+  if (tail_steps > 0) {
+    a.tail = g->tail.view();
+    a.tail.cap = pick_cap(m, total, opts);
+  }
   const int grid = grid_for(m, block, total, a.scheme);
   hipStream_t cs;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -1224,16 +1290,16 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   snprintf(key, sizeof key, "%016llx:%d:%s%s", (unsigned long long)m->entry->hash, bucket,
            arch_name(m->device).c_str(),
            (base && base->scheme == SCHEME_RKF45) ? ":rkf45" : "");
-  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0, 0};
+  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<TuneEntry> cache;
   if (cache_path) {
     cache = read_cache(cache_path);
     for (const auto& en : cache)
       if (en.key == key) {
-        m->tuned[tkey] = {en.block, en.chunk, en.tail};
+        m->tuned[tkey] = {en.block, en.chunk, en.tail, en.cap};
         if (best) {
           *best = o; best->block_size = en.block; best->chunk_steps = en.chunk;
-          best->tail_steps = en.tail;
+          best->tail_steps = en.tail; best->tail_cap = en.cap;
         }
         return CHEM_OK;
       }
@@ -1280,40 +1346,56 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   };
   // Coordinate descent: chunk at the default block, block at the best
   // chunk, chunk again at the best block, then the hand-off point for the
-  // best pair (each sweep keeps the incumbent unless a candidate is faster).
+  // best pair, then hand-off point and cooperative cap together (an early
+  // hand-off only pays when the cap lets the cooperative kernel take the
+  // longer list).  Each sweep keeps the incumbent unless a candidate is
+  // faster.
   const int blocks[] = {64, 128, 192, 256, 384, 512};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
   const int tails[] = {8, 16, 32, 64, 128, 256, 512, -1};
+  const int pair_tails[] = {8, 16, 32, 64};
+  const int caps[] = {kDefaultTailCap, 128, 256, -1};
   double best_ms = 1e300;
   int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
   int best_tail = o.tail_steps != 0 ? o.tail_steps : kDefaultTail;
-  const bool tune_tail = o.tail_steps == 0 && o.fixed_steps == 0;
-  auto consider = [&](int b, int c, int tl) -> int {
+  int best_cap = o.tail_cap != 0 ? o.tail_cap : kDefaultTailCap;
+  const bool tune_tail = o.tail_steps == 0 && o.fixed_steps == 0 && o.scheme == SCHEME_LSRK;
+  const bool tune_cap = tune_tail && o.tail_cap == 0;
+  auto consider = [&](int b, int c, int tl, int cap) -> int {
     if (m->entry->lds_per_lane() * b > 65536) return CHEM_OK;
     chem_opts t = o;
     t.block_size = b;
     t.chunk_steps = c;
     t.tail_steps = tl;
+    t.tail_cap = cap;
     double med = 0;
     const int trc = trial(t, &med);
     if (trc != CHEM_OK) return trc;
-    if (med < best_ms) { best_ms = med; best_block = b; best_chunk = c; best_tail = tl; }
+    if (med < best_ms) {
+      best_ms = med; best_block = b; best_chunk = c; best_tail = tl; best_cap = cap;
+    }
     return CHEM_OK;
   };
   rc = CHEM_OK;
   for (int c : chunks)
-    if (rc == CHEM_OK) rc = consider(best_block, c, best_tail);
+    if (rc == CHEM_OK) rc = consider(best_block, c, best_tail, best_cap);
   for (int b : blocks)
-    if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail);
+    if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail, best_cap);
   {
     const int b0 = best_block;
     for (int c : chunks)
-      if (rc == CHEM_OK && c != best_chunk) rc = consider(b0, c, best_tail);
+      if (rc == CHEM_OK && c != best_chunk) rc = consider(b0, c, best_tail, best_cap);
   }
   if (tune_tail) {
     const int b0 = best_block, c0 = best_chunk, t0 = best_tail;
     for (int tl : tails)
-      if (rc == CHEM_OK && tl != t0) rc = consider(b0, c0, tl);
+      if (rc == CHEM_OK && tl != t0) rc = consider(b0, c0, tl, best_cap);
+  }
+  if (tune_cap) {
+    const int b0 = best_block, c0 = best_chunk, t0 = best_tail, k0 = best_cap;
+    for (int tl : pair_tails)
+      for (int cap : caps)
+        if (rc == CHEM_OK && !(tl == t0 && cap == k0)) rc = consider(b0, c0, tl, cap);
   }
   if ((e = restore()) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "restore");
   hipStreamSynchronize(s);
@@ -1321,13 +1403,13 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   hipEventDestroy(e1);
   cleanup();
   if (rc != CHEM_OK) return rc;
-  m->tuned[tkey] = {best_block, best_chunk, best_tail};
+  m->tuned[tkey] = {best_block, best_chunk, best_tail, best_cap};
   if (best) {
     *best = o; best->block_size = best_block; best->chunk_steps = best_chunk;
-    best->tail_steps = best_tail;
+    best->tail_steps = best_tail; best->tail_cap = best_cap;
   }
   if (cache_path) {
-    cache.push_back(TuneEntry{key, best_block, best_chunk, best_tail, best_ms});
+    cache.push_back(TuneEntry{key, best_block, best_chunk, best_tail, best_cap, best_ms});
     rc = write_cache(cache_path, cache);
   }
   return rc;

@@ -218,15 +218,30 @@ def test_tail_cells_match_oracle(gmech9, omech9, mech9_path, tail):
                   max_flag_frac=0.02, tail_steps=tail)
 
 
-def test_long_tail_list_resumes_per_lane(gmech9, mech9_path):
-    """More handed-over cells than the cooperative kernel takes (64 per CU):
-    the list is resumed one cell per lane, bitwise the result of never
-    handing over."""
+@pytest.mark.parametrize("cap", [0, 1])
+def test_long_tail_list_resumes_per_lane(gmech9, mech9_path, cap):
+    """More handed-over cells than the cooperative kernel takes (default 64
+    per CU, or 1): the list is resumed one cell per lane, bitwise the result
+    of never handing over."""
     s0, hot = wl.front_2d(mech9_path, nx=1024, ny=1024, seed=37)
     s1 = np.ascontiguousarray(np.tile(s0[:, hot], (1, 2)))       # ~42,000 stiff cells
     ref, rst, rcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=-1)
-    g, gst, gcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=1)
+    g, gst, gcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=1, tail_cap=cap)
     assert np.array_equal(g, ref) and np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
+
+
+def test_long_tail_list_without_cap(gmech9, omech9, mech9_path):
+    """With no cap the cooperative kernel takes a list of ~42,000 cells (far
+    more than the groups resident on the chip, so groups claim cell after
+    cell): every cell is finished, and a seeded sample matches the oracle."""
+    s0, hot = wl.front_2d(mech9_path, nx=1024, ny=1024, seed=37)
+    s1 = np.ascontiguousarray(np.tile(s0[:, hot], (1, 2)))
+    g, gst, gcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=1, tail_cap=-1)
+    assert (gst == 0).all() and (gcn[0] >= 1).all()
+    rng = np.random.Generator(np.random.PCG64(38))
+    idx = rng.choice(s1.shape[1], 1500, replace=False)
+    assert_parity(gmech9, omech9, s1, wl.DT_FLOW, idx=idx, label="tail list without cap",
+                  max_flag_frac=0.02, tail_steps=1, tail_cap=-1)
 
 
 def test_tail_mech32(gmech32, omech32, mech32_path):
