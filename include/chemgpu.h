@@ -309,6 +309,21 @@ const char *chem_last_error(void);
  * can be checked against a reference.  Enqueued on `stream`. */
 int chem_eval_exp(const double *x, double *y, int64_t n, void *stream);
 
+/* Diagnostics for every elementary function the integrators use in place of
+ * the library's: y[i] = fn(x[i]) for i < n (device arrays, caller-owned),
+ * enqueued on `stream`.  fn is one of
+ *   CHEM_MATH_EXP_CW      the per-lane rate exponential (as chem_eval_exp);
+ *   CHEM_MATH_EXP_ESTRIN  the cooperative kernel's exponential (same
+ *                         reduction, Estrin-form polynomial; within 1 ulp);
+ *   CHEM_MATH_LOG_ATANH   the logarithm of ln T (reduction to [sqrt(1/2),
+ *                         sqrt(2)) and the atanh series; within 1 ulp for
+ *                         finite x > 0, NaN otherwise).
+ * CHEM_EINVAL for an unknown fn, n < 0 or a null array with n > 0. */
+#define CHEM_MATH_EXP_CW 0
+#define CHEM_MATH_EXP_ESTRIN 1
+#define CHEM_MATH_LOG_ATANH 2
+int chem_eval_math(int32_t fn, const double *x, double *y, int64_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -396,6 +396,21 @@ def chem_eval_exp(x, stream=None):
     return y
 
 
+_lib.chem_eval_math.restype = C.c_int
+_lib.chem_eval_math.argtypes = [C.c_int32, _P, _P, C.c_int64, _P]
+MATH_FNS = {"exp_cw": 0, "exp_estrin": 1, "log_atanh": 2}
+
+
+def chem_eval_math(fn, x, stream=None):
+    """fn(x) on the device with one of the integrators' own elementary
+    functions ("exp_cw", "exp_estrin", "log_atanh")."""
+    import torch
+    y = torch.empty_like(x)
+    _check(_lib.chem_eval_math(MATH_FNS[fn], x.data_ptr(), y.data_ptr(), x.numel(),
+                               _stream(stream)), "chem_eval_math")
+    return y
+
+
 def exported_symbols():
     """Names declared in include/chemgpu.h that this library must export."""
     return ["chem_mech_load", "chem_mech_query", "chem_mech_free", "chem_workspace_reserve",
@@ -404,4 +419,4 @@ def exported_symbols():
             "chem_last_error", "surrogate_create", "surrogate_query", "surrogate_get_params",
             "surrogate_set_params", "surrogate_make_pairs", "surrogate_train", "surrogate_forward",
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
-            "surrogate_free", "chem_eval_exp", "chem_react_conserved"]
+            "surrogate_free", "chem_eval_exp", "chem_eval_math", "chem_react_conserved"]

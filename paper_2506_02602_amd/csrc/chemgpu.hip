@@ -169,9 +169,11 @@ struct Slots {
   static size_t bytes(int block) { return (size_t)block * (ND * sizeof(double) + NI * sizeof(int)); }
 };
 
-__global__ void eval_exp_kernel(const double* x, double* y, int64_t n) {
+__global__ void eval_math_kernel(int fn, const double* x, double* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = exp_cw(x[i]);
+  if (i >= n) return;
+  const double v = x[i];
+  y[i] = fn == CHEM_MATH_EXP_ESTRIN ? exp_estrin(v) : fn == CHEM_MATH_LOG_ATANH ? log_atanh(v) : exp_cw(v);
 }
 
 __global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
@@ -429,10 +431,11 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   for (int i = tid; i < C::ND; i += blockDim.x) D[i] = C::dtab()[i];
   for (int i = tid; i < C::NI; i += blockDim.x) I[i] = C::itab()[i];
   const int gl = tid % G;
-  double* sgrp = scr + (tid / G) * CoopScratch<M>::SIZE;
+  using S = CoopScratch<M>;
+  double* sgrp = scr + (tid / G) * S::SIZE;
   if (gl == 0) {
-    sgrp[CoopScratch<M>::SC + N] = 1.0;
-    sgrp[CoopScratch<M>::SG + N] = 0.0;
+    sgrp[S::SC + N] = 1.0;
+    sgrp[S::SG + N] = 0.0;
   }
   __syncthreads();
   const CoopCtx<M> x{D, I, sgrp, gl};
@@ -1015,15 +1018,21 @@ const char* chem_strerror(int code) {
 
 const char* chem_last_error(void) { return g_err.c_str(); }
 
-int chem_eval_exp(const double* x, double* y, int64_t n, void* stream) {
-  if (n < 0 || (n > 0 && (!x || !y))) return fail(CHEM_EINVAL, "chem_eval_exp: bad argument");
+int chem_eval_math(int32_t fn, const double* x, double* y, int64_t n, void* stream) {
+  if (fn != CHEM_MATH_EXP_CW && fn != CHEM_MATH_EXP_ESTRIN && fn != CHEM_MATH_LOG_ATANH)
+    return fail(CHEM_EINVAL, "chem_eval_math: unknown function");
+  if (n < 0 || (n > 0 && (!x || !y))) return fail(CHEM_EINVAL, "chem_eval_math: bad argument");
   if (n == 0) return CHEM_OK;
   const int64_t grid = (n + 255) / 256;
-  if (grid > 0x7fffffff) return fail(CHEM_EINVAL, "chem_eval_exp: n too large");
-  hipLaunchKernelGGL(eval_exp_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
-                     x, y, n);
+  if (grid > 0x7fffffff) return fail(CHEM_EINVAL, "chem_eval_math: n too large");
+  hipLaunchKernelGGL(eval_math_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                     (int)fn, x, y, n);
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? CHEM_OK : hip_fail(e, "launch eval_exp");
+  return e == hipSuccess ? CHEM_OK : hip_fail(e, "launch eval_math");
+}
+
+int chem_eval_exp(const double* x, double* y, int64_t n, void* stream) {
+  return chem_eval_math(CHEM_MATH_EXP_CW, x, y, n, stream);
 }
 
 int chem_mech_load(const char* path, chem_mech* out) {

@@ -121,7 +121,7 @@ __device__ __forceinline__ double coop_rhs(double Yk, double T, double rho, doub
   const int gl = x.gl;
   const bool sl = gl < N;
   const int k = sl ? gl : N - 1;
-  const double lnT = log(T);
+  const double lnT = log_atanh(T);
   const double invT = 1.0 / T;
   const double omlnT = 1.0 - lnT;
   const double lnPRT = C::LNPRT0 - lnT;
@@ -134,7 +134,7 @@ __device__ __forceinline__ double coop_rhs(double Yk, double T, double rho, doub
       lkf[r] = ln.lna + ln.bexp * lnT - ln.ear * invT;
     else
       lkf[r] = D[C::O_LNA + j] + D[C::O_BEXP + j] * lnT - D[C::O_EAR + j] * invT;
-    kf[r] = exp_cw(lkf[r]);
+    kf[r] = exp_estrin(lkf[r]);
   }
   // species k: concentration and thermo
   const double c = Yk * (rho * D[C::O_INVW + k]);
@@ -159,7 +159,7 @@ __device__ __forceinline__ double coop_rhs(double Yk, double T, double rho, doub
         dg += D[C::O_GNU + j * C::MG + q] * s[S::SG + I[C::O_GK + j * C::MG + q]];
     }
     const double dn = PRE ? ln.dnu : D[C::O_DNU + j];
-    const double kr = exp_cw(lkf[r] + dg - dn * lnPRT);
+    const double kr = exp_estrin(lkf[r] + dg - dn * lnPRT);
     double fw = kf[r], rv = kr;
 #pragma unroll
     for (int q = 0; q < C::MR; ++q) {

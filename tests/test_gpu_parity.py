@@ -317,3 +317,54 @@ def test_rate_exponential_within_one_ulp(chemgpu):
     print(f"[exp] max {ulp.max():.2f} ulp, mean {ulp.mean():.4f}", flush=True)
     assert ulp.max() <= 2.0 and ulp.mean() < 0.2
     assert y[-8] == 1.0 and y[-3] == np.inf and y[-2] == 0.0 and np.isnan(y[-1])
+
+
+def _ulps(y, x, fn):
+    """|y - fn(x)| in units of the last place of the double nearest the
+    extended-precision reference."""
+    ref = fn(x.astype(np.longdouble))
+    return (np.abs(y.astype(np.longdouble) - ref) / np.spacing(ref.astype(np.float64))).astype(
+        np.float64)
+
+
+def test_short_chain_exponential_within_one_ulp(chemgpu):
+    """The cooperative kernel's exponential (Estrin-form polynomial) against an
+    extended-precision reference: at most 1 ulp on [-745, 709], exact at 0,
+    same range behaviour as the per-lane exponential."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(12))
+    x = np.concatenate([rng.uniform(-708.0, 709.0, 2_000_000), rng.uniform(-60.0, 60.0, 2_000_000),
+                        rng.uniform(-0.4, 0.4, 500_000),
+                        [0.0, 1.0, -1.0, 709.7, -708.0, 800.0, -800.0, np.nan]])
+    y = chemgpu.chem_eval_math("exp_estrin", torch.from_numpy(x).cuda()).cpu().numpy()
+    fin = np.isfinite(x) & (x > -708.0) & (x < 709.7)
+    u = _ulps(y[fin], x[fin], np.exp)
+    print(f"[exp_estrin] max {u.max():.3f} ulp, mean {u.mean():.4f}", flush=True)
+    # a correctly rounded function averages 0.25 ulp from an exact reference
+    assert u.max() <= 1.0 and u.mean() < 0.3
+    assert y[-8] == 1.0 and y[-3] == np.inf and y[-2] == 0.0 and np.isnan(y[-1])
+
+
+def test_log_within_one_ulp(chemgpu):
+    """ln T for the rate constants and the Gibbs energies: at most 1 ulp from
+    an extended-precision reference over the whole positive range and densely
+    over temperatures, exact at 1, NaN for 0, negative and NaN inputs."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(13))
+    x = np.concatenate([np.exp(rng.uniform(-700.0, 700.0, 2_000_000)),
+                        rng.uniform(100.0, 5000.0, 2_000_000),
+                        rng.uniform(0.70, 1.45, 500_000),
+                        [1.0, 2.0, 0.5, np.sqrt(0.5), 0.0, -1.0, np.nan]])
+    y = chemgpu.chem_eval_math("log_atanh", torch.from_numpy(x).cuda()).cpu().numpy()
+    u = _ulps(y[:-3], x[:-3], np.log)
+    print(f"[log_atanh] max {u.max():.3f} ulp, mean {u.mean():.4f}", flush=True)
+    assert u.max() <= 1.0 and u.mean() < 0.3
+    assert y[-7] == 0.0 and y[-6] == np.log(2.0) and np.isnan(y[-3:]).all()
+
+
+def test_eval_math_rejects_unknown_function(chemgpu):
+    import torch
+    x = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(chemgpu.ChemError):
+        chemgpu._check(chemgpu._lib.chem_eval_math(7, x.data_ptr(), x.data_ptr(), 4, None),
+                       "chem_eval_math")
