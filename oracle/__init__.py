@@ -52,6 +52,7 @@ def lib():
         L.or_thermo.argtypes = [P, D, P, P, P]
         L.or_rates.argtypes = [P, D, P, P, P, P, P]
         L.or_rhs.argtypes = [P, D, P, P]
+        L.or_jacobian.argtypes = [P, D, P, P]
         L.or_lsrk_coeffs.argtypes = [P, P, P]
         L.or_integrate_cell.argtypes = [P, D, P, D, D, D, I, I, C.POINTER(D), C.POINTER(I),
                                         C.POINTER(I), P, I, C.POINTER(I)]
@@ -87,7 +88,7 @@ def lsrk_coeffs():
     return a, b, bh
 
 
-SCHEMES = {"lsrk": 0, "rkf45": 1}
+SCHEMES = {"lsrk": 0, "rkf45": 1, "ros4": 2}
 
 
 def rkf45_coeffs():
@@ -140,6 +141,13 @@ class Mech:
         f = np.zeros(self.ns + 1)
         lib().or_rhs(self._h, float(rho), _ptr(u), _ptr(f))
         return f
+
+    def jacobian(self, rho: float, u: np.ndarray) -> np.ndarray:
+        """df/du of the RHS at u = (T, Y) by complex-step differentiation."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        J = np.zeros((self.ns + 1, self.ns + 1))
+        lib().or_jacobian(self._h, float(rho), _ptr(u), _ptr(J))
+        return J
 
     def integrate_cell(self, rho, u, dt, rtol=1e-8, atol=1e-10, max_steps=100000,
                        fixed_steps=0, h0=0.0, trace_cap=0, scheme="lsrk"):

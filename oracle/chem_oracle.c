@@ -18,7 +18,13 @@
  *     error register, and the WRMS step-size controller of Eq. 22;
  *   - a per-cell driver over one flow time step;
  *   - for comparison, a full-storage Runge-Kutta-Fehlberg 4(5) step under the
- *     same controller (exponent 1/5 for its fourth-order error estimate).
+ *     same controller (exponent 1/5 for its fourth-order error estimate);
+ *   - and, as the implicit comparator the paper measures against, a
+ *     linearly implicit Rosenbrock step: fourth order with an embedded third
+ *     order solution (Shampine's parameter set in the Kaps-Rentrop form),
+ *     the exact Jacobian by complex-step differentiation of the RHS, a dense
+ *     LU factorisation with partial pivoting, the same controller
+ *     (exponent 1/4).
  *
  * Readings where the paper is silent or garbled (each also listed in the
  * design notes of the repository):
@@ -36,6 +42,7 @@
  * Units: cgs (mol/cm^3, g/cm^3, s); activation energy in J/mol.
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared -o liboracle.so chem_oracle.c -lm
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -327,6 +334,80 @@ void or_rhs(const or_mech *m, double rho, const double *u, double *f) {
     free(cp); free(h); free(s); free(w);
 }
 
+/* ------------------------------------------------ Jacobian (complex step) */
+/* The RHS of or_rhs evaluated in complex arithmetic: every operation in it
+ * (polynomials, exp, log, powers, products, the quotient of the T equation)
+ * is analytic, so for a real state u and a tiny real step s,
+ * Im f(u + i s e_k) / s = df/du_k to rounding, with no subtractive
+ * cancellation (the complex-step derivative of Squire and Trapp, 1998).  The
+ * NASA-7 range is chosen from the real part of T. */
+static void rhs_cplx(const or_mech *m, double rho, const double complex *u, double complex *f) {
+    int ns = m->ns;
+    double complex T = u[0];
+    double complex lnT = clog(T);
+    double complex *cp = malloc(sizeof(double complex) * ns);
+    double complex *h = malloc(sizeof(double complex) * ns);
+    double complex *g = malloc(sizeof(double complex) * ns);
+    double complex *c = malloc(sizeof(double complex) * ns);
+    double complex *w = malloc(sizeof(double complex) * ns);
+    for (int k = 0; k < ns; k++) {
+        const double *a = (creal(T) < m->Tmid[k]) ? &m->lo[k * 7] : &m->hi[k * 7];
+        cp[k] = a[0] + a[1] * T + a[2] * T * T + a[3] * T * T * T + a[4] * T * T * T * T;
+        h[k] = a[0] + a[1] * T / 2.0 + a[2] * T * T / 3.0 + a[3] * T * T * T / 4.0
+             + a[4] * T * T * T * T / 5.0 + a[5] / T;
+        double complex sR = a[0] * lnT + a[1] * T + a[2] * T * T / 2.0 + a[3] * T * T * T / 3.0
+                          + a[4] * T * T * T * T / 4.0 + a[6];
+        g[k] = h[k] - sR;
+        c[k] = rho * u[1 + k] / m->W[k];
+        w[k] = 0.0;
+    }
+    for (int j = 0; j < m->nr; j++) {
+        const or_reaction *r = &m->rx[j];
+        double complex kf = r->A * cexp(r->b * lnT) * cexp(-r->Ea / (OR_R_J * T));
+        double complex dG = 0.0;
+        int dnu = 0;
+        for (int i = 0; i < r->n_prod; i++) { dG += r->prod_nu[i] * g[r->prod_sp[i]]; dnu += r->prod_nu[i]; }
+        for (int i = 0; i < r->n_reac; i++) { dG -= r->reac_nu[i] * g[r->reac_sp[i]]; dnu -= r->reac_nu[i]; }
+        double complex Kc = cexp(-dG) * cexp(dnu * clog(m->pstd / (OR_R_CGS * T)));
+        double complex fwd = kf, rev = kf / Kc;
+        for (int i = 0; i < r->n_reac; i++)
+            for (int n = 0; n < r->reac_nu[i]; n++) fwd *= c[r->reac_sp[i]];
+        for (int i = 0; i < r->n_prod; i++)
+            for (int n = 0; n < r->prod_nu[i]; n++) rev *= c[r->prod_sp[i]];
+        double complex M = 1.0;
+        if (r->third_body) {
+            M = 0.0;
+            for (int k = 0; k < ns; k++) M += r->eff[k] * c[k];
+        }
+        double complex q = M * (fwd - rev);
+        for (int i = 0; i < r->n_reac; i++) w[r->reac_sp[i]] -= r->reac_nu[i] * q;
+        for (int i = 0; i < r->n_prod; i++) w[r->prod_sp[i]] += r->prod_nu[i] * q;
+    }
+    double complex num = 0.0, den = 0.0;
+    for (int k = 0; k < ns; k++) {
+        num += (h[k] - 1.0) * w[k];
+        den += c[k] * (cp[k] - 1.0);
+        f[1 + k] = m->W[k] * w[k] / rho;
+    }
+    f[0] = -T * num / den;
+    free(cp); free(h); free(g); free(c); free(w);
+}
+
+/* J[i*n + k] = df_i/du_k for u = (T, Y), n = N + 1. */
+void or_jacobian(const or_mech *m, double rho, const double *u, double *J) {
+    int n = m->ns + 1;
+    const double s = 1e-30;
+    double complex *uc = malloc(sizeof(double complex) * n);
+    double complex *fc = malloc(sizeof(double complex) * n);
+    for (int k = 0; k < n; k++) {
+        for (int i = 0; i < n; i++) uc[i] = u[i];
+        uc[k] += s * I;
+        rhs_cplx(m, rho, uc, fc);
+        for (int i = 0; i < n; i++) J[i * n + k] = cimag(fc[i]) / s;
+    }
+    free(uc); free(fc);
+}
+
 /* -------------------------------------------------------- LSRK coefficients */
 /* Kennedy, Carpenter & Lewis (2000) RK4(3)5[2R+]C: subdiagonal a_{i+1,i},
  * weights b_i and embedded weights bhat_i, as exact rationals. */
@@ -416,6 +497,88 @@ static void rkf45_step(or_rhs_fn f, const void *ctx, int n, double h, const doub
     }
 }
 
+/* The implicit comparator: a Rosenbrock (linearly implicit) step in the
+ * Kaps-Rentrop form, with W = I/(gamma h) - J(u_n) and stages
+ *   W g1 = f(u_n)
+ *   W g2 = f(u_n + a21 g1)              + c21 g1 / h
+ *   W g3 = f(u_n + a31 g1 + a32 g2)     + (c31 g1 + c32 g2) / h
+ *   W g4 = f(u_n + a31 g1 + a32 g2)     + (c41 g1 + c42 g2 + c43 g3) / h
+ * (the fourth stage reuses the third RHS evaluation), u_{n+1} = u_n + sum b_i g_i
+ * (fourth order) and the error estimate e = sum e_i g_i (the difference to
+ * the embedded third-order solution).  Parameters: Shampine (1982), gamma =
+ * 1/2.  For an autonomous RHS the time-derivative terms of the form vanish. */
+static const double RO_GAMMA = 0.5;
+static const double RO_A21 = 2.0, RO_A31 = 48.0 / 25.0, RO_A32 = 6.0 / 25.0;
+static const double RO_C21 = -8.0, RO_C31 = 372.0 / 25.0, RO_C32 = 12.0 / 5.0;
+static const double RO_C41 = -112.0 / 125.0, RO_C42 = -54.0 / 125.0, RO_C43 = -2.0 / 5.0;
+static const double RO_B[4] = {19.0 / 9.0, 1.0 / 2.0, 25.0 / 108.0, 125.0 / 108.0};
+static const double RO_E[4] = {17.0 / 54.0, 7.0 / 36.0, 0.0, 125.0 / 108.0};
+
+typedef void (*or_jac_fn)(const void *ctx, const double *u, double *J);
+
+/* In-place LU factorisation with partial pivoting of the n x n row-major
+ * matrix a; piv[k] = row swapped with row k at column k. */
+static void lu_factor(int n, double *a, int *piv) {
+    for (int k = 0; k < n; k++) {
+        int p = k;
+        for (int r = k + 1; r < n; r++)
+            if (fabs(a[r * n + k]) > fabs(a[p * n + k])) p = r;
+        piv[k] = p;
+        if (p != k)
+            for (int j = 0; j < n; j++) {
+                double t = a[k * n + j]; a[k * n + j] = a[p * n + j]; a[p * n + j] = t;
+            }
+        for (int r = k + 1; r < n; r++) {
+            double l = a[r * n + k] / a[k * n + k];
+            a[r * n + k] = l;
+            for (int j = k + 1; j < n; j++) a[r * n + j] -= l * a[k * n + j];
+        }
+    }
+}
+
+static void lu_solve(int n, const double *a, const int *piv, double *b) {
+    for (int k = 0; k < n; k++) {
+        if (piv[k] != k) { double t = b[k]; b[k] = b[piv[k]]; b[piv[k]] = t; }
+        for (int r = k + 1; r < n; r++) b[r] -= a[r * n + k] * b[k];
+    }
+    for (int k = n - 1; k >= 0; k--) {
+        double s = b[k];
+        for (int j = k + 1; j < n; j++) s -= a[k * n + j] * b[j];
+        b[k] = s / a[k * n + k];
+    }
+}
+
+static void ros4_step(or_rhs_fn f, or_jac_fn jac, const void *ctx, int n, double h,
+                      const double *un, double *unew, double *e) {
+    double *W = malloc(sizeof(double) * n * n);
+    double *g = malloc(sizeof(double) * n * 4), *y = malloc(sizeof(double) * n);
+    double *f3 = malloc(sizeof(double) * n);
+    int *piv = calloc((size_t)n, sizeof(int));
+    jac(ctx, un, W);
+    for (int i = 0; i < n * n; i++) W[i] = -W[i];
+    for (int i = 0; i < n; i++) W[i * n + i] += 1.0 / (RO_GAMMA * h);
+    lu_factor(n, W, piv);
+    double *g1 = g, *g2 = g + n, *g3 = g + 2 * n, *g4 = g + 3 * n;
+    f(ctx, un, g1);
+    lu_solve(n, W, piv, g1);
+    for (int i = 0; i < n; i++) y[i] = un[i] + RO_A21 * g1[i];
+    f(ctx, y, g2);
+    for (int i = 0; i < n; i++) g2[i] += RO_C21 * g1[i] / h;
+    lu_solve(n, W, piv, g2);
+    for (int i = 0; i < n; i++) y[i] = un[i] + RO_A31 * g1[i] + RO_A32 * g2[i];
+    f(ctx, y, f3);
+    for (int i = 0; i < n; i++) g3[i] = f3[i] + (RO_C31 * g1[i] + RO_C32 * g2[i]) / h;
+    lu_solve(n, W, piv, g3);
+    for (int i = 0; i < n; i++)
+        g4[i] = f3[i] + (RO_C41 * g1[i] + RO_C42 * g2[i] + RO_C43 * g3[i]) / h;
+    lu_solve(n, W, piv, g4);
+    for (int i = 0; i < n; i++) {
+        unew[i] = un[i] + RO_B[0] * g1[i] + RO_B[1] * g2[i] + RO_B[2] * g3[i] + RO_B[3] * g4[i];
+        e[i] = RO_E[0] * g1[i] + RO_E[1] * g2[i] + RO_E[2] * g3[i] + RO_E[3] * g4[i];
+    }
+    free(W); free(g); free(y); free(f3); free(piv);
+}
+
 /* Eq. 22: WRMS norm of the error with weights from the state at step start. */
 static double wrms(int n, const double *e, const double *un, double rtol, double atol) {
     double sum = 0.0;
@@ -442,15 +605,18 @@ typedef struct { double t, h, err; int accepted; } or_trace;
 
 /* Integrate u over [0, dt]; returns a status code.  h_inout: initial step
  * hint (<= 0 => dt) and, on return, the proposed next step. */
-enum { OR_SCHEME_LSRK = 0, OR_SCHEME_RKF45 = 1 };
+enum { OR_SCHEME_LSRK = 0, OR_SCHEME_RKF45 = 1, OR_SCHEME_ROS4 = 2 };
 
-static void scheme_step(int scheme, or_rhs_fn f, const void *ctx, int n, double h,
-                        const double *un, double *unew, double *e, double *U, double *F) {
+static void scheme_step(int scheme, or_rhs_fn f, or_jac_fn jac, const void *ctx, int n,
+                        double h, const double *un, double *unew, double *e, double *U,
+                        double *F) {
     if (scheme == OR_SCHEME_RKF45) rkf45_step(f, ctx, n, h, un, unew, e, U, F);
+    else if (scheme == OR_SCHEME_ROS4) ros4_step(f, jac, ctx, n, h, un, unew, e);
     else lsrk_step(f, ctx, n, h, un, unew, e, U, F);
 }
 
-static int drive(int scheme, or_rhs_fn f, const void *ctx, int n, double *u, double dt,
+static int drive(int scheme, or_rhs_fn f, or_jac_fn jac, const void *ctx, int n, double *u,
+                 double dt,
                  double rtol, double atol, int max_steps, int fixed_steps, double *h_inout,
                  int *nacc, int *nrej, or_trace *trace, int trace_cap, int *trace_len) {
     double *unew = malloc(sizeof(double) * n), *e = malloc(sizeof(double) * n);
@@ -462,7 +628,7 @@ static int drive(int scheme, or_rhs_fn f, const void *ctx, int n, double *u, dou
     if (fixed_steps > 0) {
         double h = dt / fixed_steps;
         for (int s = 0; s < fixed_steps; s++) {
-            scheme_step(scheme, f, ctx, n, h, u, unew, e, U, F);
+            scheme_step(scheme, f, jac, ctx, n, h, u, unew, e, U, F);
             for (int i = 0; i < n; i++) u[i] = unew[i];
             (*nacc)++;
         }
@@ -475,7 +641,7 @@ static int drive(int scheme, or_rhs_fn f, const void *ctx, int n, double *u, dou
     for (;;) {
         int last = 0;
         if (h >= dt - t) { h = dt - t; last = 1; }
-        scheme_step(scheme, f, ctx, n, h, u, unew, e, U, F);
+        scheme_step(scheme, f, jac, ctx, n, h, u, unew, e, U, F);
         double err = wrms(n, e, u, rtol, atol);
         double fac = step_factor(err, expo);
         int ok = (err <= 1.0);
@@ -509,6 +675,11 @@ static void chem_rhs_cb(const void *ctx, const double *u, double *f) {
     or_rhs(c->m, c->rho, u, f);
 }
 
+static void chem_jac_cb(const void *ctx, const double *u, double *J) {
+    const chem_ctx *c = ctx;
+    or_jacobian(c->m, c->rho, u, J);
+}
+
 /* One cell: u (N+1) in/out.  Returns status. */
 int or_integrate_cell_scheme(int scheme, const or_mech *m, double rho, double *u, double dt,
                              double rtol, double atol, int max_steps, int fixed_steps,
@@ -519,7 +690,7 @@ int or_integrate_cell_scheme(int scheme, const or_mech *m, double rho, double *u
     if (!isfinite(rho)) { *nacc = *nrej = 0; return OR_NONFINITE; }
     chem_ctx ctx = {m, rho};
     or_trace *tr = trace_out ? malloc(sizeof(or_trace) * (trace_cap > 0 ? trace_cap : 1)) : NULL;
-    int st = drive(scheme, chem_rhs_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps,
+    int st = drive(scheme, chem_rhs_cb, chem_jac_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps,
                    h_inout, nacc, nrej, tr, trace_cap, trace_len);
     if (tr) {
         for (int i = 0; i < *trace_len; i++) {
@@ -659,6 +830,12 @@ static void lin_rhs_cb(const void *ctx, const double *u, double *f) {
     }
 }
 
+static void lin_jac_cb(const void *ctx, const double *u, double *J) {
+    const lin_ctx *c = ctx;
+    (void)u;
+    for (int i = 0; i < c->n * c->n; i++) J[i] = c->A[i];
+}
+
 /* u' = A u with the same step, controller and driver as the chemistry path. */
 int or_integrate_linear_scheme(int scheme, int n, const double *A, double *u, double dt,
                                double rtol, double atol, int max_steps, int fixed_steps,
@@ -666,7 +843,7 @@ int or_integrate_linear_scheme(int scheme, int n, const double *A, double *u, do
                                int trace_cap, int *trace_len) {
     lin_ctx ctx = {n, A};
     or_trace *tr = trace_out ? malloc(sizeof(or_trace) * (trace_cap > 0 ? trace_cap : 1)) : NULL;
-    int st = drive(scheme, lin_rhs_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps,
+    int st = drive(scheme, lin_rhs_cb, lin_jac_cb, &ctx, n, u, dt, rtol, atol, max_steps, fixed_steps,
                    h_inout, nacc, nrej, tr, trace_cap, trace_len);
     if (tr) {
         for (int i = 0; i < *trace_len; i++) {
