@@ -517,7 +517,8 @@ static const double RO_E[4] = {17.0 / 54.0, 7.0 / 36.0, 0.0, 125.0 / 108.0};
 typedef void (*or_jac_fn)(const void *ctx, const double *u, double *J);
 
 /* In-place LU factorisation with partial pivoting of the n x n row-major
- * matrix a; piv[k] = row swapped with row k at column k. */
+ * matrix a (P a = L U, whole rows swapped, unit L below the diagonal);
+ * piv[k] = row swapped with row k at column k. */
 static void lu_factor(int n, double *a, int *piv) {
     for (int k = 0; k < n; k++) {
         int p = k;
@@ -536,11 +537,13 @@ static void lu_factor(int n, double *a, int *piv) {
     }
 }
 
+/* Solve a x = b in place: b <- P b (the swaps in factorisation order), then
+ * L y = P b and U x = y. */
 static void lu_solve(int n, const double *a, const int *piv, double *b) {
-    for (int k = 0; k < n; k++) {
+    for (int k = 0; k < n; k++)
         if (piv[k] != k) { double t = b[k]; b[k] = b[piv[k]]; b[piv[k]] = t; }
+    for (int k = 0; k < n; k++)
         for (int r = k + 1; r < n; r++) b[r] -= a[r * n + k] * b[k];
-    }
     for (int k = n - 1; k >= 0; k--) {
         double s = b[k];
         for (int j = k + 1; j < n; j++) s -= a[k * n + j] * b[j];

@@ -169,3 +169,28 @@ def test_agrees_with_the_explicit_scheme(mech9_path, omech9):
     omech9.integrate(c, 1e-7, scheme="ros4")
     assert np.max(np.abs(c[0] - b[0]) / b[0]) < 2e-7
     assert np.max(np.abs(c[1:N + 1] - b[1:N + 1])) < 2e-7
+
+
+def test_linear_step_is_the_stability_function_of_the_matrix():
+    """On u' = A u one step is u1 = R(hA) u0 with R the scalar stability
+    function; with A = V D V^-1 that is V R(hD) V^-1 u0 (numpy's eigenvalue
+    routine, R from one-component steps).  At h = 1 the matrix W = 2I - A is
+    dominated by off-diagonal entries, so the LU factorisation pivots, also
+    after the first column: a pin of the row swaps and the solve."""
+    rng = np.random.Generator(np.random.PCG64(41))
+    n = 7
+    lam = -np.logspace(0, 2.5, n) * rng.uniform(0.8, 1.2, n)
+    V = rng.normal(size=(n, n))
+    A = V @ np.diag(lam) @ np.linalg.inv(V)
+    u0 = rng.normal(size=n)
+    W = 2.0 * np.eye(n) - A
+    # the pivot column changes after the first step of elimination
+    assert np.argmax(np.abs(W[:, 0])) != 0
+
+    def R(z):
+        return oracle.integrate_linear(np.array([[z]]), [1.0], 1.0, fixed_steps=1,
+                                       scheme="ros4")["u"][0]
+
+    expect = V @ np.diag([R(x) for x in lam]) @ np.linalg.solve(V, u0)
+    got = oracle.integrate_linear(A, u0, 1.0, fixed_steps=1, scheme="ros4")["u"]
+    assert np.allclose(got, expect, rtol=1e-9, atol=1e-9 * np.abs(expect).max())
