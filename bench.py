@@ -42,9 +42,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--scheme", default="lsrk", choices=["lsrk", "rkf45"],
+    ap.add_argument("--scheme", default="lsrk", choices=["lsrk", "rkf45", "ros4"],
                     help="lsrk: the paper's two-register LSRK4(3)5; rkf45: the full-storage "
-                         "Runge-Kutta-Fehlberg 4(5) comparison scheme")
+                         "Runge-Kutta-Fehlberg 4(5) comparison scheme; ros4: the implicit "
+                         "(Rosenbrock) comparator")
     ap.add_argument("--tail", type=int, default=0,
                     help="steps after which a cell moves to the cooperative kernel "
                          "(0 = default, < 0 = never)")

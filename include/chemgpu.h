@@ -66,7 +66,13 @@ typedef struct {
     int32_t scheme;      /* 0: the paper's low-storage LSRK4(3)5 two-register scheme (Eq. 21);
                             1: the full-storage Runge-Kutta-Fehlberg 4(5) comparison scheme
                             (six stages, all stage vectors kept; same controller with
-                            exponent 1/5; no cooperative tail) */
+                            exponent 1/5; no cooperative tail);
+                            2: the implicit comparator, a fourth-order Rosenbrock method
+                            (Shampine's parameters, Kaps-Rentrop form, embedded third
+                            order; exact Jacobian, LU with partial pivoting; same
+                            controller, exponent 1/4; no cooperative tail).  Built only for
+                            mechanisms of at most 15 species (CHEM_EUNSUPPORTED otherwise)
+                            and run with block_size <= 256 (CHEM_EINVAL otherwise) */
     int32_t tail_cap;    /* most handed-over cells per CU that the cooperative kernel takes
                             (see tail_steps): 0 = tuned default, else 64; < 0 = no limit */
 } chem_opts;

@@ -99,7 +99,7 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
-SCHEMES = {"lsrk": 0, "rkf45": 1}
+SCHEMES = {"lsrk": 0, "rkf45": 1, "ros4": 2}
 
 
 def make_opts(rtol=0.0, atol=0.0, max_steps=0, chunk_steps=0, block_size=0, fixed_steps=0,

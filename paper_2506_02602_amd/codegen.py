@@ -234,6 +234,166 @@ def gen_rhs(m: dict) -> str:
     return "\n".join(L)
 
 
+ROS4_MAX_N1 = 16   # the Rosenbrock comparator holds the (N+1)^2 Jacobian in registers
+
+
+def gen_jac(m: dict) -> str:
+    """f(u) and the exact Jacobian J[i*(N+1) + k] = df_i/du_k of the same ODE,
+    for the implicit (Rosenbrock) comparator: derivatives of every term of
+    ``gen_rhs`` written out (chain rule through the Arrhenius and equilibrium
+    exponentials, the NASA-7 polynomials, the mass-action products, the
+    third-body sums and the quotient of the temperature equation).  Only
+    nonzero species couplings get a register; the rest of J is zero.
+    Mechanisms with N + 1 > ROS4_MAX_N1 get no Jacobian (the comparator is not
+    built for them)."""
+    sp, rxs = m["species"], m["reactions"]
+    N = len(sp)
+    N1 = N + 1
+    if N1 > ROS4_MAX_N1:
+        return "  static constexpr bool HAS_JAC = false;"
+    L = ["  static constexpr bool HAS_JAC = true;",
+         "  __device__ __forceinline__ static void jac(const double* __restrict__ u, double rho,",
+         "                                             double inv_rho, double* __restrict__ f,",
+         "                                             double* __restrict__ J) {",
+         "    asm volatile(\"\" : \"+v\"(rho), \"+v\"(inv_rho));",
+         "    const double T = u[0];",
+         "    const double lnT = log(T);",
+         "    const double invT = 1.0 / T;",
+         "    const double omlnT = 1.0 - lnT;",
+         f"    const double lnPRT = {lit(math.log(m['pstd'] / R_CGS))} - lnT;"]
+    for k, s_ in enumerate(sp):
+        L.append(f"    const double c{k} = u[{k + 1}] * (rho * {lit(1.0 / s_['W'])});")
+    # thermo and its T-derivatives, per lane range selection
+    for k, s_ in enumerate(sp):
+        L.append(f"    double h{k}, g{k}, cm{k}, dcp{k};")
+        for rng, head in (("lo", f"    if (T < {lit(s_['Tmid'])}) {{"), ("hi", "    } else {")):
+            a = s_[rng]
+            L.append(head)
+            L.append(f"      h{k} = {_horner([a[0], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5], 'T')} + {lit(a[5])} * invT;")
+            L.append(f"      g{k} = {lit(a[0])} * omlnT - T * ({_horner([a[1] / 2, a[2] / 6, a[3] / 12, a[4] / 20], 'T')}) + {lit(a[5])} * invT - {lit(a[6])};")
+            L.append(f"      cm{k} = {_horner([a[0] - 1.0] + list(a[1:5]), 'T')};")
+            L.append(f"      dcp{k} = {_horner([a[1], 2 * a[2], 3 * a[3], 4 * a[4]], 'T')};")
+        L.append("    }")
+        # d(h/RT)/dT = (cp/R - h/RT)/T, d(g/RT)/dT = -(h/RT)/T
+        L.append(f"    const double dh{k} = (cm{k} + 1.0 - h{k}) * invT;")
+        L.append(f"    const double dg{k} = -h{k} * invT;")
+    L.append("    const double den = " + " + ".join(f"c{k} * cm{k}" for k in range(N)) + ";")
+    L.append("    const double dden_dT = " + " + ".join(f"c{k} * dcp{k}" for k in range(N)) + ";")
+    # production rates and their derivatives (concentration space, and T)
+    pairs = set()
+    for rx in rxs:
+        nu = {}
+        for k, v in rx["reac"].items():
+            nu[k] = nu.get(k, 0) - v
+        for k, v in rx["prod"].items():
+            nu[k] = nu.get(k, 0) + v
+        dep = set(rx["reac"]) | set(rx["prod"])
+        if rx["tb"]:
+            dep |= {k for k in range(N) if rx["eff"][k] != 0.0}
+        for k, v in nu.items():
+            if v != 0:
+                for l in dep:
+                    pairs.add((k, l))
+    pairs = sorted(pairs)
+    L.append("    double " + ", ".join(f"w{k} = 0.0, wT{k} = 0.0" for k in range(N)) + ";")
+    if pairs:
+        L.append("    double " + ", ".join(f"wc{k}_{l} = 0.0" for k, l in pairs) + ";")
+
+    def mono(side, coef, skip=None):
+        """coef * prod c^nu, or its derivative in c_skip (nu c^(nu-1) ...)."""
+        terms = [coef]
+        for k, v in sorted(side.items()):
+            p = v - 1 if k == skip else v
+            if k == skip:
+                terms.insert(0, lit(float(v)) if v != 1 else "1.0")
+            terms += [f"c{k}"] * p
+        return " * ".join(terms)
+
+    for j, rx in enumerate(rxs):
+        L.append(f"    {{  // reaction {j}")
+        e = [lit(math.log(rx["A"]))]
+        if rx["b"] != 0.0:
+            e.append(f"{lit(rx['b'])} * lnT")
+        if rx["Ea"] != 0.0:
+            e.append(f"- {lit(rx['Ea'] / R_J)} * invT")
+        L.append(f"      const double lkf = {' + '.join(e).replace('+ -', '-')};")
+        L.append(f"      const double dlkf = ({lit(rx['b'])} + {lit(rx['Ea'] / R_J)} * invT) * invT;")
+        L.append("      const double kf = exp_cw(lkf);")
+        nu = {}
+        for k, v in rx["reac"].items():
+            nu[k] = nu.get(k, 0) - v
+        for k, v in rx["prod"].items():
+            nu[k] = nu.get(k, 0) + v
+        dnu = sum(nu.values())
+        gsum = "".join(f" + {lit(float(v))} * g{k}" for k, v in sorted(nu.items()) if v != 0)
+        dgsum = "".join(f" + {lit(float(v))} * dg{k}" for k, v in sorted(nu.items()) if v != 0)
+        L.append(f"      const double kr = exp_cw(lkf{gsum} - {lit(float(dnu))} * lnPRT);")
+        L.append(f"      const double dlkr = dlkf{dgsum} + {lit(float(dnu))} * invT;")
+        L.append(f"      const double fw = {mono(rx['reac'], 'kf')};")
+        L.append(f"      const double rv = {mono(rx['prod'], 'kr')};")
+        dep = sorted(set(rx["reac"]) | set(rx["prod"]) |
+                     ({k for k in range(N) if rx["eff"][k] != 0.0} if rx["tb"] else set()))
+        if rx["tb"]:
+            mt = " + ".join(f"{lit(a)} * c{k}" for k, a in enumerate(rx["eff"]) if a != 0.0)
+            L.append(f"      const double mt = {mt};")
+            L.append("      const double q = mt * (fw - rv);")
+            L.append("      const double qT = mt * (fw * dlkf - rv * dlkr);")
+        else:
+            L.append("      const double q = fw - rv;")
+            L.append("      const double qT = fw * dlkf - rv * dlkr;")
+        for l in dep:
+            parts = []
+            if l in rx["reac"]:
+                parts.append(mono(rx["reac"], "kf", skip=l))
+            if l in rx["prod"]:
+                parts.append("-" + mono(rx["prod"], "kr", skip=l))
+            d = " + ".join(parts).replace("+ -", "- ") if parts else "0.0"
+            if rx["tb"]:
+                expr = f"mt * ({d})" if parts else "0.0"
+                if rx["eff"][l] != 0.0:
+                    expr = f"{expr} + {lit(rx['eff'][l])} * (fw - rv)" if parts else \
+                        f"{lit(rx['eff'][l])} * (fw - rv)"
+            else:
+                expr = d
+            L.append(f"      const double qc{l} = {expr};")
+        for k, v in sorted(nu.items()):
+            if v == 0:
+                continue
+            cv = lit(float(v))
+            L.append(f"      w{k} += {cv} * q;")
+            L.append(f"      wT{k} += {cv} * qT;")
+            for l in dep:
+                L.append(f"      wc{k}_{l} += {cv} * qc{l};")
+        L.append("    }")
+    L.append("    const double num = " + " + ".join(f"(h{k} - 1.0) * w{k}" for k in range(N)) + ";")
+    L.append("    const double inv_den = 1.0 / den;")
+    L.append("    const double r = num * inv_den;")
+    L.append("    f[0] = -T * r;")
+    for k, s_ in enumerate(sp):
+        L.append(f"    f[{k + 1}] = w{k} * ({lit(s_['W'])} * inv_rho);")
+    # species rows
+    nz = {(k, l) for k, l in pairs}
+    for k, s_ in enumerate(sp):
+        L.append(f"    J[{(k + 1) * N1}] = wT{k} * ({lit(s_['W'])} * inv_rho);")
+        for l, s2 in enumerate(sp):
+            idx = (k + 1) * N1 + l + 1
+            if (k, l) in nz:
+                L.append(f"    J[{idx}] = {lit(s_['W'] / s2['W'])} * wc{k}_{l};")
+            else:
+                L.append(f"    J[{idx}] = 0.0;")
+    # temperature row: f0 = -T num / den
+    dnT = " + ".join(f"(h{k} - 1.0) * wT{k} + dh{k} * w{k}" for k in range(N))
+    L.append(f"    const double dnum_dT = {dnT};")
+    L.append("    J[0] = -r - T * (dnum_dT - r * dden_dT) * inv_den;")
+    for l, s2 in enumerate(sp):
+        terms = [f"(h{k} - 1.0) * wc{k}_{l}" for k in range(N) if (k, l) in nz]
+        dnl = " + ".join(terms) if terms else "0.0"
+        L.append(f"    J[{l + 1}] = -T * (({dnl}) * (rho * {lit(1.0 / s2['W'])}) - r * "
+                 f"(rho * {lit(1.0 / s2['W'])}) * cm{l}) * inv_den;")
+    L.append("  }")
+    return "\n".join(L)
+
+
 def gen_aux(m: dict) -> str:
     """Constants and thermo helpers used by the surrogate's features and trust
     test: molecular weights, element mass coefficients a_ek m_e / W_k, and the
@@ -440,6 +600,19 @@ def rhs_flops(m: dict) -> int:
     return c["flops"] + FLOP_EXP * c["exp"] + FLOP_LOG * c["log"] + FLOP_DIV * c["div"]
 
 
+def jac_flops(m: dict) -> int:
+    """Operation count of the generated Jacobian (``gen_jac``): every binary
+    arithmetic operator and accumulation in its source (FMA-able pairs
+    counted as 2), plus its exponentials, logarithm and the two divisions."""
+    src = gen_jac(m)
+    if "jac(" not in src:
+        return 0
+    body = src.split("double* __restrict__ J) {", 1)[1]
+    ops = body.count(" * ") + body.count(" + ") + body.count(" - ") + body.count(" += ")
+    c = op_counts(m)
+    return ops + FLOP_EXP * c["exp"] + FLOP_LOG + 2 * FLOP_DIV
+
+
 def step_flops(m: dict, scheme: str = "lsrk") -> int:
     """Flops of one LSRK step: 5 RHS + stage updates + WRMS norm + control.
 
@@ -455,6 +628,15 @@ def step_flops(m: dict, scheme: str = "lsrk") -> int:
     of control."""
     n1 = len(m["species"]) + 1
     wrms = n1 * (2 + FLOP_DIV + 2) + 1 + FLOP_SQRT
+    if scheme == "ros4":
+        # Jacobian (which also returns f(u_n)), two more RHS, LU with
+        # partial pivoting (2/3 n^3 + one division per column), four solves
+        # (2 n^2 each, one division per row), stage combinations and the
+        # diagonal shift (~33 n), WRMS and the factor as for the LSRK step
+        lu = (2 * n1 ** 3) // 3 + n1 * FLOP_DIV
+        solves = 4 * (2 * n1 * n1 + n1 * FLOP_DIV)
+        return (jac_flops(m) + 2 * rhs_flops(m) + lu + solves + 33 * n1 + wrms
+                + 2 * FLOP_SQRT + FLOP_DIV + 4)
     if scheme == "rkf45":
         upd = 2 * (1 + 2 + 3 + 4 + 5) * n1 + 2 * 2 * 6 * n1 + 6 * 7
         return 6 * rhs_flops(m) + upd + wrms + FLOP_LOG + FLOP_EXP + 4
@@ -477,6 +659,7 @@ def gen_header(path: str) -> tuple[str, dict]:
         f"  static constexpr unsigned long long HASH = 0x{m['hash']:016x}ULL;",
         f"  static constexpr const char* NAME = \"{m['name']}\";",
         rhs,
+        gen_jac(m),
         gen_aux(m),
         coop_mem,
         "};",

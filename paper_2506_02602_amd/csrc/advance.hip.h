@@ -1,15 +1,16 @@
 // Per-lane step driver shared by the kernels: the adaptive advance towards
-// dt with the Eq. 22 controller and the fixed-step test mode, for either
-// scheme (the paper's low-storage LSRK4(3)5 or the full-storage Fehlberg
-// 4(5) comparison scheme).
+// dt with the Eq. 22 controller and the fixed-step test mode, for each
+// scheme (the paper's low-storage LSRK4(3)5, the full-storage Fehlberg 4(5)
+// comparison scheme, or the implicit Rosenbrock comparator).
 #pragma once
 
 #include "lsrk.hip.h"
 #include "rkf45.hip.h"
+#include "ros4.hip.h"
 
 namespace chemgpu {
 
-enum : int { SCHEME_LSRK = 0, SCHEME_RKF45 = 1 };
+enum : int { SCHEME_LSRK = 0, SCHEME_RKF45 = 1, SCHEME_ROS4 = 2 };
 
 template <class M, int S>
 __device__ __forceinline__ double take_step(const double (&u)[M::NS + 1], double rho,
@@ -17,6 +18,8 @@ __device__ __forceinline__ double take_step(const double (&u)[M::NS + 1], double
                                             const Control& c) {
   if constexpr (S == SCHEME_RKF45)
     return rkf45_step<M>(u, rho, inv_rho, h, X, c);
+  else if constexpr (S == SCHEME_ROS4)
+    return ros4_step<M>(u, rho, inv_rho, h, X, c);
   else
     return lsrk_step<M>(u, rho, inv_rho, h, X, c);
 }

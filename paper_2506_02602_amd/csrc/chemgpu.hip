@@ -568,6 +568,7 @@ struct MechEntry {
   unsigned long long hash;
   int ns, nr;
   const char* name;
+  bool has_jac;  // a generated Jacobian: the Rosenbrock comparator is built
   hipError_t (*launch_direct)(const PoolArgs&, int block, hipStream_t);
   hipError_t (*launch_persistent)(const PoolArgs&, int block, int grid, hipStream_t);
   hipError_t (*launch_coop)(const PoolArgs&, int n_cu, hipStream_t);
@@ -588,27 +589,47 @@ template <class M, int S>
 hipError_t launch_direct_s(const PoolArgs& a, int block, hipStream_t s) {
   const int64_t grid = (a.one.n + block - 1) / block;
   if (grid == 0) return hipSuccess;
-  if (block <= 256)
+  if constexpr (S == SCHEME_ROS4) {
     hipLaunchKernelGGL((lsrk_direct<M, 256, S>), dim3((unsigned)grid), dim3(block), 0, s, a);
-  else
-    hipLaunchKernelGGL((lsrk_direct<M, 512, S>), dim3((unsigned)grid), dim3(block), 0, s, a);
+  } else {
+    if (block <= 256)
+      hipLaunchKernelGGL((lsrk_direct<M, 256, S>), dim3((unsigned)grid), dim3(block), 0, s, a);
+    else
+      hipLaunchKernelGGL((lsrk_direct<M, 512, S>), dim3((unsigned)grid), dim3(block), 0, s, a);
+  }
   return hipGetLastError();
 }
 
+// The Rosenbrock comparator holds its (N+1)^2 matrix in registers: it is
+// built only for mechanisms with a generated Jacobian and only with the
+// 256-lane launch bound (one wave per SIMD may use every register).
 template <class M>
 hipError_t launch_direct(const PoolArgs& a, int block, hipStream_t s) {
+  if (a.scheme == SCHEME_ROS4) {
+    if constexpr (M::HAS_JAC) {
+      if (block > 256) return hipErrorInvalidConfiguration;
+      return launch_direct_s<M, SCHEME_ROS4>(a, block, s);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   return a.scheme == SCHEME_RKF45 ? launch_direct_s<M, SCHEME_RKF45>(a, block, s)
                                   : launch_direct_s<M, SCHEME_LSRK>(a, block, s);
 }
 
 template <class M, int S>
 hipError_t launch_persistent_s(const PoolArgs& a, int block, int grid, hipStream_t s) {
-  if (block <= 256)
+  if constexpr (S == SCHEME_ROS4) {
     hipLaunchKernelGGL((lsrk_persistent<M, 256, S>), dim3(grid), dim3(block),
                        Slots<M>::bytes(block), s, a);
-  else
-    hipLaunchKernelGGL((lsrk_persistent<M, 512, S>), dim3(grid), dim3(block),
-                       Slots<M>::bytes(block), s, a);
+  } else {
+    if (block <= 256)
+      hipLaunchKernelGGL((lsrk_persistent<M, 256, S>), dim3(grid), dim3(block),
+                         Slots<M>::bytes(block), s, a);
+    else
+      hipLaunchKernelGGL((lsrk_persistent<M, 512, S>), dim3(grid), dim3(block),
+                         Slots<M>::bytes(block), s, a);
+  }
   return hipGetLastError();
 }
 
@@ -617,6 +638,14 @@ hipError_t launch_persistent(const PoolArgs& a, int block, int grid, hipStream_t
   hipLaunchKernelGGL(pool_reset, dim3(1), dim3(1), 0, s, a.next,
                      a.tail_steps > 0 ? a.tail.count : nullptr,
                      a.tail_steps > 0 ? a.tail.next : nullptr);
+  if (a.scheme == SCHEME_ROS4) {
+    if constexpr (M::HAS_JAC) {
+      if (block > 256) return hipErrorInvalidConfiguration;
+      return launch_persistent_s<M, SCHEME_ROS4>(a, block, grid, s);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   return a.scheme == SCHEME_RKF45 ? launch_persistent_s<M, SCHEME_RKF45>(a, block, grid, s)
                                   : launch_persistent_s<M, SCHEME_LSRK>(a, block, grid, s);
 }
@@ -653,18 +682,27 @@ template <class M, int S>
 int max_blocks_per_cu_s(int block) {
   int nb = 0;
   hipError_t e;
-  if (block <= 256)
+  if constexpr (S == SCHEME_ROS4) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 256, S>, block,
                                                      Slots<M>::bytes(block));
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 512, S>, block,
-                                                     Slots<M>::bytes(block));
+  } else {
+    if (block <= 256)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 256, S>, block,
+                                                       Slots<M>::bytes(block));
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsrk_persistent<M, 512, S>, block,
+                                                       Slots<M>::bytes(block));
+  }
   if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
 template <class M>
 int max_blocks_per_cu(int block, int scheme) {
+  if (scheme == SCHEME_ROS4) {
+    if constexpr (M::HAS_JAC) return max_blocks_per_cu_s<M, SCHEME_ROS4>(block);
+    else return 1;
+  }
   return scheme == SCHEME_RKF45 ? max_blocks_per_cu_s<M, SCHEME_RKF45>(block)
                                 : max_blocks_per_cu_s<M, SCHEME_LSRK>(block);
 }
@@ -674,7 +712,7 @@ size_t lds_per_lane() {
   return Slots<M>::bytes(1);
 }
 
-#define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, &launch_direct<M>, &launch_persistent<M>, \
+#define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, M::HAS_JAC, &launch_direct<M>, &launch_persistent<M>, \
                        &launch_coop<M>, &launch_cons_to_prim<M>, &launch_prim_to_cons<M>, \
                        &max_blocks_per_cu<M>, &lds_per_lane<M>, \
                        &launch_surr_infer<M>, &launch_surr_hull<M>, &launch_make_pairs<M>},
@@ -801,10 +839,21 @@ int check_opts(const chem_opts* o) {
   if (!o) return CHEM_OK;
   if (!(o->rtol >= 0) || !(o->atol >= 0) || o->max_steps < 0 || o->fixed_steps < 0)
     return fail(CHEM_EINVAL, "chem_opts: negative or NaN field");
-  if (o->scheme != SCHEME_LSRK && o->scheme != SCHEME_RKF45)
-    return fail(CHEM_EINVAL, "chem_opts.scheme must be 0 (LSRK4(3)5) or 1 (RKF45)");
+  if (o->scheme != SCHEME_LSRK && o->scheme != SCHEME_RKF45 && o->scheme != SCHEME_ROS4)
+    return fail(CHEM_EINVAL,
+                "chem_opts.scheme must be 0 (LSRK4(3)5), 1 (RKF45) or 2 (Rosenbrock)");
   if (o->block_size != 0 && (o->block_size % 64 != 0 || o->block_size > 512 || o->block_size < 64))
     return fail(CHEM_EINVAL, "chem_opts.block_size must be a multiple of 64 in [64, 512]");
+  return CHEM_OK;
+}
+
+// The Rosenbrock comparator needs a generated Jacobian and the 256-lane
+// launch bound.
+int check_scheme_launch(chem_mech m, const chem_opts* o, int block) {
+  if (!o || o->scheme != SCHEME_ROS4) return CHEM_OK;
+  if (!m->entry->has_jac)
+    return fail(CHEM_EUNSUPPORTED, "no Rosenbrock kernel for this mechanism (more than 15 species)");
+  if (block > 256) return fail(CHEM_EINVAL, "the Rosenbrock scheme runs with block_size <= 256");
   return CHEM_OK;
 }
 
@@ -820,7 +869,7 @@ int size_bucket(int64_t total) {
 
 // Tuned launches are kept per (size bucket, scheme).
 int tuned_key(int64_t total, const chem_opts* o) {
-  return size_bucket(total) * 2 + ((o && o->scheme == SCHEME_RKF45) ? 1 : 0);
+  return size_bucket(total) * 4 + (o ? o->scheme : SCHEME_LSRK);
 }
 
 int pick_tail(chem_mech m, int64_t total, const chem_opts* o) {
@@ -890,6 +939,8 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
   if (m->entry->lds_per_lane() * block > 65536)
     return fail(CHEM_EINVAL, "block_size too large for this mechanism's LDS compaction slots");
   if (a.total > 0x7fffffff) return fail(CHEM_EINVAL, "more than 2^31-1 work items in one call");
+  int rc0 = check_scheme_launch(m, o, block);
+  if (rc0) return rc0;
   a.next = next;
   a.chunk = chunk > 0 ? chunk : kDefaultChunk;
   a.tail_steps = pick_tail(m, a.total, o);
@@ -1117,6 +1168,8 @@ int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, doub
   int block, chunk;
   pick_launch(m, n_cells, opts, &block, &chunk);
   if (chunk < 0) {
+    rc = check_scheme_launch(m, opts, block);
+    if (rc) return rc;
     hipError_t e = m->entry->launch_direct(a, block, s);
     if (e != hipSuccess) return hip_fail(e, "launch lsrk_direct");
     return CHEM_OK;
@@ -1210,6 +1263,8 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   pick_launch(m, total, opts, &block, &chunk);
   if (m->entry->lds_per_lane() * block > 65536)
     return fail(CHEM_EINVAL, "block_size too large for this mechanism's LDS compaction slots");
+  rc = check_scheme_launch(m, opts, block);
+  if (rc) return rc;
   chem_graph g = new (std::nothrow) chem_graph_s();
   if (!g) return fail(CHEM_ENOMEM, "chem_graph_capture_batched: host allocation");
   auto bail = [&](hipError_t e, const char* what) {
@@ -1298,7 +1353,9 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   char key[160];
   snprintf(key, sizeof key, "%016llx:%d:%s%s", (unsigned long long)m->entry->hash, bucket,
            arch_name(m->device).c_str(),
-           (base && base->scheme == SCHEME_RKF45) ? ":rkf45" : "");
+           (base && base->scheme == SCHEME_RKF45)  ? ":rkf45"
+           : (base && base->scheme == SCHEME_ROS4) ? ":ros4"
+                                                   : "");
   chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<TuneEntry> cache;
   if (cache_path) {
@@ -1372,6 +1429,7 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   const bool tune_cap = tune_tail && o.tail_cap == 0;
   auto consider = [&](int b, int c, int tl, int cap) -> int {
     if (m->entry->lds_per_lane() * b > 65536) return CHEM_OK;
+    if (o.scheme == SCHEME_ROS4 && b > 256) return CHEM_OK;
     chem_opts t = o;
     t.block_size = b;
     t.chunk_steps = c;
