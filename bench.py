@@ -75,8 +75,8 @@ def parse():
 # reads for the restore copy of known size in the same run (FETCH_SIZE
 # reports 0.5002 of the copied bytes, WRITE_SIZE 1.000).  Keyed by a digest of
 # the kernel sources the counters were taken on; any change nulls it.
-TRAFFIC = {"front": ("ade5cec27b6939e7", 218.3e6),
-           "stress9": ("ade5cec27b6939e7", 3182.7e6)}
+TRAFFIC = {"front": ("ceccbd054f9c2546", 218.4e6),
+           "stress9": ("ceccbd054f9c2546", 3181.7e6)}
 
 
 def kernel_digest():
