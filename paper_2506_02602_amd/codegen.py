@@ -6,8 +6,11 @@ a ``__device__`` right-hand side of the chemistry ODE (paper Eq. 20 with the
 source of Eq. 14-16) in which every stoichiometric coefficient, Arrhenius
 parameter and NASA-7 coefficient is a literal:
 
-* thermo (Eq. 10 fits): per species cp/R, h/RT and g/RT = h/RT - s/R in Horner
-  form, with a wave-coherent branch on T < Tmid (one branch per distinct Tmid);
+* thermo (Eq. 10 fits): per species cp/R, h/RT and g/RT = h/RT - s/R as sums
+  over the shared powers T, T^2, T^3, T^4 (each multiply-add takes one
+  coefficient from a scalar register; a Horner chain costs two vector moves
+  per coefficient for its accumulator), with a wave-coherent branch on
+  T < Tmid (one branch per distinct Tmid);
 * forward rate k_f = exp(ln A + b ln T - Ea/(R T)), reverse rate
   k_r = k_f / K_c computed as exp(ln k_f + sum_k nu_k g_k/RT - dnu ln(P/(R T)))
   (the exponential is the device's own ``exp_cw``, within 1 ulp);
@@ -110,16 +113,27 @@ def _horner(coefs, var):
     return expr
 
 
+def _powsum(coefs):
+    """coefs[0] + coefs[1] T + coefs[2] T^2 + ... from the shared powers
+    T, T2, T3, T4, accumulated from the highest power down with the constant
+    term last: every multiply-add takes one coefficient (a scalar register)
+    and one power, so no coefficient has to be copied into a vector
+    register as the running accumulator of a Horner chain would need."""
+    pw = ["", "T", "T2", "T3", "T4"]
+    terms = [f"{lit(c)} * {pw[i]}" for i, c in reversed(list(enumerate(coefs))) if i > 0]
+    return " + ".join(terms + [lit(coefs[0])])
+
+
 def _thermo_block(species, idx, rng, suffix="", den="den"):
     out = []
     for k in idx:
         a = species[k][rng]
         # h/RT = a1 + a2 T/2 + a3 T^2/3 + a4 T^3/4 + a5 T^4/5 + a6/T
-        h = _horner([a[0], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5], "T")
+        h = _powsum([a[0], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5])
         # g/RT = h/RT - s/R = a1 (1 - ln T) - (a2 T/2 + a3 T^2/6 + a4 T^3/12 + a5 T^4/20) + a6/T - a7
-        gp = _horner([a[1] / 2, a[2] / 6, a[3] / 12, a[4] / 20], "T")
+        gp = _powsum([a[1] / 2, a[2] / 6, a[3] / 12, a[4] / 20])
         # c_k (cp_k/R - 1), cp/R = a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4
-        out.append(f"    {den} += c{k} * ({_horner([a[0] - 1.0] + list(a[1:5]), 'T')});")
+        out.append(f"    {den} += c{k} * ({_powsum([a[0] - 1.0] + list(a[1:5]))});")
         decl = "const double " if suffix else ""
         out.append(f"    {decl}h{k}{suffix} = {h} + {lit(a[5])} * invT;")
         out.append(f"    {decl}g{k}{suffix} = {lit(a[0])} * omlnT - T * ({gp}) + {lit(a[5])} * invT - {lit(a[6])};")
@@ -175,6 +189,7 @@ def gen_rhs(m: dict) -> str:
     L.append("    const double lnT = log(T);")
     L.append("    const double invT = 1.0 / T;")
     L.append("    const double omlnT = 1.0 - lnT;")
+    L.append("    const double T2 = T * T, T3 = T2 * T, T4 = T2 * T2;")
     L.append(f"    const double lnPRT = {lit(math.log(m['pstd'] / R_CGS))} - lnT;")
     for k, s in enumerate(sp):
         L.append(f"    const double c{k} = u[{k + 1}] * (rho * {lit(1.0 / s['W'])});")
