@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--tail-cap", type=int, default=0,
                     help="most handed-over cells per CU the cooperative kernel takes "
                          "(0 = default, < 0 = no limit)")
+    ap.add_argument("--pool-order", type=int, default=0,
+                    help="deal cells expected to be slow over the first claims (1), keep the "
+                         "pool order (-1), or the tuned choice (0)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--workload", default="front",
@@ -304,7 +307,7 @@ def main():
     chemgpu.chem_workspace_reserve(mech, n)
     base = chemgpu.make_opts(rtol=wl.RTOL, atol=wl.ATOL, chunk_steps=args.chunk,
                              block_size=args.block, tail_steps=args.tail, scheme=args.scheme,
-                             tail_cap=args.tail_cap)
+                             tail_cap=args.tail_cap, pool_order=args.pool_order)
     stream = torch.cuda.current_stream()
 
     def restore():
@@ -320,7 +323,8 @@ def main():
         tb = chemgpu.chem_autotune(mech, boxes, base, reps=3 if n <= 2_000_000 else 1,
                                    cache_path=cache)
         tuned = {"block_size": tb.block_size, "chunk_steps": tb.chunk_steps,
-                 "tail_steps": tb.tail_steps, "tail_cap": tb.tail_cap}
+                 "tail_steps": tb.tail_steps, "tail_cap": tb.tail_cap,
+                 "pool_order": tb.pool_order}
     log(f"launch {tuned}; untimed pass with per-cell counters")
     # one untimed pass with per-cell counters for the flop count
     restore()
@@ -368,7 +372,7 @@ def main():
                    "cells": n, "boxes": len(boxes),
                    "scheme": args.scheme,
                    "chunk_steps": args.chunk, "block_size": args.block, "tail_steps": args.tail,
-                   "tail_cap": args.tail_cap,
+                   "tail_cap": args.tail_cap, "pool_order": args.pool_order,
                    "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,

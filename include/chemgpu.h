@@ -75,6 +75,13 @@ typedef struct {
                             and run with block_size <= 256 (CHEM_EINVAL otherwise) */
     int32_t tail_cap;    /* most handed-over cells per CU that the cooperative kernel takes
                             (see tail_steps): 0 = tuned default, else 64; < 0 = no limit */
+    int32_t pool_order;  /* > 0: before the step, cells expected to take many steps (a step
+                            hint below dt/8 over the flow step, or without a usable hint
+                            T >= 1000 K) are dealt round-robin over the first work claim of
+                            every resident block, so they start at once and spread over the
+                            chip; < 0: pool order as laid out; 0: tuned default, else off.
+                            Changes no result (cells are independent); uses 8 bytes of
+                            workspace per cell */
 } chem_opts;
 
 /*
@@ -99,8 +106,8 @@ int chem_mech_query(chem_mech m, int32_t *n_species, int32_t *n_reactions, uint6
 /* Release a mechanism and its workspace (destroy its graphs first). */
 void chem_mech_free(chem_mech m);
 
-/* Reserve the device workspace (work queue, per-cell progress) for up to
- * max_cells cells.  All device allocation of the integrate calls happens here
+/* Reserve the device workspace (work queue, per-cell progress, tail records,
+ * pool order) for up to max_cells cells.  All device allocation of the integrate calls happens here
  * or, if never called, on the first integrate call that needs it. */
 int chem_workspace_reserve(chem_mech m, int64_t max_cells);
 
@@ -195,7 +202,8 @@ void chem_graph_destroy(chem_graph g);
  * block, then, if base->tail_steps is 0, tail_steps in {8, 16, 32, 64, 128,
  * 256, 512, never} for the best pair, and, if base->tail_cap is 0 too, the
  * pairs of tail_steps in {8, 16, 32, 64} and tail_cap in {64, 128, 256, no
- * limit}.  Each candidate is timed with HIP events on
+ * limit}, then, if base->pool_order is 0, the dealt pool order on, then
+ * chunk once more at the final choice.  Each candidate is timed with HIP events on
  * `stream` (median of `reps` launches after one untimed launch) on the
  * caller's boxes; the boxes' states are snapshotted first and restored
  * after every trial and at the end, so the caller's data is left unchanged.  The

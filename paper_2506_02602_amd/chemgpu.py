@@ -34,7 +34,8 @@ class chem_opts(C.Structure):
                 ("fixed_steps", C.c_int32),
                 ("tail_steps", C.c_int32),
                 ("scheme", C.c_int32),
-                ("tail_cap", C.c_int32)]
+                ("tail_cap", C.c_int32),
+                ("pool_order", C.c_int32)]
 
 
 class chem_box(C.Structure):
@@ -103,9 +104,10 @@ SCHEMES = {"lsrk": 0, "rkf45": 1, "ros4": 2}
 
 
 def make_opts(rtol=0.0, atol=0.0, max_steps=0, chunk_steps=0, block_size=0, fixed_steps=0,
-              tail_steps=0, scheme="lsrk", tail_cap=0):
+              tail_steps=0, scheme="lsrk", tail_cap=0, pool_order=0):
     return chem_opts(rtol, atol, max_steps, chunk_steps, block_size, fixed_steps, tail_steps,
-                     SCHEMES[scheme] if isinstance(scheme, str) else int(scheme), tail_cap)
+                     SCHEMES[scheme] if isinstance(scheme, str) else int(scheme), tail_cap,
+                     pool_order)
 
 
 class Mechanism:

@@ -83,7 +83,8 @@ struct PoolArgs {
   int tail_steps;              // > 0: a cell that has taken this many steps moves to the tail
   TailBuf tail;
   int resume;                  // 1: the work items are tail records, resumed one per lane
-  int scheme;                  // SCHEME_LSRK or SCHEME_RKF45
+  int scheme;                  // SCHEME_LSRK, SCHEME_RKF45 or SCHEME_ROS4
+  const int32_t* order;        // NULL, or pool position -> work item (order_place)
 };
 
 __device__ __forceinline__ int find_box(const PoolArgs& a, int64_t g) {
@@ -225,6 +226,126 @@ __global__ __launch_bounds__(1024) void tail_order(TailBuf tb) {
     tb.order[atomicAdd(&off[tb.key[r]], 1u)] = (int32_t)r;
 }
 
+// Pool order.  Blocks claim work items in pool order, so cells that need
+// many steps but sit late in the pool (a hot band in the middle of a field)
+// start late, and cells that sit together land in a few blocks.  With
+// ordering on, "heavy" cells are dealt round-robin over the first claim of
+// every resident block (R claims of B items): claim c gets heavy items
+// c, c + R, c + 2R, ... at its start and light items fill the rest, in pool
+// order (runs of up to 64 consecutive cells stay together, so loads stay
+// coalesced); everything after the first R*B positions keeps pool order.
+// A cell is heavy when its step hint promises at least kHeavySteps steps
+// over its flow step, or, without a usable hint (h <= 0 or h >= dt), when
+// it is at least kHeavyT hot (below that the chemistry is slow).  The order
+// changes no result: each cell's integration is independent of when and
+// where it runs.  Skipped (identity) when nothing is heavy, when heavy
+// cells are more than half of the first round, or when the pool is smaller
+// than one round.
+constexpr double kHeavySteps = 8.0;
+constexpr double kHeavyT = 1000.0;
+
+struct OrderBuf {
+  int32_t* rank;          // per item: rank among heavy (>= 0) or -(rank among light) - 1
+  int32_t* order;         // pool position -> item
+  unsigned int* counts;   // [0] heavy, [1] light (zeroed before order_rank)
+};
+
+__global__ void order_reset(unsigned int* counts) {
+  counts[0] = 0u;
+  counts[1] = 0u;
+}
+
+// Classify every item and rank it within its class.  One 1024-lane block
+// takes kOrderRounds * 1024 consecutive items: wave ballots count each
+// class, one lane turns the per-wave counts into offsets in pool order and
+// takes the block's two ranges with one atomic each, so the ranks keep pool
+// order within the block and the counters see a few hundred atomics (one
+// per wave would serialise tens of thousands on two addresses).
+constexpr int kOrderRounds = 4;
+constexpr int kOrderBlock = 1024;
+
+__global__ __launch_bounds__(kOrderBlock) void order_rank(PoolArgs a, int ns, OrderBuf ob) {
+  constexpr int W = kOrderBlock / 64;
+  __shared__ unsigned int off_h[kOrderRounds][W], off_l[kOrderRounds][W];
+  __shared__ unsigned int base_h, base_l;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t first = (int64_t)blockIdx.x * kOrderBlock * kOrderRounds;
+  bool heavy[kOrderRounds];
+  unsigned long long bh[kOrderRounds], bl[kOrderRounds];
+#pragma unroll
+  for (int r = 0; r < kOrderRounds; ++r) {
+    const int64_t g = first + (int64_t)r * kOrderBlock + threadIdx.x;
+    const bool valid = g < a.total;
+    heavy[r] = false;
+    if (valid) {
+      const BoxDesc& bd = box_ref(a, find_box(a, g));
+      const int64_t i = cell_index(bd, g);
+      const double T = bd.state[i];
+      const double h = bd.state[(int64_t)(ns + 2) * bd.ld + i];
+      heavy[r] = (h > 0.0 && h < bd.dt) ? (double)bd.n_sub * bd.dt >= kHeavySteps * h
+                                        : T >= kHeavyT;
+    }
+    bh[r] = __ballot(valid && heavy[r]);
+    bl[r] = __ballot(valid && !heavy[r]);
+    if (lane == 0) {
+      off_h[r][wave] = (unsigned int)__popcll(bh[r]);
+      off_l[r][wave] = (unsigned int)__popcll(bl[r]);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int th = 0u, tl = 0u;
+    for (int r = 0; r < kOrderRounds; ++r)
+      for (int w = 0; w < W; ++w) {
+        const unsigned int xh = off_h[r][w], xl = off_l[r][w];
+        off_h[r][w] = th;
+        off_l[r][w] = tl;
+        th += xh;
+        tl += xl;
+      }
+    base_h = th ? atomicAdd(&ob.counts[0], th) : 0u;
+    base_l = tl ? atomicAdd(&ob.counts[1], tl) : 0u;
+  }
+  __syncthreads();
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < kOrderRounds; ++r) {
+    const int64_t g = first + (int64_t)r * kOrderBlock + threadIdx.x;
+    if (g >= a.total) continue;
+    ob.rank[g] = heavy[r]
+                     ? (int32_t)(base_h + off_h[r][wave] + (unsigned int)__popcll(bh[r] & below))
+                     : -(int32_t)(base_l + off_l[r][wave] + (unsigned int)__popcll(bl[r] & below)) - 1;
+  }
+}
+
+// Position of every item in the dealt order (a bijection of [0, total)).
+__global__ __launch_bounds__(256) void order_place(int64_t total, int R, int B, OrderBuf ob) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int64_t H = ob.counts[0];
+  const int64_t RB = (int64_t)R * B;
+  int64_t q = g;
+  if (H > 0 && 2 * H <= RB && total >= RB) {
+    const int64_t r = ob.rank[g];
+    const int64_t hq = H / R, hr = H % R;
+    if (r >= 0) {
+      q = (r % R) * B + r / R;
+    } else {
+      const int64_t p = -r - 1;
+      const int64_t w1 = B - hq - 1, w0 = B - hq;  // light slots of claims c < hr, c >= hr
+      if (p < hr * w1) {
+        q = (p / w1) * B + hq + 1 + p % w1;
+      } else if (p < RB - H) {
+        const int64_t pp = p - hr * w1;
+        q = (hr + pp / w0) * B + hq + pp % w0;
+      } else {
+        q = p + H;
+      }
+    }
+  }
+  if (q >= 0 && q < total) ob.order[q] = (int32_t)g;
+}
+
 template <class M, int LB, int S>
 __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   constexpr int N1 = M::NS + 1;
@@ -274,10 +395,13 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
         nacc = a.tail.nacc[g]; nrej = a.tail.nrej[g];
         sub = a.tail.sub[g]; base = a.tail.base[g];
       } else if (g < total) {
-        item = g;
-        bx = find_box(a, g);
+        item = a.order ? (int64_t)a.order[g] : g;
+        if (item < 0 || item >= total) item = -1;
+      }
+      if (item >= 0 && !a.resume) {
+        bx = find_box(a, item);
         const BoxDesc& bd = box_ref(a, bx);
-        const int64_t i = cell_index(bd, g);
+        const int64_t i = cell_index(bd, item);
         load_cell<M>(bd, i, u, rho, h);
         nacc = nrej = 0; sub = 0; base = 0; t = 0.0;
         if (!all_finite(u, rho)) {
@@ -759,10 +883,27 @@ struct TailStore {
   static size_t bytes(int64_t cap) { return 16 + (size_t)cap * (sizeof(double) + 7 * sizeof(int32_t)); }
 };
 
+// Device storage of the pool order (see OrderBuf): rank and order arrays of
+// cap entries and the two class counters, one allocation.
+struct OrderStore {
+  void* mem = nullptr;
+  int64_t cap = 0;
+  OrderBuf view() const {
+    OrderBuf b{};
+    char* p = static_cast<char*>(mem);
+    b.counts = reinterpret_cast<unsigned int*>(p);
+    b.rank = reinterpret_cast<int32_t*>(p + 16);
+    b.order = b.rank + cap;
+    return b;
+  }
+  static size_t bytes(int64_t cap) { return 16 + (size_t)cap * 2 * sizeof(int32_t); }
+};
+
 struct chem_mech_s {
   const MechEntry* entry;
   TailStore tail;
-  struct Tuned { int block, chunk, tail, cap; };
+  OrderStore order;
+  struct Tuned { int block, chunk, tail, cap, order; };
   std::map<int, Tuned> tuned;  // (size bucket, scheme) -> tuned launch
   unsigned long long* d_next = nullptr;
   BoxDesc* d_boxes = nullptr;
@@ -779,6 +920,7 @@ struct chem_mech_s {
 
 struct chem_graph_s {
   TailStore tail;
+  OrderStore order;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   BoxDesc* d_boxes = nullptr;
@@ -806,6 +948,21 @@ int ensure_tail(TailStore& ts, int64_t cap) {
   hipError_t e = hipMalloc(&ts.mem, TailStore::bytes(cap));
   if (e != hipSuccess) { ts.mem = nullptr; return hip_fail(e, "hipMalloc(tail records)"); }
   ts.cap = cap;
+  return CHEM_OK;
+}
+
+int ensure_order(OrderStore& os, int64_t cap) {
+  if (cap <= os.cap) return CHEM_OK;
+  if (os.mem) {
+    hipError_t e = hipDeviceSynchronize();  // a queued call may still use the old arrays
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(pool order)");
+    hipFree(os.mem);
+  }
+  os.mem = nullptr;
+  os.cap = 0;
+  hipError_t e = hipMalloc(&os.mem, OrderStore::bytes(cap));
+  if (e != hipSuccess) { os.mem = nullptr; return hip_fail(e, "hipMalloc(pool order)"); }
+  os.cap = cap;
   return CHEM_OK;
 }
 
@@ -886,6 +1043,17 @@ int pick_tail(chem_mech m, int64_t total, const chem_opts* o) {
 constexpr int kDefaultTailCap = 64;
 
 // Most handed-over cells the cooperative kernel takes, over the whole chip.
+// Pool order on (dealt heavy cells) or off: chem_opts.pool_order > 0 / < 0,
+// else the tuned choice, else off.
+bool pick_order(chem_mech m, int64_t total, const chem_opts* o) {
+  int v = o ? o->pool_order : 0;
+  if (v == 0) {
+    auto it = m->tuned.find(tuned_key(total, o));
+    v = it != m->tuned.end() ? it->second.order : 0;
+  }
+  return v > 0;
+}
+
 int pick_cap(chem_mech m, int64_t total, const chem_opts* o) {
   int c = o ? o->tail_cap : 0;
   if (c == 0) {
@@ -915,8 +1083,22 @@ int grid_for(chem_mech m, int block, int64_t total, int scheme);
 // the per-lane resumption of the list (exactly one of the last two does
 // work, chosen by the list's length against a.tail.cap: several lanes per
 // cell only pay while the tail is short next to the chip).
-hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_t s) {
-  hipError_t e = m->entry->launch_persistent(a, block, grid, s);
+hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_t s,
+                       const OrderBuf* ob) {
+  hipError_t e;
+  a.order = nullptr;
+  if (ob && a.total > 0 && !a.total_dev && !a.resume) {
+    // the dealt pool order: R = the resident blocks (the grid), B = block
+    const int64_t per = (int64_t)kOrderBlock * kOrderRounds;
+    const unsigned rg = (unsigned)((a.total + per - 1) / per);
+    const unsigned og = (unsigned)((a.total + 255) / 256);
+    hipLaunchKernelGGL(order_reset, dim3(1), dim3(1), 0, s, ob->counts);
+    hipLaunchKernelGGL(order_rank, dim3(rg), dim3(kOrderBlock), 0, s, a, m->entry->ns, *ob);
+    hipLaunchKernelGGL(order_place, dim3(og), dim3(256), 0, s, a.total, grid, block, *ob);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    a.order = ob->order;
+  }
+  e = m->entry->launch_persistent(a, block, grid, s);
   if (e != hipSuccess || a.tail_steps <= 0) return e;
   hipLaunchKernelGGL(tail_order, dim3(1), dim3(1024), 0, s, a.tail);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -927,13 +1109,14 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
   r.tail_steps = 0;
   r.next = a.tail.next;
   r.total_dev = nullptr;
+  r.order = nullptr;
   return m->entry->launch_persistent(r, block, grid, s);
 }
 
 // The integrator over a work pool with a given pool counter and tail store
 // (calls that may run concurrently on one mechanism each bring their own).
 int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
-                  unsigned long long* next, TailStore& tail) {
+                  unsigned long long* next, TailStore& tail, OrderStore* order) {
   int block, chunk;
   pick_launch(m, a.total, o, &block, &chunk);
   if (m->entry->lds_per_lane() * block > 65536)
@@ -950,7 +1133,15 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
     a.tail = tail.view();
     a.tail.cap = pick_cap(m, a.total, o);
   }
-  hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s);
+  OrderBuf ob{};
+  const bool ordered = order && !a.total_dev && pick_order(m, a.total, o);
+  if (ordered) {
+    int rc = ensure_order(*order, std::max<int64_t>(a.total, m->reserved));
+    if (rc) return rc;
+    ob = order->view();
+  }
+  hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s,
+                             ordered ? &ob : nullptr);
   if (e != hipSuccess) return hip_fail(e, "launch integrator kernels");
   return CHEM_OK;
 }
@@ -958,7 +1149,7 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
 int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
   int rc = ensure_pool(m);
   if (rc) return rc;
-  return run_pool_with(m, a, o, s, m->d_next, m->tail);
+  return run_pool_with(m, a, o, s, m->d_next, m->tail, &m->order);
 }
 
 int grid_for(chem_mech m, int block, int64_t total, int scheme) {
@@ -1000,7 +1191,7 @@ std::string arch_name(int device) {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-struct TuneEntry { std::string key; int block, chunk, tail, cap; double ms; };
+struct TuneEntry { std::string key; int block, chunk, tail, cap, order; double ms; };
 
 std::vector<TuneEntry> read_cache(const char* path) {
   std::vector<TuneEntry> v;
@@ -1017,15 +1208,17 @@ std::vector<TuneEntry> read_cache(const char* path) {
     pos += tag.size();
     const size_t end = txt.find('"', pos);
     if (end == std::string::npos) break;
-    TuneEntry e{txt.substr(pos, end - pos), 0, 0, 0, 0, 0.0};
+    TuneEntry e{txt.substr(pos, end - pos), 0, 0, 0, 0, 0, 0.0};
     const size_t close = txt.find('}', end);
     const std::string rec = txt.substr(end, close == std::string::npos ? std::string::npos : close - end);
     const size_t pb = rec.find("\"block\":"), pc = rec.find("\"chunk\":"), pm = rec.find("\"ms\":");
     const size_t pt = rec.find("\"tail\":"), pk = rec.find("\"cap\":");
+    const size_t po = rec.find("\"order\":");
     if (pb != std::string::npos) e.block = atoi(rec.c_str() + pb + 8);
     if (pc != std::string::npos) e.chunk = atoi(rec.c_str() + pc + 8);
     if (pt != std::string::npos) e.tail = atoi(rec.c_str() + pt + 7);
     if (pk != std::string::npos) e.cap = atoi(rec.c_str() + pk + 6);
+    if (po != std::string::npos) e.order = atoi(rec.c_str() + po + 8);
     if (pm != std::string::npos) e.ms = atof(rec.c_str() + pm + 5);
     if (e.block > 0 && e.chunk != 0) v.push_back(e);
     pos = end;
@@ -1041,8 +1234,8 @@ int write_cache(const char* path, const std::vector<TuneEntry>& v) {
   for (size_t i = 0; i < v.size(); ++i)
     fprintf(f,
             "  {\"key\": \"%s\", \"block\": %d, \"chunk\": %d, \"tail\": %d, \"cap\": %d, "
-            "\"ms\": %.6f}%s\n",
-            v[i].key.c_str(), v[i].block, v[i].chunk, v[i].tail, v[i].cap, v[i].ms,
+            "\"order\": %d, \"ms\": %.6f}%s\n",
+            v[i].key.c_str(), v[i].block, v[i].chunk, v[i].tail, v[i].cap, v[i].order, v[i].ms,
             i + 1 < v.size() ? "," : "");
   fprintf(f, "]}\n");
   fclose(f);
@@ -1132,6 +1325,7 @@ void chem_mech_free(chem_mech m) {
   if (m->boxes_copied) { hipEventSynchronize(m->boxes_copied); hipEventDestroy(m->boxes_copied); }
   if (m->d_next) hipFree(m->d_next);
   if (m->tail.mem) hipFree(m->tail.mem);
+  if (m->order.mem) hipFree(m->order.mem);
   if (m->d_prim) hipFree(m->d_prim);
   if (m->d_flag) hipFree(m->d_flag);
   if (m->d_boxes) hipFree(m->d_boxes);
@@ -1144,7 +1338,9 @@ int chem_workspace_reserve(chem_mech m, int64_t max_cells) {
   int rc = ensure_pool(m);
   if (rc) return rc;
   m->reserved = std::max(m->reserved, max_cells);
-  return ensure_tail(m->tail, m->reserved);
+  rc = ensure_tail(m->tail, m->reserved);
+  if (rc) return rc;
+  return ensure_order(m->order, m->reserved);
 }
 
 int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, double dt,
@@ -1280,6 +1476,11 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
     rc = ensure_tail(g->tail, total);
     if (rc) { chem_graph_destroy(g); return rc; }
   }
+  const bool ordered = pick_order(m, total, opts);
+  if (ordered) {
+    rc = ensure_order(g->order, total);
+    if (rc) { chem_graph_destroy(g); return rc; }
+  }
   e = hipMemcpy(g->d_boxes, table.data(), sizeof(BoxDesc) * table.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(e, "hipMemcpy(graph box table)");
   if (stream) {
@@ -1307,7 +1508,8 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   if (e != hipSuccess) return bail(e, "hipStreamCreate(capture)");
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) { hipStreamDestroy(cs); return bail(e, "hipStreamBeginCapture"); }
-  hipError_t le = launch_step(m, a, block, grid, cs);
+  OrderBuf ob = ordered ? g->order.view() : OrderBuf{};
+  hipError_t le = launch_step(m, a, block, grid, cs, ordered ? &ob : nullptr);
   e = hipStreamEndCapture(cs, &g->graph);
   hipStreamDestroy(cs);
   if (le != hipSuccess) return bail(le, "launch integrator kernels (capture)");
@@ -1333,6 +1535,7 @@ void chem_graph_destroy(chem_graph g) {
   if (g->d_boxes) hipFree(g->d_boxes);
   if (g->d_next) hipFree(g->d_next);
   if (g->tail.mem) hipFree(g->tail.mem);
+  if (g->order.mem) hipFree(g->order.mem);
   delete g;
 }
 
@@ -1356,16 +1559,16 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
            (base && base->scheme == SCHEME_RKF45)  ? ":rkf45"
            : (base && base->scheme == SCHEME_ROS4) ? ":ros4"
                                                    : "");
-  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0, 0, 0};
+  chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<TuneEntry> cache;
   if (cache_path) {
     cache = read_cache(cache_path);
     for (const auto& en : cache)
       if (en.key == key) {
-        m->tuned[tkey] = {en.block, en.chunk, en.tail, en.cap};
+        m->tuned[tkey] = {en.block, en.chunk, en.tail, en.cap, en.order};
         if (best) {
           *best = o; best->block_size = en.block; best->chunk_steps = en.chunk;
-          best->tail_steps = en.tail; best->tail_cap = en.cap;
+          best->tail_steps = en.tail; best->tail_cap = en.cap; best->pool_order = en.order;
         }
         return CHEM_OK;
       }
@@ -1414,8 +1617,8 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   // chunk, chunk again at the best block, then the hand-off point for the
   // best pair, then hand-off point and cooperative cap together (an early
   // hand-off only pays when the cap lets the cooperative kernel take the
-  // longer list).  Each sweep keeps the incumbent unless a candidate is
-  // faster.
+  // longer list), then chunk once more.  Each sweep keeps the incumbent
+  // unless a candidate is faster.
   const int blocks[] = {64, 128, 192, 256, 384, 512};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
   const int tails[] = {8, 16, 32, 64, 128, 256, 512, -1};
@@ -1425,9 +1628,10 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
   int best_tail = o.tail_steps != 0 ? o.tail_steps : kDefaultTail;
   int best_cap = o.tail_cap != 0 ? o.tail_cap : kDefaultTailCap;
+  int best_order = o.pool_order != 0 ? o.pool_order : -1;
   const bool tune_tail = o.tail_steps == 0 && o.fixed_steps == 0 && o.scheme == SCHEME_LSRK;
   const bool tune_cap = tune_tail && o.tail_cap == 0;
-  auto consider = [&](int b, int c, int tl, int cap) -> int {
+  auto consider = [&](int b, int c, int tl, int cap, int ord) -> int {
     if (m->entry->lds_per_lane() * b > 65536) return CHEM_OK;
     if (o.scheme == SCHEME_ROS4 && b > 256) return CHEM_OK;
     chem_opts t = o;
@@ -1435,34 +1639,49 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     t.chunk_steps = c;
     t.tail_steps = tl;
     t.tail_cap = cap;
+    t.pool_order = ord;
     double med = 0;
     const int trc = trial(t, &med);
     if (trc != CHEM_OK) return trc;
     if (med < best_ms) {
       best_ms = med; best_block = b; best_chunk = c; best_tail = tl; best_cap = cap;
+      best_order = ord;
     }
     return CHEM_OK;
   };
   rc = CHEM_OK;
+  const int o0 = best_order;
   for (int c : chunks)
-    if (rc == CHEM_OK) rc = consider(best_block, c, best_tail, best_cap);
+    if (rc == CHEM_OK) rc = consider(best_block, c, best_tail, best_cap, o0);
   for (int b : blocks)
-    if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail, best_cap);
+    if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail, best_cap, o0);
   {
     const int b0 = best_block;
     for (int c : chunks)
-      if (rc == CHEM_OK && c != best_chunk) rc = consider(b0, c, best_tail, best_cap);
+      if (rc == CHEM_OK && c != best_chunk) rc = consider(b0, c, best_tail, best_cap, o0);
   }
   if (tune_tail) {
     const int b0 = best_block, c0 = best_chunk, t0 = best_tail;
     for (int tl : tails)
-      if (rc == CHEM_OK && tl != t0) rc = consider(b0, c0, tl, best_cap);
+      if (rc == CHEM_OK && tl != t0) rc = consider(b0, c0, tl, best_cap, o0);
   }
   if (tune_cap) {
     const int b0 = best_block, c0 = best_chunk, t0 = best_tail, k0 = best_cap;
     for (int tl : pair_tails)
       for (int cap : caps)
-        if (rc == CHEM_OK && !(tl == t0 && cap == k0)) rc = consider(b0, c0, tl, cap);
+        if (rc == CHEM_OK && !(tl == t0 && cap == k0)) rc = consider(b0, c0, tl, cap, o0);
+  }
+  if (o.pool_order == 0 && o.fixed_steps == 0) {
+    // the dealt pool order, on, at the best launch so far
+    if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, 1);
+  }
+  {
+    // the hand-off and the order move the balance between compaction and
+    // the tail, so the chunk length is swept once more at the final choice
+    const int b0 = best_block, c0 = best_chunk, t0 = best_tail, k0 = best_cap;
+    const int ob0 = best_order;
+    for (int c : chunks)
+      if (rc == CHEM_OK && c != c0) rc = consider(b0, c, t0, k0, ob0);
   }
   if ((e = restore()) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "restore");
   hipStreamSynchronize(s);
@@ -1470,13 +1689,14 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   hipEventDestroy(e1);
   cleanup();
   if (rc != CHEM_OK) return rc;
-  m->tuned[tkey] = {best_block, best_chunk, best_tail, best_cap};
+  m->tuned[tkey] = {best_block, best_chunk, best_tail, best_cap, best_order};
   if (best) {
     *best = o; best->block_size = best_block; best->chunk_steps = best_chunk;
-    best->tail_steps = best_tail; best->tail_cap = best_cap;
+    best->tail_steps = best_tail; best->tail_cap = best_cap; best->pool_order = best_order;
   }
   if (cache_path) {
-    cache.push_back(TuneEntry{key, best_block, best_chunk, best_tail, best_cap, best_ms});
+    cache.push_back(TuneEntry{key, best_block, best_chunk, best_tail, best_cap, best_order,
+                              best_ms});
     rc = write_cache(cache_path, cache);
   }
   return rc;

@@ -494,7 +494,7 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
       if ((e = hipStreamWaitEvent(s->side, s->ev_fork, 0)) != hipSuccess)
         return hip_fail(e, "hipStreamWaitEvent");
       PoolArgs ph = fallback_args(s->hull_list, s->hull_count);
-      rc = run_pool_with(m, ph, opts, s->side, s->side_next, s->side_tail);
+      rc = run_pool_with(m, ph, opts, s->side, s->side_next, s->side_tail, nullptr);
       if (rc) return rc;
       if ((e = hipEventRecord(s->ev_join, s->side)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     }

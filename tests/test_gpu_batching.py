@@ -193,3 +193,52 @@ def test_full_amr_hierarchy_sampled(cg, gm9, omech9, mech9_path):
     print(f"[parity] full AMR: {checked} sampled cells, {flagged} flagged", flush=True)
     assert flagged <= 0.02 * checked
     g.close()
+
+
+@pytest.mark.parametrize("block,chunk,tail", [(512, 8, 32), (256, 2, 16), (128, 1, -1)])
+def test_pool_order_changes_no_result(cg, gm9, mech9_path, block, chunk, tail):
+    """Dealing the hot cells over the first claims (pool_order on) moves
+    cells between blocks and in time, never their arithmetic: state, status
+    and counts are bitwise those of the laid-out order, on the first call
+    (order from temperature) and on a second call (order from the step
+    hints the first one wrote).  The field is larger than one round of
+    claims, so the order is really dealt."""
+    import torch
+    from gpu_common import run_gpu
+    s0, hot = wl.front_2d(mech9_path, nx=512, ny=512, seed=61)
+    kw = dict(block_size=block, chunk_steps=chunk, tail_steps=tail)
+    off1 = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=-1, **kw)
+    on1 = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=1, **kw)
+    assert all(np.array_equal(x, y) for x, y in zip(off1, on1))
+    s1 = off1[0]                                   # carries the hints of the first call
+    off2 = run_gpu(gm9, s1, wl.DT_FLOW, pool_order=-1, **kw)
+    on2 = run_gpu(gm9, s1, wl.DT_FLOW, pool_order=1, **kw)
+    assert all(np.array_equal(x, y) for x, y in zip(off2, on2))
+
+
+def test_pool_order_batched_and_graph(cg, gm9, mech9_path):
+    """The same with boxes of three levels (sub-calls, own dt) in one batched
+    call and in a captured graph replayed several times."""
+    import torch
+    hier = wl.amr_hierarchy(mech9_path, seed=62, boxes_per_level=(2, 3, 4), edges=(32, 48, 64))
+    ncells = sum(b["state"].shape[1] for b in hier)
+    assert ncells > 512 * 256
+    off = gpu_boxes(hier)
+    cg.chem_integrate_batched(gm9, off, cg.make_opts(pool_order=-1))
+    on = gpu_boxes(hier)
+    cg.chem_integrate_batched(gm9, on, cg.make_opts(pool_order=1))
+    torch.cuda.synchronize()
+    for x, y in zip(off, on):
+        assert torch.equal(x["state"], y["state"]) and torch.equal(x["counts"], y["counts"])
+        assert torch.equal(x["status"], y["status"])
+    boxes = gpu_boxes(hier)
+    pristine = [b["state"].clone() for b in boxes]
+    g = cg.chem_graph_capture_batched(gm9, boxes, cg.make_opts(pool_order=1))
+    for rep in range(3):
+        for b, p in zip(boxes, pristine):
+            b["state"].copy_(p)
+        g.launch()
+        torch.cuda.synchronize()
+        for b, e in zip(boxes, off):
+            assert torch.equal(b["state"], e["state"]), f"replay {rep}"
+    g.close()
