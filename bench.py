@@ -78,8 +78,8 @@ def parse():
 # reads for the restore copy of known size in the same run (FETCH_SIZE
 # reports 0.5002 of the copied bytes, WRITE_SIZE 1.000).  Keyed by a digest of
 # the kernel sources the counters were taken on; any change nulls it.
-TRAFFIC = {"front": ("ceccbd054f9c2546", 218.4e6),
-           "stress9": ("ceccbd054f9c2546", 3181.7e6)}
+TRAFFIC = {"front": ("c4aa770c865d6e8a", 233.6e6),
+           "stress9": ("c4aa770c865d6e8a", 2988.9e6)}
 
 
 def kernel_digest():
