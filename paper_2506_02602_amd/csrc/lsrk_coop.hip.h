@@ -29,6 +29,15 @@
 
 namespace chemgpu {
 
+// 1/x from the hardware reciprocal refined by two Newton steps (within an
+// ulp of the quotient for positive normal x).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 __device__ __forceinline__ void coop_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -125,7 +134,7 @@ __device__ __forceinline__ double coop_rhs(double Yk, double T, double rho, doub
   const bool sl = gl < N;
   const int k = sl ? gl : N - 1;
   const double lnT = log_atanh(T);
-  const double invT = 1.0 / T;
+  const double invT = rcp_nr(T);
   const double omlnT = 1.0 - lnT;
   const double lnPRT = C::LNPRT0 - lnT;
   // forward rates: depend on T only
@@ -213,7 +222,7 @@ __device__ __forceinline__ double coop_rhs(double Yk, double T, double rho, doub
   double num = 0.0;
 #pragma unroll
   for (int kk = 0; kk < N; ++kk) num += s[S::SW + kk];
-  fT = -T * num / den;
+  fT = -T * num * rcp_nr(den);
   return sl ? wk * (D[C::O_WK + k] * inv_rho) : 0.0;
 }
 
