@@ -553,8 +553,8 @@ def gen_coop(m: dict, tag: str) -> tuple[str, str]:
 
     ns = f"coop_{tag}"
     glob = [f"namespace {ns} {{",
-            f"__constant__ double D[{len(D)}] = {{" + ", ".join(lit(x) for x in D) + "};",
-            f"__constant__ int I[{len(I)}] = {{" + ", ".join(str(x) for x in I) + "};",
+            f"static __constant__ double D[{len(D)}] = {{" + ", ".join(lit(x) for x in D) + "};",
+            f"static __constant__ int I[{len(I)}] = {{" + ", ".join(str(x) for x in I) + "};",
             "}"]
     mem = ["  struct Coop {",
            f"    static constexpr int G = {coop_group(m)};",

@@ -30,108 +30,13 @@
 
 #include "chemgpu.h"
 #include "advance.hip.h"
-#include "lsrk_coop.hip.h"
+#include "pool.hip.h"
 
 using namespace chemgpu;
 
 #include "generated/registry.inc"
 
 namespace {
-
-struct BoxDesc {
-  double* state;
-  int64_t ld;
-  int64_t n;
-  int64_t start;  // first pool index of this block
-  double dt;
-  int32_t n_sub;
-  int32_t pad;
-  int32_t* status;
-  int32_t* counts;
-  const int32_t* index;  // NULL, or the cell index of each of this block's pool items
-};
-
-// Cells handed from the per-lane kernel to the cooperative one, as
-// structure-of-arrays records; the cell's (T, Y) and step hint at time t are
-// in its own state rows.
-struct TailBuf {
-  int32_t* item;          // pool index
-  double* t;              // time reached within the current sub-call
-  int32_t* nacc;
-  int32_t* nrej;
-  int32_t* sub;           // current sub-call
-  int32_t* base;          // steps taken before the current sub-call
-  int32_t* key;           // bucket of the cell's estimated remaining steps (tail_key)
-  int32_t* order;         // record indices, largest key first (tail_order)
-  unsigned int* count;    // records written (zeroed before launch)
-  unsigned long long* next;  // records claimed by whichever kernel finishes them (zeroed)
-  int cap;                // at most this many records go to the cooperative kernel; more
-                          // are resumed one per lane (the count decides, so the choice is
-                          // a function of the input only)
-};
-
-struct PoolArgs {
-  BoxDesc one;                 // used when boxes == nullptr
-  const BoxDesc* boxes;        // device table, sorted by start
-  int32_t n_boxes;
-  int64_t total;               // pool size
-  const unsigned int* total_dev;  // NULL, or a device word holding the pool size
-  unsigned long long* next;    // pool counter (zeroed before launch)
-  Control c;
-  int chunk;
-  int fixed_steps;
-  int tail_steps;              // > 0: a cell that has taken this many steps moves to the tail
-  TailBuf tail;
-  int resume;                  // 1: the work items are tail records, resumed one per lane
-  int scheme;                  // SCHEME_LSRK, SCHEME_RKF45 or SCHEME_ROS4
-  const int32_t* order;        // NULL, or pool position -> work item (order_place)
-};
-
-__device__ __forceinline__ int find_box(const PoolArgs& a, int64_t g) {
-  if (!a.boxes) return 0;
-  int lo = 0, hi = a.n_boxes - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.boxes[mid].start <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ const BoxDesc& box_ref(const PoolArgs& a, int b) {
-  return a.boxes ? a.boxes[b] : a.one;
-}
-
-__device__ __forceinline__ int64_t cell_index(const BoxDesc& bd, int64_t g) {
-  const int64_t j = g - bd.start;
-  return bd.index ? (int64_t)bd.index[j] : j;
-}
-
-template <class M>
-__device__ __forceinline__ void load_cell(const BoxDesc& bd, int64_t i, double (&u)[M::NS + 1],
-                                          double& rho, double& h) {
-  const double* s = bd.state;
-#pragma unroll
-  for (int v = 0; v <= M::NS; ++v) u[v] = s[v * bd.ld + i];
-  rho = s[(M::NS + 1) * bd.ld + i];
-  h = s[(M::NS + 2) * bd.ld + i];
-}
-
-template <class M>
-__device__ __forceinline__ void store_cell(const BoxDesc& bd, int64_t i, const double (&u)[M::NS + 1],
-                                           double h, int status, int nacc, int nrej) {
-  double* s = bd.state;
-  if (status != CELL_NONFINITE) {
-#pragma unroll
-    for (int v = 0; v <= M::NS; ++v) s[v * bd.ld + i] = u[v];
-    s[(M::NS + 2) * bd.ld + i] = h;
-  }
-  if (bd.status) bd.status[i] = status;
-  if (bd.counts) { bd.counts[i] = nacc; bd.counts[bd.n + i] = nrej; }
-}
-
-__device__ __forceinline__ double initial_h(double h, double dt) {
-  return (h > 0.0 && h < dt) ? h : dt;
-}
 
 // ------------------------------------------------------------ direct kernel
 template <class M, int LB, int S>
@@ -528,100 +433,6 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   }
 }
 
-// ------------------------------------------------------- cooperative kernel
-// Finishes the cells the persistent kernel handed over: each group of
-// Coop::G lanes claims tail records one at a time and integrates that cell
-// to the end of its flow step (all remaining sub-calls).  Grid-size
-// independent: a group exits once the records are used up.
-template <class M>
-size_t coop_lds_bytes(int block) {
-  using C = typename M::Coop;
-  return (size_t)C::ND * sizeof(double) + (size_t)C::NI * sizeof(int) +
-         (size_t)(block / C::G) * CoopScratch<M>::SIZE * sizeof(double);
-}
-
-template <class M>
-__global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
-  using C = typename M::Coop;
-  constexpr int G = C::G, N = M::NS;
-  static_assert(C::NI % 4 == 0 && C::ND % 2 == 0, "table padding");
-  extern __shared__ double smem[];
-  double* D = smem;
-  int* I = reinterpret_cast<int*>(smem + C::ND);
-  double* scr = smem + C::ND + C::NI / 2;
-  const unsigned int count = *a.tail.count;
-  if (count > (unsigned int)a.tail.cap) return;  // resumed one per lane instead
-  const int tid = threadIdx.x;
-  for (int i = tid; i < C::ND; i += blockDim.x) D[i] = C::dtab()[i];
-  for (int i = tid; i < C::NI; i += blockDim.x) I[i] = C::itab()[i];
-  const int gl = tid % G;
-  using S = CoopScratch<M>;
-  double* sgrp = scr + (tid / G) * S::SIZE;
-  if (gl == 0) {
-    sgrp[S::SC + N] = 1.0;
-    sgrp[S::SG + N] = 0.0;
-  }
-  __syncthreads();
-  const CoopCtx<M> x{D, I, sgrp, gl};
-  CoopLane<M, G> ln;
-  ln.load(D, I, gl);
-  // One step per iteration; a group whose cell finishes claims the next
-  // record at once instead of waiting for the other groups of its wave.
-  bool have = false;
-  double* st = nullptr;
-  int32_t* status = nullptr;
-  int32_t* counts = nullptr;
-  int64_t ld = 0, nbox = 0, i = 0;
-  double dt = 0.0;
-  int n_sub = 1;
-  double uT = 0.0, uk = 0.0, rho = 1.0, inv_rho = 1.0, h = 0.0, t = 0.0;
-  int nacc = 0, nrej = 0, sub = 0, base = 0;
-#pragma unroll 1
-  for (;;) {
-    if (!have) {
-      unsigned int r = 0;
-      if (gl == 0) r = (unsigned int)atomicAdd(a.tail.next, 1ull);
-      r = __shfl(r, 0, G);
-      if (r >= count) break;
-      r = (unsigned int)a.tail.order[r];
-      const int64_t item = a.tail.item[r];
-      {
-        const BoxDesc& bd = box_ref(a, find_box(a, item));
-        i = cell_index(bd, item);
-        st = bd.state; ld = bd.ld; nbox = bd.n; dt = bd.dt; n_sub = bd.n_sub;
-        status = bd.status; counts = bd.counts;
-      }
-      uT = st[i];
-      uk = gl < N ? st[(gl + 1) * ld + i] : 0.0;
-      rho = st[(N + 1) * ld + i];
-      inv_rho = 1.0 / rho;
-      h = st[(N + 2) * ld + i];
-      t = a.tail.t[r];
-      nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
-      sub = a.tail.sub[r]; base = a.tail.base[r];
-      have = true;
-    }
-    Control c = a.c;
-    c.max_steps = base + a.c.max_steps;
-    int code = coop_try_step<M, G>(uT, uk, rho, inv_rho, dt, t, h, nacc, nrej, c, x, ln);
-    if (code == CELL_OK && sub + 1 < n_sub) {
-      ++sub; t = 0.0; base = nacc + nrej;
-      h = initial_h(h, dt);
-      code = CELL_RUNNING;
-    }
-    if (code != CELL_RUNNING) {
-      if (gl < N) st[(gl + 1) * ld + i] = uk;
-      if (gl == 0) {
-        st[i] = uT;
-        st[(N + 2) * ld + i] = h;
-        if (status) status[i] = code;
-        if (counts) { counts[i] = nacc; counts[nbox + i] = nrej; }
-      }
-      have = false;
-    }
-  }
-}
-
 // ------------------------------------------- split-scheme coupling kernels
 // Conserved rows (paper Sec. 2.2.1, the reaction part of the Strang split):
 // rho, rho u, rho v, rho w, rho E, rho Y_1..rho Y_N, T, h.
@@ -772,17 +583,6 @@ hipError_t launch_persistent(const PoolArgs& a, int block, int grid, hipStream_t
   }
   return a.scheme == SCHEME_RKF45 ? launch_persistent_s<M, SCHEME_RKF45>(a, block, grid, s)
                                   : launch_persistent_s<M, SCHEME_LSRK>(a, block, grid, s);
-}
-
-// The cooperative kernel after the persistent one: enough 256-lane blocks to
-// put one group on every SIMD several times over; surplus groups exit at once.
-template <class M>
-hipError_t launch_coop(const PoolArgs& a, int n_cu, hipStream_t s) {
-  constexpr int kBlock = 256;
-  const size_t lds = coop_lds_bytes<M>(kBlock);
-  if (lds > 65536) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(lsrk_coop<M>, dim3(4 * n_cu), dim3(kBlock), lds, s, a);
-  return hipGetLastError();
 }
 
 template <class M>
