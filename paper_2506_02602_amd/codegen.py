@@ -449,13 +449,14 @@ COOP_TH = 18   # thermo table entries per (range, species), padded to 16-byte ro
 
 
 def coop_group(m: dict) -> int:
-    """Lanes that advance one cell together in the cooperative kernel: enough
-    for one lane per species and per reaction, 16..64."""
-    need = max(len(m["species"]), len(m["reactions"]))
-    g = 16
-    while g < need and g < 64:
-        g *= 2
-    return g
+    """Lanes that advance one cell together in the cooperative kernel: one
+    lane per species and per reaction, at most a wave (64; larger mechanisms
+    give a lane several reactions).  Groups need not divide the wave: a
+    wave holds floor(64 / G) groups, so the 21 reactions of the 9-species
+    mechanism put three cells in a wave (one lane spare) instead of two
+    with G rounded up to 32 -- the step's instruction stream is per lane,
+    so a wave's cost per step hardly depends on G."""
+    return min(64, max(len(m["species"]), len(m["reactions"])))
 
 
 def gen_coop(m: dict, tag: str) -> tuple[str, str]:

@@ -17,14 +17,16 @@ namespace {
 
 // ------------------------------------------------------- cooperative kernel
 // Finishes the cells the persistent kernel handed over: each group of
-// Coop::G lanes claims tail records one at a time and integrates that cell
-// to the end of its flow step (all remaining sub-calls).  Grid-size
-// independent: a group exits once the records are used up.
+// Coop::G lanes (floor(64 / G) groups per wave) claims tail records one at
+// a time and integrates that cell to the end of its flow step (all
+// remaining sub-calls).  Grid-size independent: a group exits once the
+// records are used up.
 template <class M>
 size_t coop_lds_bytes(int block) {
   using C = typename M::Coop;
+  const int groups = (block / 64) * CoopWave<C::G>::GPW;
   return (size_t)C::ND * sizeof(double) + (size_t)C::NI * sizeof(int) +
-         (size_t)(block / C::G) * CoopScratch<M>::SIZE * sizeof(double);
+         (size_t)groups * CoopScratch<M>::SIZE * sizeof(double);
 }
 
 template <class M>
@@ -41,10 +43,16 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   const int tid = threadIdx.x;
   for (int i = tid; i < C::ND; i += blockDim.x) D[i] = C::dtab()[i];
   for (int i = tid; i < C::NI; i += blockDim.x) I[i] = C::itab()[i];
-  const int gl = tid % G;
+  // group gw of this wave, lane gl within it; lanes past the wave's last
+  // group (gw == GPW) take no cells
+  constexpr int GPW = CoopWave<G>::GPW;
+  const int lane = tid & 63;
+  const int gw = min(lane / G, GPW);
+  const int gl = lane - gw * G;
+  const bool idle = gw == GPW;
   using S = CoopScratch<M>;
-  double* sgrp = scr + (tid / G) * S::SIZE;
-  if (gl == 0) {
+  double* sgrp = scr + ((tid >> 6) * GPW + (idle ? 0 : gw)) * S::SIZE;
+  if (gl == 0 && !idle) {
     sgrp[S::SC + N] = 1.0;
     sgrp[S::SG + N] = 0.0;
   }
@@ -65,10 +73,11 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   int nacc = 0, nrej = 0, sub = 0, base = 0;
 #pragma unroll 1
   for (;;) {
+    if (idle) break;
     if (!have) {
       unsigned int r = 0;
       if (gl == 0) r = (unsigned int)atomicAdd(a.tail.next, 1ull);
-      r = __shfl(r, 0, G);
+      r = __shfl(r, gw * G);  // the group's first lane, within the wave
       if (r >= count) break;
       r = (unsigned int)a.tail.order[r];
       const int64_t item = a.tail.item[r];

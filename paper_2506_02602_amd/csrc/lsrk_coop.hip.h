@@ -47,14 +47,22 @@ __device__ __forceinline__ void coop_sync() {
 // LDS scratch of one group (doubles): concentrations c[N+1] (c[N] = 1, the
 // pad of the species lists), g/RT g[N+1] (g[N] = 0), c_k (cp_k/R - 1) d[N],
 // rates of progress q[J], per-species terms w[N] of the energy and error
-// sums, and one discard slot per lane (up to 64): a lane without a species
-// or reaction stores there instead of branching around the store.
+// sums, and one discard slot per lane of the group: a lane without a
+// species or reaction stores there instead of branching around the store.
 template <class M>
 struct CoopScratch {
   static constexpr int N = M::NS;
   static constexpr int SC = 0, SG = N + 1, SD = 2 * (N + 1), SQ = SD + N, SW = SQ + M::Coop::J;
   static constexpr int SX = (SW + N + 1) & ~1;  // one slot per lane for discarded stores
-  static constexpr int SIZE = SX + 64;
+  static constexpr int SIZE = (SX + M::Coop::G + 1) & ~1;
+};
+
+// Groups of G lanes never straddle a wave: a wave holds floor(64 / G) of
+// them and its remaining lanes (64 mod G) stay idle.
+template <int G>
+struct CoopWave {
+  static_assert(G >= 1 && G <= 64, "a group fits in one wave");
+  static constexpr int GPW = 64 / G;  // groups per wave
 };
 
 template <class M>
