@@ -197,14 +197,17 @@ void chem_graph_destroy(chem_graph g);
 /*
  * Autotune block size, chunk length and cooperative hand-off for these
  * boxes by coordinate descent: chunk in {1, 2, 4, 8, 16, 32, 64} at the
- * default block, then block in {64, 128, 192, 256, 384, 512} (those that fit
- * the LDS compaction slots) at the best chunk, chunk again at the best
- * block, then, if base->tail_steps is 0, tail_steps in {8, 16, 32, 64, 128,
- * 256, 512, never} for the best pair, and, if base->tail_cap is 0 too, the
- * pairs of tail_steps in {8, 16, 32, 64} and tail_cap in {64, 128, 256, no
- * limit}, then, if base->pool_order is 0, the dealt pool order on, then
- * chunk once more at the final choice.  Each candidate is timed with HIP events on
- * `stream` (median of `reps` launches after one untimed launch) on the
+ * default block, then, when the best of those calls took under 50 ms,
+ * every pair of block in {64, 128, 192, 256, 384, 512} (those that fit the
+ * LDS compaction slots) and chunk, otherwise block at the best chunk and
+ * chunk again at the best block; then, if base->tail_steps is 0, tail_steps in {4, 8, 16, 32, 64,
+ * 128, 256, 512, never} for the best pair, and, if base->tail_cap is 0 too,
+ * the pairs of tail_steps in {4, 8, 16, 32, 64} and tail_cap in {64, 128,
+ * 256, no limit}, then, if base->pool_order is 0, the dealt pool order on,
+ * then chunk once more at the final choice.  Each candidate is timed with HIP
+ * events on `stream` (median of `reps` launches after one untimed launch);
+ * the four fastest distinct launches are then timed again, round-robin,
+ * 2 * reps + 1 launches each, and the lowest median wins.  Trials run on the
  * caller's boxes; the boxes' states are snapshotted first and restored
  * after every trial and at the end, so the caller's data is left unchanged.  The
  * winner is stored in the handle for the size bucket of these boxes (total

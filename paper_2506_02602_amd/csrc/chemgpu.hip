@@ -1395,18 +1395,25 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
+  // one timed call of a configuration from the snapshot
+  auto time_one = [&](const chem_opts& t, float* el) -> int {
+    if ((e = restore()) != hipSuccess) return hip_fail(e, "restore");
+    hipEventRecord(e0, s);
+    int trc = chem_integrate_batched(m, boxes, n_boxes, &t, stream);
+    if (trc != CHEM_OK) return trc;
+    hipEventRecord(e1, s);
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "trial");
+    *el = 0;
+    hipEventElapsedTime(el, e0, e1);
+    return CHEM_OK;
+  };
   // median time of `reps` calls of one configuration (after one untimed call)
   auto trial = [&](const chem_opts& t, double* med) -> int {
     std::vector<float> ms;
     for (int r = 0; r <= reps; ++r) {
-      if ((e = restore()) != hipSuccess) return hip_fail(e, "restore");
-      hipEventRecord(e0, s);
-      int trc = chem_integrate_batched(m, boxes, n_boxes, &t, stream);
-      if (trc != CHEM_OK) return trc;
-      hipEventRecord(e1, s);
-      if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "trial");
       float el = 0;
-      hipEventElapsedTime(&el, e0, e1);
+      const int trc = time_one(t, &el);
+      if (trc != CHEM_OK) return trc;
       if (r > 0) ms.push_back(el);
     }
     std::sort(ms.begin(), ms.end());
@@ -1418,11 +1425,17 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   // best pair, then hand-off point and cooperative cap together (an early
   // hand-off only pays when the cap lets the cooperative kernel take the
   // longer list), then chunk once more.  Each sweep keeps the incumbent
-  // unless a candidate is faster.
+  // unless a candidate is faster.  Finally the fastest few launches seen
+  // are timed again, round-robin and with more calls each, so that one
+  // noisy trial (a clock ramp, other work on the device) does not decide.
   const int blocks[] = {64, 128, 192, 256, 384, 512};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
-  const int tails[] = {8, 16, 32, 64, 128, 256, 512, -1};
-  const int pair_tails[] = {8, 16, 32, 64};
+  const int tails[] = {4, 8, 16, 32, 64, 128, 256, 512, -1};
+  const int pair_tails[] = {4, 8, 16, 32, 64};
+  // below this many ms per call the (block, chunk) plane is swept whole
+  constexpr double kTuneGridMs = 50.0;
+  struct Seen { int b, c, tl, cap, ord; double ms; };
+  std::vector<Seen> seen;
   const int caps[] = {kDefaultTailCap, 128, 256, -1};
   double best_ms = 1e300;
   int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
@@ -1443,6 +1456,7 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     double med = 0;
     const int trc = trial(t, &med);
     if (trc != CHEM_OK) return trc;
+    seen.push_back({b, c, tl, cap, ord, med});
     if (med < best_ms) {
       best_ms = med; best_block = b; best_chunk = c; best_tail = tl; best_cap = cap;
       best_order = ord;
@@ -1453,9 +1467,16 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   const int o0 = best_order;
   for (int c : chunks)
     if (rc == CHEM_OK) rc = consider(best_block, c, best_tail, best_cap, o0);
-  for (int b : blocks)
-    if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail, best_cap, o0);
-  {
+  if (rc == CHEM_OK && best_ms < kTuneGridMs) {
+    // cheap calls: every (block, chunk) pair (coordinate descent can stop
+    // in a local optimum: a block that loses at one chunk may win at another)
+    const int b0 = best_block;  // its chunks were just timed
+    for (int b : blocks)
+      for (int c : chunks)
+        if (rc == CHEM_OK && b != b0) rc = consider(b, c, best_tail, best_cap, o0);
+  } else {
+    for (int b : blocks)
+      if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail, best_cap, o0);
     const int b0 = best_block;
     for (int c : chunks)
       if (rc == CHEM_OK && c != best_chunk) rc = consider(b0, c, best_tail, best_cap, o0);
@@ -1482,6 +1503,40 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     const int ob0 = best_order;
     for (int c : chunks)
       if (rc == CHEM_OK && c != c0) rc = consider(b0, c, t0, k0, ob0);
+  }
+  if (rc == CHEM_OK && seen.size() > 1) {
+    // confirmation round over the (up to) four fastest distinct launches
+    std::stable_sort(seen.begin(), seen.end(),
+                     [](const Seen& x, const Seen& y) { return x.ms < y.ms; });
+    std::vector<Seen> top;
+    for (const Seen& v : seen) {
+      bool dup = false;
+      for (const Seen& w : top)
+        dup = dup || (w.b == v.b && w.c == v.c && w.tl == v.tl && w.cap == v.cap && w.ord == v.ord);
+      if (!dup) top.push_back(v);
+      if (top.size() == 4) break;
+    }
+    std::vector<std::vector<float>> ms(top.size());
+    for (int r = 0; r < 2 * reps + 1 && rc == CHEM_OK; ++r)
+      for (size_t k = 0; k < top.size() && rc == CHEM_OK; ++k) {
+        chem_opts t = o;
+        t.block_size = top[k].b; t.chunk_steps = top[k].c; t.tail_steps = top[k].tl;
+        t.tail_cap = top[k].cap; t.pool_order = top[k].ord;
+        float el = 0;
+        rc = time_one(t, &el);
+        ms[k].push_back(el);
+      }
+    if (rc == CHEM_OK) {
+      best_ms = 1e300;
+      for (size_t k = 0; k < top.size(); ++k) {
+        std::sort(ms[k].begin(), ms[k].end());
+        const double med = ms[k][ms[k].size() / 2];
+        if (med < best_ms) {
+          best_ms = med; best_block = top[k].b; best_chunk = top[k].c; best_tail = top[k].tl;
+          best_cap = top[k].cap; best_order = top[k].ord;
+        }
+      }
+    }
   }
   if ((e = restore()) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "restore");
   hipStreamSynchronize(s);
