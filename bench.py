@@ -78,8 +78,8 @@ def parse():
 # reads for the restore copy of known size in the same run (FETCH_SIZE
 # reports 0.5002 of the copied bytes, WRITE_SIZE 1.000).  Keyed by a digest of
 # the kernel sources the counters were taken on; any change nulls it.
-TRAFFIC = {"front": ("c4aa770c865d6e8a", 233.6e6),
-           "stress9": ("c4aa770c865d6e8a", 2988.9e6)}
+TRAFFIC = {"front": ("2fd71db0908810a3", 233.9e6),
+           "stress9": ("2fd71db0908810a3", 2990.9e6)}
 
 
 def kernel_digest():
