@@ -330,15 +330,19 @@ int chem_eval_exp(const double *x, double *y, int64_t n, void *stream);
  * the library's: y[i] = fn(x[i]) for i < n (device arrays, caller-owned),
  * enqueued on `stream`.  fn is one of
  *   CHEM_MATH_EXP_CW      the per-lane rate exponential (as chem_eval_exp);
- *   CHEM_MATH_EXP_ESTRIN  the cooperative kernel's exponential (same
+ *   CHEM_MATH_EXP_ESTRIN  a short-chain exponential without a table (same
  *                         reduction, Estrin-form polynomial; within 1 ulp);
  *   CHEM_MATH_LOG_ATANH   the logarithm of ln T (reduction to [sqrt(1/2),
  *                         sqrt(2)) and the atanh series; within 1 ulp for
- *                         finite x > 0, NaN otherwise).
+ *                         finite x > 0, NaN otherwise);
+ *   CHEM_MATH_EXP_TAB     the cooperative kernel's rate exponential (a table
+ *                         of 2^(j/64) in LDS and a degree-6 polynomial;
+ *                         about 1 ulp at most on [-745, 709]).
  * CHEM_EINVAL for an unknown fn, n < 0 or a null array with n > 0. */
 #define CHEM_MATH_EXP_CW 0
 #define CHEM_MATH_EXP_ESTRIN 1
 #define CHEM_MATH_LOG_ATANH 2
+#define CHEM_MATH_EXP_TAB 3
 int chem_eval_math(int32_t fn, const double *x, double *y, int64_t n, void *stream);
 
 #ifdef __cplusplus

@@ -400,7 +400,7 @@ def chem_eval_exp(x, stream=None):
 
 _lib.chem_eval_math.restype = C.c_int
 _lib.chem_eval_math.argtypes = [C.c_int32, _P, _P, C.c_int64, _P]
-MATH_FNS = {"exp_cw": 0, "exp_estrin": 1, "log_atanh": 2}
+MATH_FNS = {"exp_cw": 0, "exp_estrin": 1, "log_atanh": 2, "exp_tab": 3}
 
 
 def chem_eval_math(fn, x, stream=None):

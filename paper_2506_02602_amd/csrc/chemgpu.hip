@@ -76,10 +76,16 @@ struct Slots {
 };
 
 __global__ void eval_math_kernel(int fn, const double* x, double* y, int64_t n) {
+  __shared__ double E[64];  // exp_tab's table, staged in LDS as in the cooperative kernel
+  for (int k = threadIdx.x; k < 64; k += blockDim.x) E[k] = kExp2Frac[k];
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double v = x[i];
-  y[i] = fn == CHEM_MATH_EXP_ESTRIN ? exp_estrin(v) : fn == CHEM_MATH_LOG_ATANH ? log_atanh(v) : exp_cw(v);
+  y[i] = fn == CHEM_MATH_EXP_ESTRIN ? exp_estrin(v)
+         : fn == CHEM_MATH_LOG_ATANH ? log_atanh(v)
+         : fn == CHEM_MATH_EXP_TAB   ? exp_tab(v, E)
+                                     : exp_cw(v);
 }
 
 __global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
@@ -1063,7 +1069,8 @@ const char* chem_strerror(int code) {
 const char* chem_last_error(void) { return g_err.c_str(); }
 
 int chem_eval_math(int32_t fn, const double* x, double* y, int64_t n, void* stream) {
-  if (fn != CHEM_MATH_EXP_CW && fn != CHEM_MATH_EXP_ESTRIN && fn != CHEM_MATH_LOG_ATANH)
+  if (fn != CHEM_MATH_EXP_CW && fn != CHEM_MATH_EXP_ESTRIN && fn != CHEM_MATH_LOG_ATANH &&
+      fn != CHEM_MATH_EXP_TAB)
     return fail(CHEM_EINVAL, "chem_eval_math: unknown function");
   if (n < 0 || (n > 0 && (!x || !y))) return fail(CHEM_EINVAL, "chem_eval_math: bad argument");
   if (n == 0) return CHEM_OK;

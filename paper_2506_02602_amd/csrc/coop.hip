@@ -25,7 +25,7 @@ template <class M>
 size_t coop_lds_bytes(int block) {
   using C = typename M::Coop;
   const int groups = (block / 64) * CoopWave<C::G>::GPW;
-  return (size_t)C::ND * sizeof(double) + (size_t)C::NI * sizeof(int) +
+  return (size_t)(C::ND + 64) * sizeof(double) + (size_t)C::NI * sizeof(int) +
          (size_t)groups * CoopScratch<M>::SIZE * sizeof(double);
 }
 
@@ -34,15 +34,18 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   using C = typename M::Coop;
   constexpr int G = C::G, N = M::NS;
   static_assert(C::NI % 4 == 0 && C::ND % 2 == 0, "table padding");
+  // LDS: the double table, the 2^(j/64) table, the int table, group scratch
   extern __shared__ double smem[];
   double* D = smem;
-  int* I = reinterpret_cast<int*>(smem + C::ND);
-  double* scr = smem + C::ND + C::NI / 2;
+  double* E = smem + C::ND;
+  int* I = reinterpret_cast<int*>(smem + C::ND + 64);
+  double* scr = smem + C::ND + 64 + C::NI / 2;
   const unsigned int count = *a.tail.count;
   if (count > (unsigned int)a.tail.cap) return;  // resumed one per lane instead
   const int tid = threadIdx.x;
   for (int i = tid; i < C::ND; i += blockDim.x) D[i] = C::dtab()[i];
   for (int i = tid; i < C::NI; i += blockDim.x) I[i] = C::itab()[i];
+  for (int i = tid; i < 64; i += blockDim.x) E[i] = kExp2Frac[i];
   // group gw of this wave, lane gl within it; lanes past the wave's last
   // group (gw == GPW) take no cells
   constexpr int GPW = CoopWave<G>::GPW;
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
     sgrp[S::SG + N] = 0.0;
   }
   __syncthreads();
-  const CoopCtx<M> x{D, I, sgrp, gl};
+  const CoopCtx<M> x{D, E, I, sgrp, gl};
   CoopLane<M, G> ln;
   ln.load(D, I, gl);
   // One step per iteration; a group whose cell finishes claims the next

@@ -68,6 +68,7 @@ struct CoopWave {
 template <class M>
 struct CoopCtx {
   const double* D;  // the mechanism's double table, in LDS
+  const double* E;  // 2^(j/64), j = 0..63 (kExp2Frac), in LDS
   const int* I;     // its int table, in LDS
   double* s;        // this group's scratch
   int gl;
@@ -154,7 +155,7 @@ __device__ __forceinline__ double coop_rhs(double Yk, double T, double rho, doub
       lkf[r] = ln.lna + ln.bexp * lnT - ln.ear * invT;
     else
       lkf[r] = D[C::O_LNA + j] + D[C::O_BEXP + j] * lnT - D[C::O_EAR + j] * invT;
-    kf[r] = exp_estrin(lkf[r]);
+    kf[r] = exp_tab(lkf[r], x.E);
   }
   // species k: concentration and thermo
   const double c = Yk * (rho * D[C::O_INVW + k]);
@@ -185,7 +186,7 @@ __device__ __forceinline__ double coop_rhs(double Yk, double T, double rho, doub
         dg += D[C::O_GNU + j * C::MG + q] * s[S::SG + I[C::O_GK + j * C::MG + q]];
     }
     const double dn = PRE ? ln.dnu : D[C::O_DNU + j];
-    const double kr = exp_estrin(lkf[r] + dg - dn * lnPRT);
+    const double kr = exp_tab(lkf[r] + dg - dn * lnPRT, x.E);
     double fw = kf[r], rv = kr;
 #pragma unroll
     for (int q = 0; q < C::MR; ++q) {

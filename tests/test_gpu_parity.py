@@ -345,6 +345,26 @@ def test_short_chain_exponential_within_one_ulp(chemgpu):
     assert y[-8] == 1.0 and y[-3] == np.inf and y[-2] == 0.0 and np.isnan(y[-1])
 
 
+def test_table_exponential_within_one_ulp(chemgpu):
+    """The cooperative kernel's rate exponential (2^(j/64) from an LDS table,
+    degree-6 polynomial) against an extended-precision reference: its error
+    is the table entry's rounding plus one final rounding, so at most about
+    1 ulp on [-745, 709] (asserted with 5 % slack); exact at 0, inf above the
+    overflow threshold, 0 below underflow, NaN through."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(14))
+    x = np.concatenate([rng.uniform(-708.0, 709.0, 2_000_000), rng.uniform(-60.0, 60.0, 2_000_000),
+                        rng.uniform(-0.02, 0.02, 500_000),
+                        [0.0, 1.0, -1.0, 709.7, -708.0, 800.0, -800.0, np.nan]])
+    y = chemgpu.chem_eval_math("exp_tab", torch.from_numpy(x).cuda()).cpu().numpy()
+    fin = np.isfinite(x) & (x > -708.0) & (x < 709.7)
+    u = _ulps(y[fin], x[fin], np.exp)
+    print(f"[exp_tab] max {u.max():.3f} ulp, mean {u.mean():.4f}", flush=True)
+    assert u.max() <= 1.05 and u.mean() < 0.35
+    assert y[-8] == 1.0 and y[-3] == np.inf and y[-2] == 0.0 and np.isnan(y[-1])
+    assert np.isfinite(y[-5])
+
+
 def test_log_within_one_ulp(chemgpu):
     """ln T for the rate constants and the Gibbs energies: at most 1 ulp from
     an extended-precision reference over the whole positive range and densely
