@@ -38,8 +38,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--scheme", default="lsrk", choices=["lsrk", "rkf45", "ros4"],
@@ -356,7 +356,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     graph.close()
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    kern_all = np.array([a.elapsed_time(b) for a, b in ev])
+    kern_ms = float(np.mean(kern_all))
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed
     achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
@@ -380,6 +381,7 @@ def main():
         # per flow step: read (T, Y, rho, h), write (T, Y, h) of every cell
         "hbm_algorithmic_bytes": n * 8 * ((nv + 2) + (nv + 1)),
         "kernel_ms": kern_ms,
+        "kernel_ms_p10_p50_p90": [float(np.percentile(kern_all, q)) for q in (10, 50, 90)],
         "steps_per_flow_step": {"total_rk_steps": total_steps,
                                 "rejected": int(cn[1].sum()),
                                 "max_per_cell": int(cn.sum(axis=0).max()),

@@ -75,13 +75,17 @@ typedef struct {
                             and run with block_size <= 256 (CHEM_EINVAL otherwise) */
     int32_t tail_cap;    /* most handed-over cells per CU that the cooperative kernel takes
                             (see tail_steps): 0 = tuned default, else 64; < 0 = no limit */
-    int32_t pool_order;  /* > 0: before the step, cells expected to take many steps (a step
+    int32_t pool_order;  /* 1: before the step, cells expected to take many steps (a step
                             hint below dt/8 over the flow step, or without a usable hint
                             T >= 1000 K) are dealt round-robin over the first work claim of
                             every resident block, so they start at once and spread over the
-                            chip; < 0: pool order as laid out; 0: tuned default, else off.
-                            Changes no result (cells are independent); uses 8 bytes of
-                            workspace per cell */
+                            chip; 2: cells below the mechanism's NASA-7 range switch (the
+                            T_mid most species share) come first, the others after them,
+                            so that few waves hold cells of both ranges (such a wave
+                            evaluates both sets of polynomials); < 0: pool order as laid
+                            out; 0: tuned default, else off; > 2: CHEM_EINVAL.  Changes no
+                            result (cells are independent); uses 8 bytes of workspace per
+                            cell */
 } chem_opts;
 
 /*
@@ -203,7 +207,7 @@ void chem_graph_destroy(chem_graph g);
  * chunk again at the best block; then, if base->tail_steps is 0, tail_steps in {4, 8, 16, 32, 64,
  * 128, 256, 512, never} for the best pair, and, if base->tail_cap is 0 too,
  * the pairs of tail_steps in {4, 8, 16, 32, 64} and tail_cap in {64, 128,
- * 256, no limit}, then, if base->pool_order is 0, the dealt pool order on,
+ * 256, no limit}, then, if base->pool_order is 0, each of the two pool orders,
  * then chunk once more at the final choice.  Each candidate is timed with HIP
  * events on `stream` (median of `reps` launches after one untimed launch);
  * the four fastest distinct launches are then timed again, round-robin,

@@ -660,6 +660,14 @@ def step_flops(m: dict, scheme: str = "lsrk") -> int:
     return 5 * rhs_flops(m) + upd + wrms + 2 * FLOP_SQRT + FLOP_DIV + 4
 
 
+def t_split(m: dict) -> float:
+    """The T_mid shared by the most species (the first such on a tie)."""
+    count: dict = {}
+    for sp in m["species"]:
+        count[sp["Tmid"]] = count.get(sp["Tmid"], 0) + 1
+    return max(count, key=lambda t: count[t])
+
+
 def gen_header(path: str) -> tuple[str, dict]:
     m = parse(path)
     N = len(m["species"])
@@ -674,6 +682,9 @@ def gen_header(path: str) -> tuple[str, dict]:
         f"  static constexpr int NR = {len(m['reactions'])};",
         f"  static constexpr unsigned long long HASH = 0x{m['hash']:016x}ULL;",
         f"  static constexpr const char* NAME = \"{m['name']}\";",
+        "  // the NASA-7 range switch shared by the most species: the RHS branches",
+        "  // on it per wave, so the pool order that groups cells by range uses it",
+        f"  static constexpr double T_SPLIT = {lit(t_split(m))};",
         rhs,
         gen_jac(m),
         gen_aux(m),

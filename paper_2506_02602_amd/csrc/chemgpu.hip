@@ -147,18 +147,29 @@ __global__ __launch_bounds__(1024) void tail_order(TailBuf tb) {
 // coalesced); everything after the first R*B positions keeps pool order.
 // A cell is heavy when its step hint promises at least kHeavySteps steps
 // over its flow step, or, without a usable hint (h <= 0 or h >= dt), when
-// it is at least kHeavyT hot (below that the chemistry is slow).  The order
-// changes no result: each cell's integration is independent of when and
-// where it runs.  Skipped (identity) when nothing is heavy, when heavy
-// cells are more than half of the first round, or when the pool is smaller
-// than one round.
+// it is at least kHeavyT hot (below that the chemistry is slow).  The
+// second order, by range, puts the cells below the mechanism's NASA-7 range
+// switch first and the rest after them, each in pool order: the RHS
+// evaluates one range's polynomials for a wave whose cells all sit in it
+// and both for a wave that straddles the switch, so on a field with
+// temperatures scattered around it (the stress fields) grouping by range
+// spares most waves the second set.  Neither order changes a result: each
+// cell's integration is independent of when and where it runs.  The dealt
+// order is skipped (identity) when nothing is heavy, when heavy cells are
+// more than half of the first round, or when the pool is smaller than one
+// round.
 constexpr double kHeavySteps = 8.0;
 constexpr double kHeavyT = 1000.0;
 
+constexpr int ORDER_DEAL = 1;    // heavy cells dealt over the first claims
+constexpr int ORDER_RANGE = 2;   // cells below the NASA-7 range switch first
+
 struct OrderBuf {
-  int32_t* rank;          // per item: rank among heavy (>= 0) or -(rank among light) - 1
+  int32_t* rank;          // per item: rank among class 0 (>= 0) or -(rank among class 1) - 1
   int32_t* order;         // pool position -> item
-  unsigned int* counts;   // [0] heavy, [1] light (zeroed before order_rank)
+  unsigned int* counts;   // [0] class 0, [1] class 1 (zeroed before order_rank)
+  int mode;               // ORDER_DEAL (class 0 = heavy) or ORDER_RANGE (class 0 = T < t_split)
+  double t_split;
 };
 
 __global__ void order_reset(unsigned int* counts) {
@@ -193,8 +204,11 @@ __global__ __launch_bounds__(kOrderBlock) void order_rank(PoolArgs a, int ns, Or
       const int64_t i = cell_index(bd, g);
       const double T = bd.state[i];
       const double h = bd.state[(int64_t)(ns + 2) * bd.ld + i];
-      heavy[r] = (h > 0.0 && h < bd.dt) ? (double)bd.n_sub * bd.dt >= kHeavySteps * h
-                                        : T >= kHeavyT;
+      if (ob.mode == ORDER_RANGE)
+        heavy[r] = T < ob.t_split;
+      else
+        heavy[r] = (h > 0.0 && h < bd.dt) ? (double)bd.n_sub * bd.dt >= kHeavySteps * h
+                                          : T >= kHeavyT;
     }
     bh[r] = __ballot(valid && heavy[r]);
     bl[r] = __ballot(valid && !heavy[r]);
@@ -229,11 +243,18 @@ __global__ __launch_bounds__(kOrderBlock) void order_rank(PoolArgs a, int ns, Or
   }
 }
 
-// Position of every item in the dealt order (a bijection of [0, total)).
+// Position of every item in the order (a bijection of [0, total)): by range,
+// class 0 then class 1, each in pool order; dealt, as described above.
 __global__ __launch_bounds__(256) void order_place(int64_t total, int R, int B, OrderBuf ob) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int64_t H = ob.counts[0];
+  if (ob.mode == ORDER_RANGE) {
+    const int64_t r = ob.rank[g];
+    const int64_t q = r >= 0 ? r : H + (-r - 1);
+    if (q >= 0 && q < total) ob.order[q] = (int32_t)g;
+    return;
+  }
   const int64_t RB = (int64_t)R * B;
   int64_t q = g;
   if (H > 0 && 2 * H <= RB && total >= RB) {
@@ -510,6 +531,7 @@ struct MechEntry {
   int ns, nr;
   const char* name;
   bool has_jac;  // a generated Jacobian: the Rosenbrock comparator is built
+  double t_split;  // the NASA-7 range switch the RHS branches on (ORDER_RANGE)
   hipError_t (*launch_direct)(const PoolArgs&, int block, hipStream_t);
   hipError_t (*launch_persistent)(const PoolArgs&, int block, int grid, hipStream_t);
   hipError_t (*launch_coop)(const PoolArgs&, int n_cu, hipStream_t);
@@ -642,7 +664,8 @@ size_t lds_per_lane() {
   return Slots<M>::bytes(1);
 }
 
-#define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, M::HAS_JAC, &launch_direct<M>, &launch_persistent<M>, \
+#define CHEM_ENTRY(M) {M::HASH, M::NS, M::NR, M::NAME, M::HAS_JAC, M::T_SPLIT, \
+                       &launch_direct<M>, &launch_persistent<M>, \
                        &launch_coop<M>, &launch_cons_to_prim<M>, &launch_prim_to_cons<M>, \
                        &max_blocks_per_cu<M>, &lds_per_lane<M>, \
                        &launch_surr_infer<M>, &launch_surr_hull<M>, &launch_make_pairs<M>},
@@ -805,6 +828,8 @@ int check_opts(const chem_opts* o) {
   if (o->scheme != SCHEME_LSRK && o->scheme != SCHEME_RKF45 && o->scheme != SCHEME_ROS4)
     return fail(CHEM_EINVAL,
                 "chem_opts.scheme must be 0 (LSRK4(3)5), 1 (RKF45) or 2 (Rosenbrock)");
+  if (o->pool_order > 2)
+    return fail(CHEM_EINVAL, "chem_opts.pool_order must be <= 0 (off or tuned), 1 or 2");
   if (o->block_size != 0 && (o->block_size % 64 != 0 || o->block_size > 512 || o->block_size < 64))
     return fail(CHEM_EINVAL, "chem_opts.block_size must be a multiple of 64 in [64, 512]");
   return CHEM_OK;
@@ -849,15 +874,15 @@ int pick_tail(chem_mech m, int64_t total, const chem_opts* o) {
 constexpr int kDefaultTailCap = 64;
 
 // Most handed-over cells the cooperative kernel takes, over the whole chip.
-// Pool order on (dealt heavy cells) or off: chem_opts.pool_order > 0 / < 0,
-// else the tuned choice, else off.
-bool pick_order(chem_mech m, int64_t total, const chem_opts* o) {
+// Pool order: ORDER_DEAL or ORDER_RANGE (chem_opts.pool_order 1 or 2), off
+// (< 0), else the tuned choice, else off.  Returns 0 for off.
+int pick_order(chem_mech m, int64_t total, const chem_opts* o) {
   int v = o ? o->pool_order : 0;
   if (v == 0) {
     auto it = m->tuned.find(tuned_key(total, o));
     v = it != m->tuned.end() ? it->second.order : 0;
   }
-  return v > 0;
+  return v == ORDER_DEAL || v == ORDER_RANGE ? v : 0;
 }
 
 int pick_cap(chem_mech m, int64_t total, const chem_opts* o) {
@@ -940,11 +965,14 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
     a.tail.cap = pick_cap(m, a.total, o);
   }
   OrderBuf ob{};
-  const bool ordered = order && !a.total_dev && pick_order(m, a.total, o);
+  const int omode = order && !a.total_dev ? pick_order(m, a.total, o) : 0;
+  const bool ordered = omode != 0;
   if (ordered) {
     int rc = ensure_order(*order, std::max<int64_t>(a.total, m->reserved));
     if (rc) return rc;
     ob = order->view();
+    ob.mode = omode;
+    ob.t_split = m->entry->t_split;
   }
   hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s,
                              ordered ? &ob : nullptr);
@@ -1283,7 +1311,8 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
     rc = ensure_tail(g->tail, total);
     if (rc) { chem_graph_destroy(g); return rc; }
   }
-  const bool ordered = pick_order(m, total, opts);
+  const int omode = pick_order(m, total, opts);
+  const bool ordered = omode != 0;
   if (ordered) {
     rc = ensure_order(g->order, total);
     if (rc) { chem_graph_destroy(g); return rc; }
@@ -1316,6 +1345,8 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) { hipStreamDestroy(cs); return bail(e, "hipStreamBeginCapture"); }
   OrderBuf ob = ordered ? g->order.view() : OrderBuf{};
+  ob.mode = omode;
+  ob.t_split = m->entry->t_split;
   hipError_t le = launch_step(m, a, block, grid, cs, ordered ? &ob : nullptr);
   e = hipStreamEndCapture(cs, &g->graph);
   hipStreamDestroy(cs);
@@ -1500,8 +1531,9 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
         if (rc == CHEM_OK && !(tl == t0 && cap == k0)) rc = consider(b0, c0, tl, cap, o0);
   }
   if (o.pool_order == 0 && o.fixed_steps == 0) {
-    // the dealt pool order, on, at the best launch so far
-    if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, 1);
+    // the two pool orders at the best launch so far
+    if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_DEAL);
+    if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_RANGE);
   }
   {
     // the hand-off and the order move the balance between compaction and

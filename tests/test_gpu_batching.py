@@ -195,25 +195,55 @@ def test_full_amr_hierarchy_sampled(cg, gm9, omech9, mech9_path):
     g.close()
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("block,chunk,tail", [(512, 8, 32), (256, 2, 16), (128, 1, -1)])
-def test_pool_order_changes_no_result(cg, gm9, mech9_path, block, chunk, tail):
-    """Dealing the hot cells over the first claims (pool_order on) moves
-    cells between blocks and in time, never their arithmetic: state, status
-    and counts are bitwise those of the laid-out order, on the first call
-    (order from temperature) and on a second call (order from the step
-    hints the first one wrote).  The field is larger than one round of
-    claims, so the order is really dealt."""
+def test_pool_order_changes_no_result(cg, gm9, mech9_path, block, chunk, tail, mode):
+    """Dealing the hot cells over the first claims (pool_order 1) or grouping
+    the cells by NASA-7 range (pool_order 2) moves cells between blocks and
+    in time, never their arithmetic: state, status and counts are bitwise
+    those of the laid-out order, on the first call (order from temperature)
+    and on a second call (order from the step hints the first one wrote).
+    The field is larger than one round of claims, so the order is really
+    dealt."""
     import torch
     from gpu_common import run_gpu
     s0, hot = wl.front_2d(mech9_path, nx=512, ny=512, seed=61)
     kw = dict(block_size=block, chunk_steps=chunk, tail_steps=tail)
     off1 = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=-1, **kw)
-    on1 = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=1, **kw)
+    on1 = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=mode, **kw)
     assert all(np.array_equal(x, y) for x, y in zip(off1, on1))
     s1 = off1[0]                                   # carries the hints of the first call
     off2 = run_gpu(gm9, s1, wl.DT_FLOW, pool_order=-1, **kw)
-    on2 = run_gpu(gm9, s1, wl.DT_FLOW, pool_order=1, **kw)
+    on2 = run_gpu(gm9, s1, wl.DT_FLOW, pool_order=mode, **kw)
     assert all(np.array_equal(x, y) for x, y in zip(off2, on2))
+
+
+def test_range_order_on_scattered_temperatures(cg, gm9, mech9_path):
+    """On a stress field (T scattered over 900-2800 K, so most 64-cell waves
+    of the laid-out order straddle the 1000 K range switch and evaluate both
+    sets of NASA-7 polynomials) grouping by range gives bitwise the laid-out
+    result, also in a captured graph replayed twice; an unknown order mode
+    is refused."""
+    import torch
+    from gpu_common import run_gpu
+    s0 = wl.stress_3d(mech9_path, shape=(64, 64, 16), seed=63)
+    assert 0.02 < np.mean(s0[0] < 1000.0) < 0.2
+    kw = dict(block_size=256, chunk_steps=2, tail_steps=64)
+    off = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=-1, **kw)
+    on = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=2, **kw)
+    assert all(np.array_equal(x, y) for x, y in zip(off, on))
+    st = torch.from_numpy(s0.copy()).cuda()
+    g = cg.chem_graph_capture_batched(gm9, [dict(state=st, dt=wl.DT_FLOW)],
+                                      cg.make_opts(pool_order=2, **kw))
+    for rep in range(2):
+        st.copy_(torch.from_numpy(s0))
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(st.cpu().numpy(), off[0]), f"replay {rep}"
+    g.close()
+    with pytest.raises(cg.ChemError) as e:
+        cg.chem_integrate(gm9, st, wl.DT_FLOW, cg.make_opts(pool_order=3))
+    assert e.value.code == -1
 
 
 def test_pool_order_batched_and_graph(cg, gm9, mech9_path):
