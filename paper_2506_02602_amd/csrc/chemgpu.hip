@@ -770,7 +770,7 @@ int ensure_tail(TailStore& ts, int64_t cap) {
   if (ts.mem) {
     hipError_t e = hipDeviceSynchronize();  // a queued call may still use the old records
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(tail records)");
-    hipFree(ts.mem);
+    (void)hipFree(ts.mem);
   }
   ts.mem = nullptr;
   ts.cap = 0;
@@ -785,7 +785,7 @@ int ensure_order(OrderStore& os, int64_t cap) {
   if (os.mem) {
     hipError_t e = hipDeviceSynchronize();  // a queued call may still use the old arrays
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(pool order)");
-    hipFree(os.mem);
+    (void)hipFree(os.mem);
   }
   os.mem = nullptr;
   os.cap = 0;
@@ -797,9 +797,13 @@ int ensure_order(OrderStore& os, int64_t cap) {
 
 int ensure_box_table(chem_mech m, int32_t n) {
   if (n <= m->box_cap) return CHEM_OK;
-  if (m->boxes_copied) hipEventSynchronize(m->boxes_copied);
-  if (m->d_boxes) hipFree(m->d_boxes);
-  if (m->h_boxes) hipHostFree(m->h_boxes);
+  if (m->boxes_copied) {
+    // the previous table may still be read by a queued copy
+    hipError_t e = hipEventSynchronize(m->boxes_copied);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(box table)");
+  }
+  if (m->d_boxes) (void)hipFree(m->d_boxes);
+  if (m->h_boxes) (void)hipHostFree(m->h_boxes);
   m->d_boxes = nullptr; m->h_boxes = nullptr; m->box_cap = 0;
   hipError_t e = hipMalloc(&m->d_boxes, sizeof(BoxDesc) * n);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(box table)");
@@ -1157,14 +1161,18 @@ int chem_mech_query(chem_mech m, int32_t* n_species, int32_t* n_reactions, uint6
 
 void chem_mech_free(chem_mech m) {
   if (!m) return;
-  if (m->boxes_copied) { hipEventSynchronize(m->boxes_copied); hipEventDestroy(m->boxes_copied); }
-  if (m->d_next) hipFree(m->d_next);
-  if (m->tail.mem) hipFree(m->tail.mem);
-  if (m->order.mem) hipFree(m->order.mem);
-  if (m->d_prim) hipFree(m->d_prim);
-  if (m->d_flag) hipFree(m->d_flag);
-  if (m->d_boxes) hipFree(m->d_boxes);
-  if (m->h_boxes) hipHostFree(m->h_boxes);
+  // teardown: errors have nowhere to go
+  if (m->boxes_copied) {
+    (void)hipEventSynchronize(m->boxes_copied);
+    (void)hipEventDestroy(m->boxes_copied);
+  }
+  if (m->d_next) (void)hipFree(m->d_next);
+  if (m->tail.mem) (void)hipFree(m->tail.mem);
+  if (m->order.mem) (void)hipFree(m->order.mem);
+  if (m->d_prim) (void)hipFree(m->d_prim);
+  if (m->d_flag) (void)hipFree(m->d_flag);
+  if (m->d_boxes) (void)hipFree(m->d_boxes);
+  if (m->h_boxes) (void)hipHostFree(m->h_boxes);
   delete m;
 }
 
@@ -1225,8 +1233,8 @@ int chem_react_conserved(chem_mech m, double* cons, int64_t ld, int64_t n_cells,
     if (m->d_prim) {
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(primitive work state)");
-      hipFree(m->d_prim);
-      hipFree(m->d_flag);
+      (void)hipFree(m->d_prim);
+      (void)hipFree(m->d_flag);
     }
     m->d_prim = nullptr; m->d_flag = nullptr; m->prim_cap = 0;
     const int64_t cap = std::max<int64_t>(n_cells, m->reserved);
@@ -1343,13 +1351,13 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(e, "hipStreamCreate(capture)");
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) { hipStreamDestroy(cs); return bail(e, "hipStreamBeginCapture"); }
+  if (e != hipSuccess) { (void)hipStreamDestroy(cs); return bail(e, "hipStreamBeginCapture"); }
   OrderBuf ob = ordered ? g->order.view() : OrderBuf{};
   ob.mode = omode;
   ob.t_split = m->entry->t_split;
   hipError_t le = launch_step(m, a, block, grid, cs, ordered ? &ob : nullptr);
   e = hipStreamEndCapture(cs, &g->graph);
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (le != hipSuccess) return bail(le, "launch integrator kernels (capture)");
   if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
@@ -1367,13 +1375,14 @@ int chem_graph_launch(chem_graph g, void* stream) {
 
 void chem_graph_destroy(chem_graph g) {
   if (!g) return;
-  hipDeviceSynchronize();
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
-  if (g->d_boxes) hipFree(g->d_boxes);
-  if (g->d_next) hipFree(g->d_next);
-  if (g->tail.mem) hipFree(g->tail.mem);
-  if (g->order.mem) hipFree(g->order.mem);
+  // teardown: errors have nowhere to go
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->d_boxes) (void)hipFree(g->d_boxes);
+  if (g->d_next) (void)hipFree(g->d_next);
+  if (g->tail.mem) (void)hipFree(g->tail.mem);
+  if (g->order.mem) (void)hipFree(g->order.mem);
   delete g;
 }
 
@@ -1414,7 +1423,7 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   // snapshot every box so trials can restore the caller's data
   std::vector<double*> snap(table.size(), nullptr);
   std::vector<size_t> bytes(table.size());
-  auto cleanup = [&]() { for (double* p : snap) if (p) hipFree(p); };
+  auto cleanup = [&]() { for (double* p : snap) if (p) (void)hipFree(p); };
   hipError_t e;
   for (size_t i = 0; i < table.size(); ++i) {
     bytes[i] = sizeof(double) * (size_t)table[i].ld * (size_t)(m->entry->ns + 3);
@@ -1430,19 +1439,22 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     }
     return hipSuccess;
   };
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    cleanup();
+    return hip_fail(e, "hipEventCreate(autotune)");
+  }
   // one timed call of a configuration from the snapshot
   auto time_one = [&](const chem_opts& t, float* el) -> int {
     if ((e = restore()) != hipSuccess) return hip_fail(e, "restore");
-    hipEventRecord(e0, s);
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     int trc = chem_integrate_batched(m, boxes, n_boxes, &t, stream);
     if (trc != CHEM_OK) return trc;
-    hipEventRecord(e1, s);
+    if ((e = hipEventRecord(e1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "trial");
     *el = 0;
-    hipEventElapsedTime(el, e0, e1);
+    if ((e = hipEventElapsedTime(el, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
     return CHEM_OK;
   };
   // median time of `reps` calls of one configuration (after one untimed call)
@@ -1578,9 +1590,9 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     }
   }
   if ((e = restore()) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "restore");
-  hipStreamSynchronize(s);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  if ((e = hipStreamSynchronize(s)) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "autotune sync");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   cleanup();
   if (rc != CHEM_OK) return rc;
   m->tuned[tkey] = {best_block, best_chunk, best_tail, best_cap, best_order};

@@ -61,7 +61,7 @@ void surr_free_batch(chem_surr s) {
   for (void* p : {(void*)s->X0, (void*)s->H1, (void*)s->H2, (void*)s->H3, (void*)s->dout,
                   (void*)s->dZb1, (void*)s->dZb2, (void*)s->dZb3, (void*)s->Z1, (void*)s->Z2,
                   (void*)s->Z3, (void*)s->out, (void*)s->Yb, (void*)s->dZ, (void*)s->part})
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   s->X0 = s->H1 = s->H2 = s->H3 = s->dout = s->dZb1 = s->dZb2 = s->dZb3 = nullptr;
   s->Z1 = s->Z2 = s->Z3 = s->out = s->Yb = s->dZ = s->part = nullptr;
   s->bcap = 0;
@@ -237,17 +237,17 @@ int surrogate_create(chem_mech mech, int32_t hidden, int32_t depth, uint64_t see
 
 void surrogate_free(chem_surr s) {
   if (!s) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();  // teardown: nothing to report an error to
   surr_free_batch(s);
   for (void* p : {(void*)s->theta, (void*)s->m, (void*)s->v, (void*)s->grad, (void*)s->wbf,
                   (void*)s->norm, (void*)s->wpack, (void*)s->bpack, (void*)s->Xn, (void*)s->Yn,
                   (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count, (void*)s->hull_list,
                   (void*)s->hull_count, (void*)s->hull_flag, (void*)s->side_next,
                   s->side_tail.mem})
-    if (p) hipFree(p);
-  if (s->ev_fork) hipEventDestroy(s->ev_fork);
-  if (s->ev_join) hipEventDestroy(s->ev_join);
-  if (s->side) hipStreamDestroy(s->side);
+    if (p) (void)hipFree(p);
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->side) (void)hipStreamDestroy(s->side);
   delete s;
 }
 
@@ -306,16 +306,19 @@ int surrogate_grad(chem_surr s, const float* Xn, const float* Yn, int32_t B, flo
   int rc = surr_ensure_batch(s, B);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  hipMemsetAsync(s->sse, 0, sizeof(double), st);
+  hipError_t e = hipMemsetAsync(s->sse, 0, sizeof(double), st);
+  if (e != hipSuccess) return hip_fail(e, "surrogate_grad clear");
   hipLaunchKernelGGL(surr::gather_batch, dim3((B + 255) / 256), dim3(256), 0, st, Xn, Yn, (long)B,
                      s->ni, s->no, 0L, B, 1ull, 0ull, s->X0, s->Yb);
-  hipError_t e = surr_forward_batch(s, B, st);
+  e = surr_forward_batch(s, B, st);
   if (e == hipSuccess) e = surr_backward_batch(s, B, st);
+  if (e == hipSuccess && grad_out)
+    e = hipMemcpyAsync(grad_out, s->grad, sizeof(float) * s->P, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "surrogate_grad");
-  if (grad_out) hipMemcpyAsync(grad_out, s->grad, sizeof(float) * s->P, hipMemcpyDeviceToDevice, st);
   if (loss_host) {
     double sse = 0;
-    hipMemcpyAsync(&sse, s->sse, sizeof(double), hipMemcpyDeviceToHost, st);
+    if ((e = hipMemcpyAsync(&sse, s->sse, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return hip_fail(e, "surrogate_grad loss copy");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "surrogate_grad sync");
     *loss_host = (float)(sse / ((double)B * s->no));
   }
@@ -342,8 +345,9 @@ int surrogate_forward(chem_surr s, const float* X, int64_t n, float* out, void* 
     if (e == hipSuccess)
       e = hipMemcpyAsync(out + c0 * s->no, s->out, sizeof(float) * b * s->no, hipMemcpyDeviceToDevice, st);
   }
-  hipStreamSynchronize(st);
-  hipFree(tmp);
+  const hipError_t es = hipStreamSynchronize(st);
+  (void)hipFree(tmp);
+  if (e == hipSuccess) e = es;
   if (e != hipSuccess) return hip_fail(e, "surrogate_forward");
   return CHEM_OK;
 }
@@ -356,16 +360,19 @@ int surrogate_train(chem_surr s, const float* X, const float* Y, int64_t n, int3
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   if (n > s->ncap) {
-    if (s->Xn) hipFree(s->Xn);
-    if (s->Yn) hipFree(s->Yn);
+    if (s->Xn) (void)hipFree(s->Xn);
+    if (s->Yn) (void)hipFree(s->Yn);
     s->Xn = s->Yn = nullptr;
     s->ncap = 0;
     if ((e = dalloc(&s->Xn, n * s->ni)) != hipSuccess) return hip_fail(e, "hipMalloc(train X)");
     if ((e = dalloc(&s->Yn, n * s->no)) != hipSuccess) return hip_fail(e, "hipMalloc(train Y)");
     s->ncap = n;
   }
-  hipMemcpyAsync(s->Xn, X, sizeof(float) * n * s->ni, hipMemcpyDeviceToDevice, st);
-  hipMemcpyAsync(s->Yn, Y, sizeof(float) * n * s->no, hipMemcpyDeviceToDevice, st);
+  if ((e = hipMemcpyAsync(s->Xn, X, sizeof(float) * n * s->ni, hipMemcpyDeviceToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(s->Yn, Y, sizeof(float) * n * s->no, hipMemcpyDeviceToDevice, st)) !=
+          hipSuccess)
+    return hip_fail(e, "surrogate_train copy");
   float* mu_in = s->norm;
   float* sd_in = s->norm + s->ni;
   float* mu_out = s->norm + 2 * s->ni;
@@ -399,7 +406,8 @@ int surrogate_train(chem_surr s, const float* X, const float* Y, int64_t n, int3
       while (b0) { const unsigned long long r = a0 % b0; a0 = b0; b0 = r; }
       if (a0 == 1) break;
     }
-    hipMemsetAsync(s->sse, 0, sizeof(double), st);
+    if ((e = hipMemsetAsync(s->sse, 0, sizeof(double), st)) != hipSuccess)
+      return hip_fail(e, "surrogate_train clear");
     for (long k = 0; k < steps; ++k, ++t) {
       hipLaunchKernelGGL(surr::gather_batch, dim3((batch + 255) / 256), dim3(256), 0, st, s->Xn, s->Yn,
                          (long)n, s->ni, s->no, k * batch, batch, pa, pb, s->X0, s->Yb);
@@ -416,7 +424,8 @@ int surrogate_train(chem_surr s, const float* X, const float* Y, int64_t n, int3
     }
     if (loss_host) {
       double sse = 0;
-      hipMemcpyAsync(&sse, s->sse, sizeof(double), hipMemcpyDeviceToHost, st);
+      if ((e = hipMemcpyAsync(&sse, s->sse, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(e, "surrogate_train loss copy");
       if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "surrogate_train sync");
       loss_host[ep] = (float)(sse / ((double)steps * batch * s->no));
     }
@@ -444,7 +453,7 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
   hipError_t e;
   if (fallback && n_cells > s->fb_cap) {
     for (void* p : {(void*)s->fb_list, (void*)s->hull_list, (void*)s->hull_flag})
-      if (p) hipFree(p);
+      if (p) (void)hipFree(p);
     s->fb_list = nullptr; s->hull_list = nullptr; s->hull_flag = nullptr;
     s->fb_cap = 0;
     if ((e = dalloc(&s->fb_list, n_cells)) != hipSuccess) return hip_fail(e, "hipMalloc(fallback list)");
@@ -511,9 +520,10 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
   }
   if (n_fallback_host) {
     unsigned cnt[2] = {0, 0};
-    hipMemcpyAsync(&cnt[0], s->fb_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
-    if (fallback && n_cells > 0)
-      hipMemcpyAsync(&cnt[1], s->hull_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(&cnt[0], s->fb_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && fallback && n_cells > 0)
+      e = hipMemcpyAsync(&cnt[1], s->hull_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "surrogate_infer count copy");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "surrogate_infer sync");
     *n_fallback_host = (int64_t)cnt[0] + cnt[1];
   }
