@@ -186,8 +186,8 @@ def gen_rhs(m: dict) -> str:
     L.append("    // hoisted out of the step loop and pinned in registers.")
     L.append("    asm volatile(\"\" : \"+v\"(rho), \"+v\"(inv_rho));")
     L.append("    const double T = u[0];")
-    L.append("    const double lnT = log(T);")
-    L.append("    const double invT = 1.0 / T;")
+    L.append("    const double lnT = log_atanh(T);")
+    L.append("    const double invT = rcp_nr(T);")
     L.append("    const double omlnT = 1.0 - lnT;")
     L.append("    const double T2 = T * T, T3 = T2 * T, T4 = T2 * T2;")
     L.append(f"    const double lnPRT = {lit(math.log(m['pstd'] / R_CGS))} - lnT;")
@@ -242,7 +242,7 @@ def gen_rhs(m: dict) -> str:
         L.append("    }")
     num = " + ".join(f"(h{k} - 1.0) * w{k}" for k in range(N))
     L.append(f"    const double num = {num};")
-    L.append("    f[0] = -T * num / den;")
+    L.append("    f[0] = -T * num * rcp_nr(den);")
     for k, s in enumerate(sp):
         L.append(f"    f[{k + 1}] = w{k} * ({lit(s['W'])} * inv_rho);")
     L.append("  }")

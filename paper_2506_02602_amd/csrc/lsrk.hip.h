@@ -205,6 +205,17 @@ __device__ __forceinline__ double exp_tab(double x, const double* E) {
   return ldexp(fma(t, p, t), mi >> 6);
 }
 
+// 1/x from the hardware reciprocal refined by two Newton steps: within an
+// ulp of the quotient for normal x (T and the heat-capacity sum of the
+// temperature equation, both positive), half the instructions of the IEEE
+// division sequence.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 // ln x for finite x > 0 (NaN otherwise) with a short dependency chain: x =
 // 2^e m with m in [sqrt(1/2), sqrt(2)), f = m - 1 (exact), s = f / (2 + f)
 // (hardware reciprocal refined by two Newton steps), and

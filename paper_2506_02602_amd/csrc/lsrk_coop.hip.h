@@ -29,15 +29,6 @@
 
 namespace chemgpu {
 
-// 1/x from the hardware reciprocal refined by two Newton steps (within an
-// ulp of the quotient for positive normal x).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return r;
-}
-
 __device__ __forceinline__ void coop_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
