@@ -1556,7 +1556,7 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
       if (rc == CHEM_OK && c != c0) rc = consider(b0, c, t0, k0, ob0);
   }
   if (rc == CHEM_OK && seen.size() > 1) {
-    // confirmation round over the (up to) four fastest distinct launches
+    // confirmation round over the (up to) six fastest distinct launches
     std::stable_sort(seen.begin(), seen.end(),
                      [](const Seen& x, const Seen& y) { return x.ms < y.ms; });
     std::vector<Seen> top;
@@ -1565,10 +1565,10 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
       for (const Seen& w : top)
         dup = dup || (w.b == v.b && w.c == v.c && w.tl == v.tl && w.cap == v.cap && w.ord == v.ord);
       if (!dup) top.push_back(v);
-      if (top.size() == 4) break;
+      if (top.size() == 6) break;
     }
     std::vector<std::vector<float>> ms(top.size());
-    for (int r = 0; r < 2 * reps + 1 && rc == CHEM_OK; ++r)
+    for (int r = 0; r < 3 * reps + 1 && rc == CHEM_OK; ++r)
       for (size_t k = 0; k < top.size() && rc == CHEM_OK; ++k) {
         chem_opts t = o;
         t.block_size = top[k].b; t.chunk_steps = top[k].c; t.tail_steps = top[k].tl;
