@@ -10,8 +10,9 @@ pristine field with a device-to-device copy (inside the timed region) so
 every step integrates the same input.  --workload selects the other fields
 (AMR hierarchy, stress fields, the hot-cell throughput probe).
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on a
-single GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: the integrator runs on
+one GPU per process (cells are independent; sharding them over GPUs is
+described in the design notes, not built).
 """
 from __future__ import annotations
 
@@ -285,7 +286,7 @@ def cpu_baseline(boxes, path, threads, target_s=10.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the integrator runs on one GPU (asked for --gpus {args.gpus}); "
               "the chemistry step needs no cross-GPU exchange, see the design notes",
               file=sys.stderr)
         sys.exit(2)
