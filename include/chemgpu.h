@@ -210,8 +210,9 @@ void chem_graph_destroy(chem_graph g);
  * 256, no limit}, then, if base->pool_order is 0, each of the two pool orders,
  * then chunk once more at the final choice.  Each candidate is timed with HIP
  * events on `stream` (median of `reps` launches after one untimed launch);
- * the six fastest distinct launches are then timed again, round-robin,
- * 3 * reps + 1 launches each, and the lowest median wins.  Trials run on the
+ * the eight fastest distinct launches are then timed again, round-robin,
+ * 3 * reps + 1 launches each, and the lowest median wins (2 * reps + 2
+ * untimed launches come first, so start-up clocks do not count).  Trials run on the
  * caller's boxes; the boxes' states are snapshotted first and restored
  * after every trial and at the end, so the caller's data is left unchanged.  The
  * winner is stored in the handle for the size bucket of these boxes (total
