@@ -208,7 +208,8 @@ void chem_graph_destroy(chem_graph g);
  * 128, 256, 512, never} for the best pair, and, if base->tail_cap is 0 too,
  * the pairs of tail_steps in {4, 8, 16, 32, 64} and tail_cap in {64, 128,
  * 256, no limit}, then, if base->pool_order is 0, each of the two pool orders,
- * then chunk once more at the final choice.  Each candidate is timed with HIP
+ * then block and chunk once more at the final hand-off, cap and order (the
+ * whole plane when calls take under 50 ms, else chunk, block, chunk).  Each candidate is timed with HIP
  * events on `stream` (median of `reps` launches after one untimed launch);
  * the eight fastest distinct launches are then timed again, round-robin,
  * 3 * reps + 1 launches each, and the lowest median wins (2 * reps + 2

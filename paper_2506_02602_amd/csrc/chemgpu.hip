@@ -1474,7 +1474,8 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
   // chunk, chunk again at the best block, then the hand-off point for the
   // best pair, then hand-off point and cooperative cap together (an early
   // hand-off only pays when the cap lets the cooperative kernel take the
-  // longer list), then chunk once more.  Each sweep keeps the incumbent
+  // longer list), then the two pool orders, then block and chunk once more
+  // at the final hand-off, cap and order.  Each sweep keeps the incumbent
   // unless a candidate is faster.  Finally the fastest few launches seen
   // are timed again, round-robin and with more calls each, so that one
   // noisy trial (a clock ramp, other work on the device) does not decide.
@@ -1559,12 +1560,28 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_RANGE);
   }
   {
-    // the hand-off and the order move the balance between compaction and
-    // the tail, so the chunk length is swept once more at the final choice
-    const int b0 = best_block, c0 = best_chunk, t0 = best_tail, k0 = best_cap;
-    const int ob0 = best_order;
-    for (int c : chunks)
-      if (rc == CHEM_OK && c != c0) rc = consider(b0, c, t0, k0, ob0);
+    // the hand-off, the cap and the order move the balance between
+    // compaction and the tail (the first sweeps ran at the default hand-off,
+    // where a long tail list may go to the per-lane resumption), so block
+    // and chunk are swept once more at the final choice: the whole plane
+    // for cheap calls, else chunk, block, chunk
+    const int t0 = best_tail, k0 = best_cap, ob0 = best_order;
+    if (best_ms < kTuneGridMs) {
+      const int b1 = best_block, c1 = best_chunk;
+      for (int b : blocks)
+        for (int c : chunks)
+          if (rc == CHEM_OK && !(b == b1 && c == c1)) rc = consider(b, c, t0, k0, ob0);
+    } else {
+      const int b1 = best_block, c1 = best_chunk;
+      for (int c : chunks)
+        if (rc == CHEM_OK && c != c1) rc = consider(b1, c, t0, k0, ob0);
+      const int c2 = best_chunk, b2 = best_block;
+      for (int b : blocks)
+        if (rc == CHEM_OK && b != b2) rc = consider(b, c2, t0, k0, ob0);
+      const int b3 = best_block, c3 = best_chunk;
+      for (int c : chunks)
+        if (rc == CHEM_OK && c != c3) rc = consider(b3, c, t0, k0, ob0);
+    }
   }
   if (rc == CHEM_OK && seen.size() > 1) {
     // confirmation round over the (up to) eight fastest distinct launches
