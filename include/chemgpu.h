@@ -116,6 +116,20 @@ void chem_mech_free(chem_mech m);
 int chem_workspace_reserve(chem_mech m, int64_t max_cells);
 
 /*
+ * Per-kernel timing (for measurement, not needed to integrate).  With on != 0
+ * every later chem_integrate / chem_integrate_batched / chem_react_conserved
+ * call on m records HIP events on its stream around each launch of the flow
+ * step (creating the events on first use; captured graphs are not timed);
+ * on == 0 stops it.  chem_kernel_times then waits for the last such call and
+ * writes n >= 4 durations in ms: [0] the persistent per-lane kernel, [1] the
+ * tail-list sort, [2] the cooperative kernel, [3] the per-lane resumption of
+ * the tail list (0 for those the call did not launch).  CHEM_EINVAL for a
+ * null argument, n < 4, or no timed call since timing was last set.
+ */
+int chem_set_kernel_timing(chem_mech m, int32_t on);
+int chem_kernel_times(chem_mech m, float *ms, int32_t n);
+
+/*
  * Advance n_cells cells by dt (paper Eq. 20-22), in place.
  *   status: NULL or int32[n_cells] device array of CHEM_CELL_* codes.
  *   counts: NULL or int32[2 * n_cells] device array; counts[i] = accepted

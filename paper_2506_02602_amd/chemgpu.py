@@ -65,6 +65,10 @@ _lib.chem_mech_free.argtypes = [_P]
 _lib.chem_mech_free.restype = None
 _lib.chem_workspace_reserve.argtypes = [_P, C.c_int64]
 _lib.chem_workspace_reserve.restype = C.c_int
+_lib.chem_set_kernel_timing.argtypes = [_P, C.c_int32]
+_lib.chem_set_kernel_timing.restype = C.c_int
+_lib.chem_kernel_times.argtypes = [_P, C.POINTER(C.c_float), C.c_int32]
+_lib.chem_kernel_times.restype = C.c_int
 _lib.chem_integrate.argtypes = [_P, _P, C.c_int64, C.c_int64, C.c_double,
                                 C.POINTER(chem_opts), _P, _P, _P]
 _lib.chem_integrate.restype = C.c_int
@@ -140,6 +144,17 @@ def chem_mech_load(path: str) -> Mechanism:
 
 def chem_workspace_reserve(mech: Mechanism, max_cells: int) -> None:
     _check(_lib.chem_workspace_reserve(mech.handle, int(max_cells)), "chem_workspace_reserve")
+
+
+def chem_set_kernel_timing(mech: Mechanism, on: bool = True) -> None:
+    _check(_lib.chem_set_kernel_timing(mech.handle, 1 if on else 0), "chem_set_kernel_timing")
+
+
+def chem_kernel_times(mech: Mechanism) -> dict:
+    """Durations (ms) of the last timed call's launches (waits for it)."""
+    ms = (C.c_float * 4)()
+    _check(_lib.chem_kernel_times(mech.handle, ms, 4), "chem_kernel_times")
+    return {"persistent": ms[0], "tail_sort": ms[1], "coop": ms[2], "resume": ms[3]}
 
 
 def chem_integrate(mech: Mechanism, state, dt: float, opts: chem_opts | None = None,
@@ -421,4 +436,5 @@ def exported_symbols():
             "chem_last_error", "surrogate_create", "surrogate_query", "surrogate_get_params",
             "surrogate_set_params", "surrogate_make_pairs", "surrogate_train", "surrogate_forward",
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
-            "surrogate_free", "chem_eval_exp", "chem_eval_math", "chem_react_conserved"]
+            "surrogate_free", "chem_eval_exp", "chem_eval_math", "chem_react_conserved",
+            "chem_set_kernel_timing", "chem_kernel_times"]

@@ -745,6 +745,12 @@ struct chem_mech_s {
   double* d_prim = nullptr;        // primitive work state of chem_react_conserved
   int8_t* d_flag = nullptr;
   int64_t prim_cap = 0;
+  // optional per-kernel timing of plain (not captured) calls: events around
+  // the persistent launch, the tail sort, the cooperative launch and the
+  // resumption launch of the last call
+  bool timing = false;
+  bool timed_last = false;
+  hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 struct chem_graph_s {
@@ -919,9 +925,10 @@ int grid_for(chem_mech m, int block, int64_t total, int scheme);
 // work, chosen by the list's length against a.tail.cap: several lanes per
 // cell only pay while the tail is short next to the chip).
 hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_t s,
-                       const OrderBuf* ob) {
+                       const OrderBuf* ob, bool timed = false) {
   hipError_t e;
   a.order = nullptr;
+  hipEvent_t* tv = timed ? m->tev : nullptr;
   if (ob && a.total > 0 && !a.total_dev && !a.resume) {
     // the dealt pool order: R = the resident blocks (the grid), B = block
     const int64_t per = (int64_t)kOrderBlock * kOrderRounds;
@@ -933,19 +940,32 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
     if ((e = hipGetLastError()) != hipSuccess) return e;
     a.order = ob->order;
   }
+  if (tv && (e = hipEventRecord(tv[0], s)) != hipSuccess) return e;
   e = m->entry->launch_persistent(a, block, grid, s);
-  if (e != hipSuccess || a.tail_steps <= 0) return e;
+  if (e != hipSuccess) return e;
+  if (tv && (e = hipEventRecord(tv[1], s)) != hipSuccess) return e;
+  if (a.tail_steps <= 0) {
+    // no tail: the remaining intervals are empty
+    for (int k = 2; tv && k < 5; ++k)
+      if ((e = hipEventRecord(tv[k], s)) != hipSuccess) return e;
+    return hipSuccess;
+  }
   hipLaunchKernelGGL(tail_order, dim3(1), dim3(1024), 0, s, a.tail);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (tv && (e = hipEventRecord(tv[2], s)) != hipSuccess) return e;
   e = m->entry->launch_coop(a, m->n_cu, s);
   if (e != hipSuccess) return e;
+  if (tv && (e = hipEventRecord(tv[3], s)) != hipSuccess) return e;
   PoolArgs r = a;
   r.resume = 1;
   r.tail_steps = 0;
   r.next = a.tail.next;
   r.total_dev = nullptr;
   r.order = nullptr;
-  return m->entry->launch_persistent(r, block, grid, s);
+  e = m->entry->launch_persistent(r, block, grid, s);
+  if (e != hipSuccess) return e;
+  if (tv && (e = hipEventRecord(tv[4], s)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 // The integrator over a work pool with a given pool counter and tail store
@@ -978,9 +998,11 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
     ob.mode = omode;
     ob.t_split = m->entry->t_split;
   }
+  const bool timed = m->timing && next == m->d_next;  // the mechanism's own pool only
   hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s,
-                             ordered ? &ob : nullptr);
+                             ordered ? &ob : nullptr, timed);
   if (e != hipSuccess) return hip_fail(e, "launch integrator kernels");
+  if (timed) m->timed_last = true;
   return CHEM_OK;
 }
 
@@ -1162,6 +1184,8 @@ int chem_mech_query(chem_mech m, int32_t* n_species, int32_t* n_reactions, uint6
 void chem_mech_free(chem_mech m) {
   if (!m) return;
   // teardown: errors have nowhere to go
+  for (hipEvent_t& ev : m->tev)
+    if (ev) (void)hipEventDestroy(ev);
   if (m->boxes_copied) {
     (void)hipEventSynchronize(m->boxes_copied);
     (void)hipEventDestroy(m->boxes_copied);
@@ -1184,6 +1208,33 @@ int chem_workspace_reserve(chem_mech m, int64_t max_cells) {
   rc = ensure_tail(m->tail, m->reserved);
   if (rc) return rc;
   return ensure_order(m->order, m->reserved);
+}
+
+int chem_set_kernel_timing(chem_mech m, int32_t on) {
+  if (!m) return fail(CHEM_EINVAL, "chem_set_kernel_timing: null mechanism");
+  if (on) {
+    for (hipEvent_t& ev : m->tev) {
+      if (ev) continue;
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) { ev = nullptr; return hip_fail(e, "hipEventCreate(kernel timing)"); }
+    }
+  }
+  m->timing = on != 0;
+  m->timed_last = false;
+  return CHEM_OK;
+}
+
+int chem_kernel_times(chem_mech m, float* ms, int32_t n) {
+  if (!m || !ms || n < 4) return fail(CHEM_EINVAL, "chem_kernel_times: bad argument");
+  if (!m->timed_last) return fail(CHEM_EINVAL, "chem_kernel_times: no timed call since timing was set");
+  hipError_t e = hipEventSynchronize(m->tev[4]);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(kernel timing)");
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = 0.0f;
+    e = hipEventElapsedTime(&ms[k], m->tev[k], m->tev[k + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime(kernel timing)");
+  }
+  return CHEM_OK;
 }
 
 int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, double dt,

@@ -272,3 +272,24 @@ def test_pool_order_batched_and_graph(cg, gm9, mech9_path):
         for b, e in zip(boxes, off):
             assert torch.equal(b["state"], e["state"]), f"replay {rep}"
     g.close()
+
+
+def test_kernel_timing_reports_each_launch(cg, gm9, mech9_path):
+    """Per-kernel timing: refused before any timed call; after one, the
+    persistent, tail-sort, cooperative and resumption durations are reported
+    (the cooperative kernel ran, the list being under the cap); timing
+    changes no result."""
+    from gpu_common import run_gpu
+    s0, hot = wl.front_2d(mech9_path, nx=256, ny=256, seed=71)
+    kw = dict(block_size=256, chunk_steps=1, tail_steps=8, tail_cap=-1)
+    cg.chem_set_kernel_timing(gm9, True)
+    with pytest.raises(cg.ChemError):
+        cg.chem_kernel_times(gm9)
+    on = run_gpu(gm9, s0, wl.DT_FLOW, **kw)
+    kt = cg.chem_kernel_times(gm9)
+    cg.chem_set_kernel_timing(gm9, False)
+    off = run_gpu(gm9, s0, wl.DT_FLOW, **kw)
+    assert all(np.array_equal(x, y) for x, y in zip(on, off))
+    assert set(kt) == {"persistent", "tail_sort", "coop", "resume"}
+    assert all(v >= 0.0 for v in kt.values())
+    assert kt["persistent"] > 0.0 and kt["coop"] > 0.0
