@@ -203,25 +203,36 @@ __device__ __forceinline__ double coop_rhs(double Yk, double T, double rho, doub
     const double qj = tb >= 0 ? mt * qraw : qraw;
     s[j0 < C::J ? S::SQ + j : S::SX + gl] = qj;
   }
-  // sum_k c_k (cp_k/R - 1), the same order on every lane
-  double den = 0.0;
+  // sum_k c_k (cp_k/R - 1), the same order on every lane (two interleaved
+  // partial sums: half the dependent chain)
+  double den0 = 0.0, den1 = 0.0;
 #pragma unroll
-  for (int kk = 0; kk < N; ++kk) den += s[S::SD + kk];
+  for (int kk = 0; kk < N; ++kk) {
+    if (kk & 1) den1 += s[S::SD + kk];
+    else den0 += s[S::SD + kk];
+  }
+  const double den = den0 + den1;
   coop_sync();
-  // species k: production rate
-  double wk = 0.0;
+  // species k: production rate (two partial sums)
+  double wk0 = 0.0, wk1 = 0.0;
 #pragma unroll
   for (int l = 0; l < C::L; ++l) {
+    double& acc = (l & 1) ? wk1 : wk0;
     if constexpr (PRE)
-      wk += ln.slnu[l] * s[S::SQ + ln.slj[l]];
+      acc = fma(ln.slnu[l], s[S::SQ + ln.slj[l]], acc);
     else
-      wk += D[C::O_SLNU + k * C::L + l] * s[S::SQ + I[C::O_SLJ + k * C::L + l]];
+      acc = fma(D[C::O_SLNU + k * C::L + l], s[S::SQ + I[C::O_SLJ + k * C::L + l]], acc);
   }
+  const double wk = wk0 + wk1;
   s[sl ? S::SW + k : S::SX + gl] = hm1 * wk;
   coop_sync();
-  double num = 0.0;
+  double num0 = 0.0, num1 = 0.0;
 #pragma unroll
-  for (int kk = 0; kk < N; ++kk) num += s[S::SW + kk];
+  for (int kk = 0; kk < N; ++kk) {
+    if (kk & 1) num1 += s[S::SW + kk];
+    else num0 += s[S::SW + kk];
+  }
+  const double num = num0 + num1;
   fT = -T * num * rcp_nr(den);
   return sl ? wk * (D[C::O_WK + k] * inv_rho) : 0.0;
 }
