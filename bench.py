@@ -79,10 +79,10 @@ def parse():
 # reads for the restore copy of known size in the same run (FETCH_SIZE
 # reports 0.5002 of the copied bytes, WRITE_SIZE 1.000).  Keyed by a digest of
 # the kernel sources the counters were taken on; any change nulls it.
-TRAFFIC = {"front": ("64fe02900c3daf56", 237.1e6,
-                     {"lsrk_persistent": 203.23e6, "lsrk_coop": 33.70e6}),
-           "stress9": ("64fe02900c3daf56", 3605.9e6,
-                       {"lsrk_persistent": 3518.74e6, "lsrk_coop": 0.04e6})}
+TRAFFIC = {"front": ("5c9d19c03c3dbae1", 232.9e6,
+                     {"lsrk_persistent": 203.20e6, "lsrk_coop": 29.54e6}),
+           "stress9": ("5c9d19c03c3dbae1", 3605.3e6,
+                       {"lsrk_persistent": 3518.15e6, "lsrk_coop": 0.04e6})}
 
 
 def kernel_digest():
