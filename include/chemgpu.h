@@ -36,7 +36,7 @@ extern "C" {
 #define CHEM_EHIP (-3)         /* a HIP runtime call failed (message has the HIP error) */
 #define CHEM_EPARSE (-4)       /* mechanism file unreadable or malformed (message has the line) */
 #define CHEM_EUNSUPPORTED (-5) /* no kernel was built for this mechanism's content hash */
-#define CHEM_ECAPACITY (-6)    /* more cells than the reserved workspace holds */
+#define CHEM_ECAPACITY (-6)    /* reserved: no call returns it (calls past a reservation grow it) */
 
 /* Per-cell status codes written to the status array. */
 #define CHEM_CELL_OK 0          /* reached dt */
@@ -110,9 +110,15 @@ int chem_mech_query(chem_mech m, int32_t *n_species, int32_t *n_reactions, uint6
 /* Release a mechanism and its workspace (destroy its graphs first). */
 void chem_mech_free(chem_mech m);
 
-/* Reserve the device workspace (work queue, per-cell progress, tail records,
- * pool order) for up to max_cells cells.  All device allocation of the integrate calls happens here
- * or, if never called, on the first integrate call that needs it. */
+/* Reserve the device workspace (work-queue counter, tail records, pool
+ * order) for up to max_cells cells.  After it, chem_integrate calls on up
+ * to max_cells cells allocate no device memory, and neither do
+ * chem_integrate_batched calls once an earlier batched call with at least
+ * as many boxes has sized the box table (one entry per box).  Without a
+ * reservation, or past it, a call that needs more grows the workspace.
+ * chem_react_conserved's primitive work state is not allocated here; its
+ * first call allocates it for max(n_cells, max_cells) cells.  CHEM_EINVAL
+ * for a null handle or max_cells < 0. */
 int chem_workspace_reserve(chem_mech m, int64_t max_cells);
 
 /*

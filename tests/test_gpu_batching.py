@@ -293,3 +293,48 @@ def test_kernel_timing_reports_each_launch(cg, gm9, mech9_path):
     assert set(kt) == {"persistent", "tail_sort", "coop", "resume"}
     assert all(v >= 0.0 for v in kt.values())
     assert kt["persistent"] > 0.0 and kt["coop"] > 0.0
+
+
+def test_reserved_workspace_allocates_nothing_later(cg, gm9, mech9_path):
+    """After chem_workspace_reserve(n), plain and batched calls on up to n
+    cells (tail list and pool order on) take no device memory: free device
+    memory is the same before and after them, where the same calls on a
+    handle that was not reserved take ~11 MB for tail records and order
+    arrays.  Both handles give bitwise the same results; a negative size is
+    refused."""
+    import torch
+    big, small = 262144, 4096
+    s0 = wl.cells_uniform(mech9_path, n=big, seed=73)
+    o = cg.make_opts(block_size=256, chunk_steps=2, tail_steps=2, tail_cap=-1, pool_order=2)
+    half = big // 2
+    outs, drops = [], []
+    for reserve in (True, False):
+        m = cg.chem_mech_load(mech9_path)
+        try:
+            if reserve:
+                cg.chem_workspace_reserve(m, big)
+            part = [torch.from_numpy(np.ascontiguousarray(s0[:, a:a + small])).cuda()
+                    for a in (0, small, 2 * small)]
+            st = torch.from_numpy(s0.copy()).cuda()
+            sa = torch.from_numpy(np.ascontiguousarray(s0[:, :half])).cuda()
+            sb = torch.from_numpy(np.ascontiguousarray(s0[:, half:])).cuda()
+            # first calls load the kernels and size the box table (two boxes)
+            cg.chem_integrate(m, part[0], wl.DT_FLOW, o)
+            cg.chem_integrate_batched(m, [dict(state=part[1], dt=wl.DT_FLOW),
+                                          dict(state=part[2], dt=wl.DT_FLOW / 2, n_sub=2)], o)
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            cg.chem_integrate(m, st, wl.DT_FLOW, o)
+            cg.chem_integrate_batched(m, [dict(state=sa, dt=wl.DT_FLOW),
+                                          dict(state=sb, dt=wl.DT_FLOW / 2, n_sub=2)], o)
+            torch.cuda.synchronize()
+            drops.append(free0 - torch.cuda.mem_get_info()[0])
+            outs.append([t.cpu().numpy() for t in (st, sa, sb)])
+        finally:
+            m.close()
+    assert drops[0] == 0, drops
+    assert drops[1] > 8e6, drops
+    assert all(np.array_equal(x, y) for x, y in zip(outs[0], outs[1]))
+    with pytest.raises(cg.ChemError) as e:
+        cg.chem_workspace_reserve(gm9, -1)
+    assert e.value.code == -1
