@@ -67,3 +67,49 @@ def test_react_conserved_matches_oracle(omech9, mech9_path):
         assert units < 500
     # mass: sum_k rho Y_k stays rho to rounding
     assert np.allclose(out[5:14, ok].sum(axis=0), out[0, ok], rtol=1e-13)
+
+
+def test_react_conserved_full_front_sampled(omech9, mech9_path):
+    """The whole 1024 x 1024 front field (1,048,576 cells, 2 % hot band) in
+    one call with the default launch, ld > n: the padding columns are not
+    touched, rho, momentum and rho E of every cell are not touched, sum_k
+    rho Y_k stays rho, every cell ends OK, and a seeded sample of 300 hot
+    and 100 cold cells equals the oracle's conserved-variable step to the
+    parity bar of one flow step.  Temperature guesses: the previous
+    temperature, as a flow solver carries it, off by up to 5 %."""
+    import torch
+    from paper_2506_02602_amd import chemgpu as cg
+    rng = np.random.Generator(np.random.PCG64(67))
+    s, hot = wl.front_2d(mech9_path, nx=1024, ny=1024, seed=67)
+    N, n = 9, s.shape[1]
+    ld = n + 37
+    e = np.array([omech9.energy(s[0, i], s[1:N + 1, i])[0] for i in range(n)])
+    vel = rng.uniform(-5e4, 5e4, (3, n))
+    c0 = np.full((N + 7, ld), 123.0)
+    c0[0, :n] = s[N + 1]
+    c0[1:4, :n] = s[N + 1] * vel
+    c0[4, :n] = s[N + 1] * (e + 0.5 * (vel ** 2).sum(axis=0))
+    c0[5:5 + N, :n] = s[N + 1] * s[1:N + 1]
+    c0[5 + N, :n] = s[0] * rng.uniform(0.95, 1.05, n)
+    c0[6 + N, :n] = 0.0
+    m = cg.chem_mech_load(mech9_path)
+    g = to_gpu(c0)
+    st = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+    cg.chem_react_conserved(m, g, wl.DT_FLOW, status=st, n_cells=n)
+    torch.cuda.synchronize()
+    out = g.cpu().numpy()
+    assert (st.cpu().numpy() == 0).all()
+    assert (out[:, n:] == 123.0).all()
+    assert np.array_equal(out[:5, :n], c0[:5, :n])
+    assert np.allclose(out[5:5 + N, :n].sum(axis=0), out[0, :n], rtol=1e-13)
+    idx = np.concatenate([rng.choice(np.where(hot)[0], 300, replace=False),
+                          rng.choice(np.where(~hot)[0], 100, replace=False)])
+    c = np.ascontiguousarray(c0[:, idx])
+    cst, _ = omech9.react_conserved(c, wl.DT_FLOW)
+    assert (cst == 0).all()
+
+    def prim(a):
+        return np.vstack([a[5 + N], a[5:5 + N] / a[0]])
+    bad = parity_violations(prim(out[:, idx]), prim(c), 9)
+    print(f"[conserved full] {n} cells, sample {idx.size}, {int(bad.sum())} flagged", flush=True)
+    assert bad.mean() <= 0.02
