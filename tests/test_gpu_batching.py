@@ -338,3 +338,58 @@ def test_reserved_workspace_allocates_nothing_later(cg, gm9, mech9_path):
     with pytest.raises(cg.ChemError) as e:
         cg.chem_workspace_reserve(gm9, -1)
     assert e.value.code == -1
+
+
+def test_front_field_in_the_timed_launch(cg, omech9, mech9_path):
+    """The 1024 x 1024 front field exactly as the benchmark times it: the
+    committed launch cache (read from a copy, which must come back
+    unchanged: a hit, no tuning), the workspace reserved, the one-box
+    batched call captured in a graph and replayed three times from the
+    pristine field.  Every replay equals the eager batched call bitwise, the
+    eager call equals a plain call with the tuned launch spelled out, and
+    that launch meets the parity bar against the oracle on every hot cell
+    and a seeded sample of 20,000 cold cells."""
+    import shutil
+    import torch
+    from gpu_common import assert_parity, run_gpu
+    s0, hot = wl.front_2d(mech9_path)
+    n = s0.shape[1]
+    fd, cache = tempfile.mkstemp(suffix=".json")
+    os.close(fd)
+    shutil.copy(os.path.join(os.path.dirname(cg.__file__), "tuning_gfx950.json"), cache)
+    before = open(cache).read()
+    m = cg.chem_mech_load(mech9_path)
+    try:
+        cg.chem_workspace_reserve(m, n)
+        base = cg.make_opts(rtol=wl.RTOL, atol=wl.ATOL)
+        pristine = to_gpu(s0)
+        st = pristine.clone()
+        tb = cg.chem_autotune(m, [dict(state=st, dt=wl.DT_FLOW)], base, reps=3, cache_path=cache)
+        assert open(cache).read() == before
+        assert torch.equal(st, pristine)
+        cg.chem_integrate_batched(m, [dict(state=st, dt=wl.DT_FLOW)], base)
+        torch.cuda.synchronize()
+        eager = st.cpu().numpy()
+        g = cg.chem_graph_capture_batched(m, [dict(state=st, dt=wl.DT_FLOW)], base)
+        try:
+            for rep in range(3):
+                st.copy_(pristine)
+                g.launch()
+                torch.cuda.synchronize()
+                assert np.array_equal(st.cpu().numpy(), eager), f"replay {rep}"
+        finally:
+            g.close()
+    finally:
+        m.close()
+        os.unlink(cache)
+    launch = dict(rtol=wl.RTOL, atol=wl.ATOL, block_size=tb.block_size,
+                  chunk_steps=tb.chunk_steps, tail_steps=tb.tail_steps,
+                  tail_cap=tb.tail_cap, pool_order=tb.pool_order)
+    gm = cg.chem_mech_load(mech9_path)
+    assert np.array_equal(run_gpu(gm, s0, wl.DT_FLOW, **launch)[0], eager)
+    rng = np.random.Generator(np.random.PCG64(79))
+    idx = np.concatenate([np.where(hot)[0],
+                          rng.choice(np.where(~hot)[0], 20000, replace=False)])
+    assert_parity(gm, omech9, s0, wl.DT_FLOW, idx=idx, label="front 1024^2, timed launch",
+                  max_flag_frac=0.02, **launch)
+    gm.close()
