@@ -1,4 +1,6 @@
 """Shared helpers for the GPU parity tests (HIP path vs the CPU oracle)."""
+import os
+
 import numpy as np
 
 # Parity bar for one flow step from identical inputs: per component
@@ -110,3 +112,25 @@ def oracle_subcalls(om, state, dt, n_sub, **kw):
         status[live] = st
         live = live[st == 0]
     return s, status, counts
+
+
+def tuned_launch(mech, boxes, rtol=1e-8, atol=1e-10):
+    """The launch the committed tuning cache holds for these boxes, read
+    through chem_autotune from a copy of the cache that must come back
+    unchanged (a hit: nothing is tuned or timed).  Returns make_opts
+    keywords with every launch field spelled out."""
+    import shutil
+    import tempfile
+    from paper_2506_02602_amd import chemgpu
+    fd, cache = tempfile.mkstemp(suffix=".json")
+    os.close(fd)
+    try:
+        shutil.copy(os.path.join(os.path.dirname(chemgpu.__file__), "tuning_gfx950.json"), cache)
+        before = open(cache).read()
+        tb = chemgpu.chem_autotune(mech, boxes, chemgpu.make_opts(rtol=rtol, atol=atol), reps=1,
+                                   cache_path=cache)
+        assert open(cache).read() == before, "no cached launch for this workload"
+    finally:
+        os.unlink(cache)
+    return dict(rtol=rtol, atol=atol, block_size=tb.block_size, chunk_steps=tb.chunk_steps,
+                tail_steps=tb.tail_steps, tail_cap=tb.tail_cap, pool_order=tb.pool_order)

@@ -9,23 +9,30 @@ import pytest
 
 from paper_2506_02602_amd import workloads as wl
 
-from gpu_common import oracle_subcalls, parity_violations, to_gpu
+from gpu_common import oracle_subcalls, parity_violations, to_gpu, tuned_launch
 
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("launch", ["default", "tuned"])
 @pytest.mark.parametrize("alpha", [1.0, 0.1])
-def test_divergence_field_matches_oracle(omech9, mech9_path, alpha):
+def test_divergence_field_matches_oracle(omech9, mech9_path, alpha, launch):
+    """With the library's default launch and with the launch the committed
+    tuning cache holds for this field (the one the benchmark times)."""
     import torch
     from paper_2506_02602_amd import chemgpu as cg
     m = cg.chem_mech_load(mech9_path)
     s0 = wl.diverge_box(mech9_path, alpha)
     n = s0.shape[1]
     g = to_gpu(s0)
+    opts = None
+    if launch == "tuned":
+        kw = tuned_launch(m, [dict(state=g, dt=wl.DIVERGE_DT, n_sub=wl.DIVERGE_CALLS)])
+        opts = cg.make_opts(**kw)
     st = torch.full((n,), -7, dtype=torch.int32, device="cuda")
     cn = torch.full((2 * n,), -7, dtype=torch.int32, device="cuda")
     cg.chem_integrate_batched(m, [dict(state=g, dt=wl.DIVERGE_DT, n_sub=wl.DIVERGE_CALLS,
-                                       status=st, counts=cn)])
+                                       status=st, counts=cn)], opts)
     torch.cuda.synchronize()
     out = g.cpu().numpy()
     gst = st.cpu().numpy()

@@ -10,7 +10,8 @@ import pytest
 import oracle
 from paper_2506_02602_amd import workloads as wl
 
-from gpu_common import assert_parity, max_rel, parity_violations, run_gpu, to_gpu
+from gpu_common import (assert_parity, max_rel, parity_violations, run_gpu, to_gpu,
+                        tuned_launch)
 
 pytestmark = pytest.mark.gpu
 
@@ -196,27 +197,13 @@ def test_stress_field_full_size_in_the_tuned_launch(chemgpu, request, name, stri
     with the launch the committed tuning cache holds for it (read from a
     copy that must come back unchanged: a hit, no tuning); every stride-th
     cell against the oracle."""
-    import shutil
     gm = request.getfixturevalue(f"g{name}")
     om = request.getfixturevalue(f"o{name}")
     path = request.getfixturevalue(f"{name}_path")
     s0 = wl.stress_3d(path)
-    fd, cache = tempfile.mkstemp(suffix=".json")
-    os.close(fd)
-    shutil.copy(os.path.join(os.path.dirname(chemgpu.__file__), "tuning_gfx950.json"), cache)
-    before = open(cache).read()
-    try:
-        base = chemgpu.make_opts(rtol=wl.RTOL, atol=wl.ATOL)
-        g = to_gpu(s0)
-        tb = chemgpu.chem_autotune(gm, [dict(state=g, dt=wl.DT_FLOW)], base, reps=1,
-                                   cache_path=cache)
-        assert open(cache).read() == before
-        del g
-    finally:
-        os.unlink(cache)
-    launch = dict(rtol=wl.RTOL, atol=wl.ATOL, block_size=tb.block_size,
-                  chunk_steps=tb.chunk_steps, tail_steps=tb.tail_steps,
-                  tail_cap=tb.tail_cap, pool_order=tb.pool_order)
+    g = to_gpu(s0)
+    launch = tuned_launch(gm, [dict(state=g, dt=wl.DT_FLOW)], wl.RTOL, wl.ATOL)
+    del g
     idx = np.arange(0, s0.shape[1], stride)
     assert_parity(gm, om, s0, wl.DT_FLOW, idx=idx,
                   label=f"stress 256x256x64 {name}, tuned launch", **launch)
