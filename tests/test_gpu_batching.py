@@ -164,15 +164,20 @@ def test_autotune_keeps_data_and_caches(cg, mech9_path):
             os.unlink(cache)
 
 
-def test_full_amr_hierarchy_sampled(cg, gm9, omech9, mech9_path):
-    """The full 3-level, 96-box hierarchy in one graph launch; the oracle checks
-    up to 400 sampled cells per box (all of them hot on level 2)."""
+@pytest.mark.parametrize("launch", ["default", "tuned"])
+def test_full_amr_hierarchy_sampled(cg, gm9, omech9, mech9_path, launch):
+    """The full 3-level, 96-box hierarchy in one graph launch, with the
+    library's default launch and with the one the committed tuning cache
+    holds for it (the benchmark's); the oracle checks up to 400 sampled
+    cells per box (all of them hot on level 2)."""
     import torch
+    from gpu_common import tuned_launch
     hier = wl.amr_hierarchy(mech9_path)
     ncells = sum(b["state"].shape[1] for b in hier)
     print(f"[amr] {len(hier)} boxes, {ncells} cells", flush=True)
     boxes = gpu_boxes(hier)
-    g = cg.chem_graph_capture_batched(gm9, boxes)
+    opts = cg.make_opts(**tuned_launch(gm9, boxes)) if launch == "tuned" else None
+    g = cg.chem_graph_capture_batched(gm9, boxes, opts)
     g.launch()
     torch.cuda.synchronize()
     rng = np.random.Generator(np.random.PCG64(99))
