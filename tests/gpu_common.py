@@ -114,7 +114,7 @@ def oracle_subcalls(om, state, dt, n_sub, **kw):
     return s, status, counts
 
 
-def tuned_launch(mech, boxes, rtol=1e-8, atol=1e-10):
+def tuned_launch(mech, boxes, rtol=1e-8, atol=1e-10, scheme="lsrk"):
     """The launch the committed tuning cache holds for these boxes, read
     through chem_autotune from a copy of the cache that must come back
     unchanged (a hit: nothing is tuned or timed).  Returns make_opts
@@ -127,10 +127,11 @@ def tuned_launch(mech, boxes, rtol=1e-8, atol=1e-10):
     try:
         shutil.copy(os.path.join(os.path.dirname(chemgpu.__file__), "tuning_gfx950.json"), cache)
         before = open(cache).read()
-        tb = chemgpu.chem_autotune(mech, boxes, chemgpu.make_opts(rtol=rtol, atol=atol), reps=1,
-                                   cache_path=cache)
+        base = chemgpu.make_opts(rtol=rtol, atol=atol, scheme=scheme)
+        tb = chemgpu.chem_autotune(mech, boxes, base, reps=1, cache_path=cache)
         assert open(cache).read() == before, "no cached launch for this workload"
     finally:
         os.unlink(cache)
-    return dict(rtol=rtol, atol=atol, block_size=tb.block_size, chunk_steps=tb.chunk_steps,
-                tail_steps=tb.tail_steps, tail_cap=tb.tail_cap, pool_order=tb.pool_order)
+    return dict(rtol=rtol, atol=atol, scheme=scheme, block_size=tb.block_size,
+                chunk_steps=tb.chunk_steps, tail_steps=tb.tail_steps, tail_cap=tb.tail_cap,
+                pool_order=tb.pool_order)

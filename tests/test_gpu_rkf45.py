@@ -62,3 +62,19 @@ def test_rkf45_chunk_and_block_invariance(gm9, mech9_path):
     for chunk, block in [(1, 64), (16, 256), (5, 512)]:
         g = run_gpu(gm9, s0, wl.DT_FLOW, chunk_steps=chunk, block_size=block, scheme="rkf45")
         assert all(np.array_equal(x, y) for x, y in zip(g, ref))
+
+
+def test_rkf45_front_field_in_its_tuned_launch(gm9, omech9, mech9_path):
+    """The full 1024 x 1024 front field in the launch the committed tuning
+    cache holds for this scheme (the one the benchmark's scheme comparison
+    times); 4,000 hot and 2,000 cold cells, seeded, against the oracle."""
+    from gpu_common import to_gpu, tuned_launch
+    s0, hot = wl.front_2d(mech9_path)
+    g = to_gpu(s0)
+    launch = tuned_launch(gm9, [dict(state=g, dt=wl.DT_FLOW)], wl.RTOL, wl.ATOL, scheme="rkf45")
+    del g
+    rng = np.random.Generator(np.random.PCG64(83))
+    idx = np.concatenate([rng.choice(np.where(hot)[0], 4000, replace=False),
+                          rng.choice(np.where(~hot)[0], 2000, replace=False)])
+    assert_parity(gm9, omech9, s0, wl.DT_FLOW, idx=idx, label="rkf45 front 1024^2, tuned launch",
+                  max_flag_frac=0.05, **launch)

@@ -124,3 +124,19 @@ def test_ros4_batched_boxes_match_single_calls(gm9, mech9_path):
     torch.cuda.synchronize()
     assert np.array_equal(ga.cpu().numpy(), ra)
     assert np.array_equal(gb.cpu().numpy(), hb.cpu().numpy())
+
+
+def test_ros4_front_field_in_its_tuned_launch(gm9, omech9, mech9_path):
+    """The full 1024 x 1024 front field in the launch the committed tuning
+    cache holds for this scheme (the one the benchmark's scheme comparison
+    times); 4,000 hot and 2,000 cold cells, seeded, against the oracle."""
+    from gpu_common import to_gpu, tuned_launch
+    s0, hot = wl.front_2d(mech9_path)
+    g = to_gpu(s0)
+    launch = tuned_launch(gm9, [dict(state=g, dt=wl.DT_FLOW)], wl.RTOL, wl.ATOL, scheme="ros4")
+    del g
+    rng = np.random.Generator(np.random.PCG64(83))
+    idx = np.concatenate([rng.choice(np.where(hot)[0], 4000, replace=False),
+                          rng.choice(np.where(~hot)[0], 2000, replace=False)])
+    assert_parity(gm9, omech9, s0, wl.DT_FLOW, idx=idx, label="ros4 front 1024^2, tuned launch",
+                  max_flag_frac=0.05, **launch)
