@@ -33,14 +33,32 @@ def build() -> str:
 
 
 _lib = None
+_lib_path = LIB_PATH
+
+
+def use_native_build(out_dir: str) -> str:
+    """Compile the oracle for the host that runs it (-O3 -march=native; still
+    no FP contraction and no fast-math, so it computes the same numbers as
+    the portable build) into out_dir and make it the library this module
+    loads.  Must be called before the library is first used.  For timing the
+    oracle on the machine it runs on; the tests use the portable build."""
+    global _lib_path
+    if _lib is not None:
+        raise RuntimeError("oracle library already loaded")
+    path = os.path.join(out_dir, f"liboracle_native_{os.getpid()}.so")
+    cmd = ["gcc", "-O3", "-march=native", "-std=c99", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-fPIC", "-shared", "-o", path, SRC_PATH, "-lm"]
+    subprocess.run(cmd, check=True)
+    _lib_path = path
+    return path
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        if not os.path.exists(_lib_path):
             build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(_lib_path)
         P, D, I = C.c_void_p, C.c_double, C.c_int
         L.or_mech_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
         L.or_mech_load.restype = I
@@ -74,8 +92,18 @@ def lib():
         L.or_integrate_scheme.restype = I
         L.or_integrate_linear_scheme.argtypes = [I] + L.or_integrate_linear.argtypes
         L.or_integrate_linear_scheme.restype = I
+        L.or_set_perturbation.argtypes = [I]
+        L.or_set_perturbation.restype = None
         _lib = L
     return _lib
+
+
+def set_perturbation(mode: int) -> None:
+    """Last-bit perturbations of the oracle (bits: 1 k_f one ulp up, 2 the
+    step factor via two square roots, 4 production rates summed in reverse
+    reaction order, 8 k_r from one exponential); 0 = off.  For the parity
+    budget study only; process-wide, set while nothing integrates."""
+    lib().or_set_perturbation(int(mode))
 
 
 def _ptr(a: np.ndarray):

@@ -259,6 +259,23 @@ void or_thermo(const or_mech *m, double T, double *cp_R, double *h_RT, double *s
     }
 }
 
+/* ------------------------------------------------- last-bit perturbations */
+/* Off (0) by default.  The test suite switches these on to measure how far
+ * two correct FP64 integrations of one cell can end apart when they differ
+ * only in the last bit of intermediate results, the way any two
+ * implementations do (the bound the GPU parity tests use for cells whose
+ * accept/reject sequence flips).  Each bit changes one rounding, not the
+ * formula:
+ *   1  k_f one ulp up (nextafter towards +inf);
+ *   2  the step factor's err^(-1/4) taken as 1/sqrt(sqrt(err));
+ *   4  wdot accumulated over the reactions in reverse order;
+ *   8  k_r from one exponential, exp(ln k_f + dG - dnu ln(pstd/RT)), instead
+ *      of k_f / (exp(-dG) (pstd/RT)^dnu).
+ * Process-wide; set it only while no integration is running. */
+static int or_perturb = 0;
+
+void or_set_perturbation(int mode) { or_perturb = mode; }
+
 /* ------------------------------------------------------------------- rates */
 /* Eq. 16 and the Arrhenius / equilibrium-constant rates.  u = (T, Y_1..Y_N).
  * Outputs per reaction (kf, kr, q) and per species wdot [mol/(cm^3 s)]; any
@@ -272,9 +289,11 @@ void or_rates(const or_mech *m, double rho, const double *u,
     or_thermo(m, T, cp, h, s);
     for (int k = 0; k < ns; k++) c[k] = rho * u[1 + k] / m->W[k];
     if (wdot) for (int k = 0; k < ns; k++) wdot[k] = 0.0;
-    for (int j = 0; j < m->nr; j++) {
+    for (int jj = 0; jj < m->nr; jj++) {
+        const int j = (or_perturb & 4) ? m->nr - 1 - jj : jj;
         const or_reaction *r = &m->rx[j];
         double kf = r->A * pow(T, r->b) * exp(-r->Ea / (OR_R_J * T));
+        if (or_perturb & 1) kf = nextafter(kf, INFINITY);
         /* Kc = exp(-sum_k nu_jk g_k/RT) * (pstd/(R T))^(sum_k nu_jk) */
         double dG = 0.0;
         int dnu = 0;
@@ -290,6 +309,7 @@ void or_rates(const or_mech *m, double rho, const double *u,
         }
         double Kc = exp(-dG) * pow(m->pstd / (OR_R_CGS * T), (double)dnu);
         double kr = kf / Kc;
+        if (or_perturb & 8) kr = exp(log(kf) + dG - dnu * log(m->pstd / (OR_R_CGS * T)));
         double fwd = kf, rev = kr;
         for (int i = 0; i < r->n_reac; i++)
             for (int n = 0; n < r->reac_nu[i]; n++) fwd *= c[r->reac_sp[i]];
@@ -599,6 +619,7 @@ static double step_factor(double err, double expo) {
     if (err != err) return 0.2;
     if (err == 0.0) return 5.0;
     double fac = 0.9 * pow(err, -expo);
+    if ((or_perturb & 2) && expo == 0.25) fac = 0.9 * (1.0 / sqrt(sqrt(err)));
     if (fac < 0.2) fac = 0.2;
     if (fac > 5.0) fac = 5.0;
     return fac;

@@ -9,7 +9,7 @@ import pytest
 
 from paper_2506_02602_amd import workloads as wl
 
-from gpu_common import oracle_subcalls, parity_violations, to_gpu, tuned_launch
+from gpu_common import check_flagged, oracle_subcalls, to_gpu, tuned_launch
 
 pytestmark = pytest.mark.gpu
 
@@ -45,26 +45,21 @@ def test_divergence_field_matches_oracle(omech9, mech9_path, alpha, launch):
     c, cst, ccn = oracle_subcalls(omech9, sub, wl.DIVERGE_DT, wl.DIVERGE_CALLS)
     gsub = np.ascontiguousarray(out[:, idx])
     assert np.array_equal(gst[idx], cst)
-    bad = parity_violations(gsub, c, 9)
-    if bad.any():
-        fi = np.where(bad)[0]
-        scale = 1e-8 * np.abs(c[:10, fi]) + np.r_[0.0, [1e-10] * 9][:, None]
-        scale[0] = 1e-8 * np.abs(c[0, fi])
-        units = (np.abs(gsub[:10, fi] - c[:10, fi]) / scale).max()
-        assert units < 500, f"flagged cells differ by {units:.1f} tolerance units"
+    budget = "diverge_a1" if alpha == 1.0 else "diverge_a01"
+
+    def rerun(fi):
         tight = np.ascontiguousarray(sub[:, fi])
         gt = to_gpu(tight)
         cg.chem_integrate_batched(m, [dict(state=gt, dt=wl.DIVERGE_DT, n_sub=wl.DIVERGE_CALLS)],
                                   cg.make_opts(rtol=1e-11, atol=1e-14, max_steps=2000000))
         c2, _, _ = oracle_subcalls(omech9, tight, wl.DIVERGE_DT, wl.DIVERGE_CALLS, rtol=1e-11,
                                    atol=1e-14, max_steps=2000000)
-        assert not parity_violations(gt.cpu().numpy(), c2, 9).any()
+        return gt.cpu().numpy(), c2
+    # On the alpha = 0.1 field many cells ignite and then step at the
+    # explicit stability limit, where steps sit on the accept/reject
+    # boundary; the allowance is the oracle's own spread under last-bit
+    # perturbations on 1024 rows of this field (tests/parity_budget.py)
+    bad = check_flagged(gsub, c, 9, budget, rerun, f"divergence alpha {alpha} ({launch} launch)")
     steps = cn.cpu().numpy().reshape(2, n).sum(axis=0)
     print(f"[diverge] alpha {alpha}: {n} cells, RK steps per cell mean {steps.mean():.0f} "
           f"max {steps.max()}, {int(bad.sum())} of {len(idx)} sampled cells flagged", flush=True)
-    # On the alpha = 0.1 field many cells ignite and then step at the
-    # explicit stability limit, where every step sits on the accept/reject
-    # boundary: the oracle against a copy of itself with one ulp changed in
-    # k_f flags 39 of these 256 cells (0 at alpha = 1).  Each flagged cell
-    # must still pass the tight re-run above.
-    assert bad.mean() <= (0.02 if alpha == 1.0 else 0.25)

@@ -35,7 +35,7 @@ def test_rkf45_uniform_cells_all(gm9, omech9, mech9_path, chunk):
 
 def test_rkf45_hot_front_cells(gm9, omech9, mech9_path):
     s0 = _hot_cells(mech9_path, 3000, seed=41)
-    assert_parity(gm9, omech9, s0, wl.DT_FLOW, label="rkf45 hot front", max_flag_frac=0.05,
+    assert_parity(gm9, omech9, s0, wl.DT_FLOW, label="rkf45 hot front", budget="front_hot_rkf45",
                   scheme="rkf45")
 
 
@@ -53,7 +53,7 @@ def test_rkf45_mech32_sampled(omech32, mech32_path):
     m = chemgpu.chem_mech_load(mech32_path)
     s0 = wl.stress_3d(mech32_path, shape=(32, 32, 2), seed=7)
     assert_parity(m, omech32, s0, wl.DT_FLOW, idx=np.arange(0, s0.shape[1], 3),
-                  label="rkf45 stress mech32", scheme="rkf45")
+                  label="rkf45 stress mech32", budget="stress32_rkf45", scheme="rkf45")
 
 
 def test_rkf45_chunk_and_block_invariance(gm9, mech9_path):
@@ -77,4 +77,4 @@ def test_rkf45_front_field_in_its_tuned_launch(gm9, omech9, mech9_path):
     idx = np.concatenate([rng.choice(np.where(hot)[0], 4000, replace=False),
                           rng.choice(np.where(~hot)[0], 2000, replace=False)])
     assert_parity(gm9, omech9, s0, wl.DT_FLOW, idx=idx, label="rkf45 front 1024^2, tuned launch",
-                  max_flag_frac=0.05, **launch)
+                  budget="front_hot_rkf45", **launch)

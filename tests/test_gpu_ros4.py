@@ -56,7 +56,7 @@ def test_ros4_uniform_cells_all(gm9, omech9, mech9_path, chunk):
 
 def test_ros4_hot_front_cells(gm9, omech9, mech9_path):
     s0 = _hot_cells(mech9_path, 3000, seed=52)
-    assert_parity(gm9, omech9, s0, wl.DT_FLOW, label="ros4 hot front", max_flag_frac=0.05,
+    assert_parity(gm9, omech9, s0, wl.DT_FLOW, label="ros4 hot front", budget="front_hot_ros4",
                   scheme="ros4", block_size=256)
 
 
@@ -65,7 +65,7 @@ def test_ros4_long_stiff_interval(gm9, omech9, mech9_path):
     hot cells reach equilibrium and the explicit scheme is stability-bound:
     parity with the oracle, and fewer steps than the explicit scheme."""
     s0 = _hot_cells(mech9_path, 256, seed=53)
-    assert_parity(gm9, omech9, s0, 1e-5, label="ros4 dt 1e-5", max_flag_frac=0.05,
+    assert_parity(gm9, omech9, s0, 1e-5, label="ros4 dt 1e-5", budget="front_hot_ros4_dt1e-5",
                   scheme="ros4")
     _, _, c_imp = run_gpu(gm9, s0, 1e-5, scheme="ros4")
     _, _, c_exp = run_gpu(gm9, s0, 1e-5, scheme="lsrk", tail_steps=-1)
@@ -139,4 +139,4 @@ def test_ros4_front_field_in_its_tuned_launch(gm9, omech9, mech9_path):
     idx = np.concatenate([rng.choice(np.where(hot)[0], 4000, replace=False),
                           rng.choice(np.where(~hot)[0], 2000, replace=False)])
     assert_parity(gm9, omech9, s0, wl.DT_FLOW, idx=idx, label="ros4 front 1024^2, tuned launch",
-                  max_flag_frac=0.05, **launch)
+                  budget="front_hot_ros4", **launch)
