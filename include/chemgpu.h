@@ -19,6 +19,16 @@
  * below; chem_last_error() gives a message for the calling thread's last
  * failure.  Per-cell outcomes never fail a call: they go to the status array.
  * Handles are not thread-safe; calls on one handle must not overlap.
+ *
+ * Device memory: the integration calls (chem_integrate, chem_integrate_batched,
+ * chem_react_conserved, surrogate_infer) allocate
+ * nothing and never synchronise the device (chem_integrate_batched's host
+ * wait on its staging ring is described there).  Their workspace is
+ * allocated up front by chem_workspace_reserve (and surrogate_reserve); a
+ * call on more cells than the reservation holds returns CHEM_ECAPACITY and
+ * enqueues nothing.  Only the set-up calls allocate: chem_workspace_reserve,
+ * surrogate_create/reserve/train/grad/forward, chem_autotune and
+ * chem_graph_capture_batched.
  */
 #ifndef CHEMGPU_H
 #define CHEMGPU_H
@@ -36,7 +46,7 @@ extern "C" {
 #define CHEM_EHIP (-3)         /* a HIP runtime call failed (message has the HIP error) */
 #define CHEM_EPARSE (-4)       /* mechanism file unreadable or malformed (message has the line) */
 #define CHEM_EUNSUPPORTED (-5) /* no kernel was built for this mechanism's content hash */
-#define CHEM_ECAPACITY (-6)    /* reserved: no call returns it (calls past a reservation grow it) */
+#define CHEM_ECAPACITY (-6)    /* more cells (or boxes) than the reserved workspace holds */
 
 /* Per-cell status codes written to the status array. */
 #define CHEM_CELL_OK 0          /* reached dt */
@@ -101,7 +111,10 @@ typedef struct {
 
 /* Load a mechanism from a .mech text file and bind the kernel that was
  * generated for it at build time, keyed by the FNV-1a 64 hash of the file's
- * bytes.  *out receives a handle to free with chem_mech_free. */
+ * bytes.  *out receives a handle to free with chem_mech_free.  The handle
+ * belongs to the device current at this call (every later call on it must
+ * run with that device current).  Allocates no device memory (see
+ * chem_workspace_reserve). */
 int chem_mech_load(const char *path, chem_mech *out);
 
 /* Species count N, reaction count and content hash of a loaded mechanism. */
@@ -110,22 +123,29 @@ int chem_mech_query(chem_mech m, int32_t *n_species, int32_t *n_reactions, uint6
 /* Release a mechanism and its workspace (destroy its graphs first). */
 void chem_mech_free(chem_mech m);
 
-/* Reserve the device workspace (work-queue counter, tail records, pool
- * order) for up to max_cells cells.  After it, chem_integrate calls on up
- * to max_cells cells allocate no device memory, and neither do
- * chem_integrate_batched calls once an earlier batched call with at least
- * as many boxes has sized the box table (one entry per box).  Without a
- * reservation, or past it, a call that needs more grows the workspace.
- * chem_react_conserved's primitive work state is not allocated here; its
- * first call allocates it for max(n_cells, max_cells) cells.  CHEM_EINVAL
- * for a null handle or max_cells < 0. */
+/* Allocate the mechanism handle's whole device workspace for calls on up to
+ * max_cells cells (all boxes of a batched call together): the work-pool
+ * counter, a ring of 4 box tables of 4096 entries (device memory plus a
+ * pinned host staging copy), the tail records through which the per-lane
+ * kernel hands long-running cells to the cooperative kernel (36 B per cell),
+ * the pool order (8 B per cell) and chem_react_conserved's primitive work
+ * state ((N+3) doubles + 1 byte per cell): 141 B per cell for 9 species.
+ * This is the only call that allocates for chem_integrate,
+ * chem_integrate_batched and chem_react_conserved; past the reservation they
+ * return CHEM_ECAPACITY.  A reservation never shrinks; growing one first
+ * waits for the whole device (hipDeviceSynchronize), since queued calls may
+ * still use the old buffers.  max_cells = 0 allocates only the fixed part.
+ * CHEM_EINVAL for a null handle or max_cells < 0; CHEM_EHIP if an allocation
+ * fails (the per-cell part is then released and the reservation is 0). */
 int chem_workspace_reserve(chem_mech m, int64_t max_cells);
 
 /*
  * Per-kernel timing (for measurement, not needed to integrate).  With on != 0
  * every later chem_integrate / chem_integrate_batched / chem_react_conserved
  * call on m records HIP events on its stream around each launch of the flow
- * step (creating the events on first use; captured graphs are not timed);
+ * step, and so does surrogate_infer with fallback around the FP64 run of the
+ * cells outside the training hull, on its side stream (creating the events
+ * on first use; captured graphs are not timed);
  * on == 0 stops it.  chem_kernel_times then waits for the last such call and
  * writes n >= 4 durations in ms: [0] the persistent per-lane kernel, [1] the
  * tail-list sort, [2] the cooperative kernel, [3] the per-lane resumption of
@@ -140,7 +160,9 @@ int chem_kernel_times(chem_mech m, float *ms, int32_t n);
  *   status: NULL or int32[n_cells] device array of CHEM_CELL_* codes.
  *   counts: NULL or int32[2 * n_cells] device array; counts[i] = accepted
  *           steps, counts[n_cells + i] = rejected steps of cell i.
- * Enqueued on `stream`; no host synchronisation.
+ * Enqueued on `stream`; no host synchronisation, no allocation.
+ * CHEM_ECAPACITY if n_cells exceeds the reservation (chem_workspace_reserve),
+ * except with chunk_steps < 0 (one cell per lane, no workspace).
  */
 int chem_integrate(chem_mech m, double *state, int64_t ld, int64_t n_cells, double dt,
                    const chem_opts *opts, void *stream, int32_t *status, int32_t *counts);
@@ -159,10 +181,10 @@ int chem_integrate(chem_mech m, double *state, int64_t ld, int64_t n_cells, doub
  * iterations, else status CHEM_CELL_T_NEWTON and the cell is left unchanged);
  * the chemistry ODE over dt at constant rho and e (as chem_integrate); then
  * rho Y_k, T and h are written back.  rho, momentum and rho E are not
- * touched (the step conserves them).  Uses a primitive work state of
- * (N+3) doubles per cell owned by the mechanism handle (allocated on the
- * first call that needs more; reserve with chem_workspace_reserve).
- * status / counts as in chem_integrate.  Enqueued on `stream`.
+ * touched (the step conserves them).  Uses the primitive work state of
+ * (N+3) doubles per cell that chem_workspace_reserve allocates;
+ * CHEM_ECAPACITY if n_cells exceeds the reservation.  status / counts as in
+ * chem_integrate.  Enqueued on `stream`; no host synchronisation.
  */
 int chem_react_conserved(chem_mech m, double *cons, int64_t ld, int64_t n_cells, double dt,
                          const chem_opts *opts, void *stream, int32_t *status, int32_t *counts);
@@ -190,8 +212,12 @@ typedef struct {
  * Advance every cell of n_boxes boxes in ONE persistent launch over a shared
  * work pool: deeper-level boxes (more sub-calls) are queued first, still-active
  * cells are compacted within each workgroup between step chunks.  The box
- * table is copied to the device through a pinned staging buffer owned by the
- * mechanism handle; the call returns without waiting for the GPU.
+ * table is copied to the device through one slot of the handle's ring of 4
+ * pinned staging tables; a slot is reused once the batched call that used it
+ * last has finished on the device, so the host waits only when 4 earlier
+ * batched calls on this handle are still queued.  CHEM_ECAPACITY if the
+ * boxes hold more cells than the reservation or more than 4096 of them are
+ * non-empty.
  */
 int chem_integrate_batched(chem_mech m, const chem_box *boxes, int32_t n_boxes,
                            const chem_opts *opts, void *stream);
@@ -242,7 +268,8 @@ void chem_graph_destroy(chem_graph g);
  * is not NULL the result is also looked up in / written to that JSON file,
  * keyed by mechanism hash, size bucket and GPU architecture name; a cache hit
  * skips the sweep.  best (may be NULL) receives the chosen options.
- * Synchronises `stream`.
+ * Allocates the snapshots (and, on a miss, grows the workspace reservation to
+ * the boxes' cells if it is smaller); synchronises `stream`.
  */
 int chem_autotune(chem_mech m, const chem_box *boxes, int32_t n_boxes, const chem_opts *base,
                   int32_t reps, const char *cache_path, void *stream, chem_opts *best);
@@ -316,10 +343,20 @@ int surrogate_grad(chem_surr s, const float *Xn, const float *Yn, int32_t B, flo
                    float *loss_host, void *stream);
 
 /*
+ * Allocate what surrogate_infer with fallback needs for up to max_cells
+ * cells: the fallback and hull lists and flags (9 B per cell), the side
+ * stream's pool counter and tail records (36 B per cell), the side stream
+ * and two events.  Growing it first waits for the whole device.  CHEM_EINVAL
+ * for a null handle or max_cells < 0.
+ */
+int surrogate_reserve(chem_surr s, int64_t max_cells);
+
+/*
  * One flow step of dt for n_cells cells through the surrogate: features in
  * FP64, the MLP on the matrix cores, then the FP64 trust test with
  * trust = {hull_margin, elem_tol, pos_tol, energy_tol}.  Trusted cells get
- * T + dT, Y + dY in place (rho and h untouched).  Untrusted cells keep their
+ * T + dT and max(Y + dY, 0) in place (rho and h untouched; the trust test
+ * allows Y + dY down to -pos_tol, the write clips it to 0).  Untrusted cells keep their
  * state and, if `fallback` is non-zero, are integrated from it by the FP64
  * LSRK path (opts as for chem_integrate) in the same stream, with no host
  * round trip: a device-side list feeds the persistent kernel.  Optional
@@ -327,6 +364,9 @@ int surrogate_grad(chem_surr s, const float *Xn, const float *Yn, int32_t B, flo
  * float[n][N+1] (raw network outputs), status / counts (as chem_integrate,
  * written for fallback cells only).  n_fallback_host (may be NULL) receives
  * the number of untrusted cells and then the call synchronises `stream`.
+ * Allocates nothing: with fallback, n_cells must be within both the
+ * surrogate's reservation (surrogate_reserve) and the mechanism's
+ * (chem_workspace_reserve), else CHEM_ECAPACITY.
  */
 int surrogate_infer(chem_surr s, chem_mech m, double *state, int64_t ld, int64_t n_cells, double dt,
                     const double trust[4], int32_t fallback, const chem_opts *opts, void *stream,
@@ -356,17 +396,15 @@ int chem_eval_exp(const double *x, double *y, int64_t n, void *stream);
  * the library's: y[i] = fn(x[i]) for i < n (device arrays, caller-owned),
  * enqueued on `stream`.  fn is one of
  *   CHEM_MATH_EXP_CW      the per-lane rate exponential (as chem_eval_exp);
- *   CHEM_MATH_EXP_ESTRIN  a short-chain exponential without a table (same
- *                         reduction, Estrin-form polynomial; within 1 ulp);
  *   CHEM_MATH_LOG_ATANH   the logarithm of ln T (reduction to [sqrt(1/2),
  *                         sqrt(2)) and the atanh series; within 1 ulp for
  *                         finite x > 0, NaN otherwise);
  *   CHEM_MATH_EXP_TAB     the cooperative kernel's rate exponential (a table
  *                         of 2^(j/64) in LDS and a degree-6 polynomial;
  *                         about 1 ulp at most on [-745, 709]).
- * CHEM_EINVAL for an unknown fn, n < 0 or a null array with n > 0. */
+ * (1 is not used.)  CHEM_EINVAL for an unknown fn, n < 0 or a null array with
+ * n > 0. */
 #define CHEM_MATH_EXP_CW 0
-#define CHEM_MATH_EXP_ESTRIN 1
 #define CHEM_MATH_LOG_ATANH 2
 #define CHEM_MATH_EXP_TAB 3
 int chem_eval_math(int32_t fn, const double *x, double *y, int64_t n, void *stream);

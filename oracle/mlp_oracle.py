@@ -152,6 +152,17 @@ def energy_cv(omech, T, Y):
 TRUST_HULL, TRUST_ELEM, TRUST_POS, TRUST_ENERGY, TRUST_NONFINITE = 1, 2, 4, 8, 16
 
 
+def trusted_update(state, inc):
+    """New (T, Y) rows of trusted cells: T + dT and Y + dY with what lies
+    below zero written as zero (the positivity criterion already bounds it
+    by pos_tol).  state: [(N+3), n]; inc: [n, N+1] de-standardised increments."""
+    N = inc.shape[1] - 1
+    out = np.array(state[:N + 1], dtype=np.float64)
+    out[0] += inc[:, 0]
+    out[1:] = np.maximum(out[1:] + inc[:, 1:].T, 0.0)
+    return out
+
+
 def trust_codes(omech, state, dt, z_in, out_std, norm, trust):
     """Per-cell bitmask of failed criteria (0 = trusted), all in FP64.
 

@@ -115,9 +115,17 @@ def make_opts(rtol=0.0, atol=0.0, max_steps=0, chunk_steps=0, block_size=0, fixe
 
 
 class Mechanism:
-    """Owns a ``chem_mech`` handle."""
+    """Owns a ``chem_mech`` handle.
 
-    def __init__(self, path: str):
+    The library's integration calls allocate nothing: they run on the
+    workspace that ``chem_workspace_reserve`` allocated and return
+    CHEM_ECAPACITY past it.  With ``auto_reserve`` (the default) the wrappers
+    below grow the reservation before a call on more cells than it holds (a
+    reservation that grows waits for the device first); a caller that wants a
+    fixed footprint reserves once up front, or sets ``auto_reserve = False``
+    and gets the library's error instead."""
+
+    def __init__(self, path: str, reserve: int = 0, auto_reserve: bool = True):
         h = _P()
         _check(_lib.chem_mech_load(path.encode(), C.byref(h)), "chem_mech_load")
         self.handle = h
@@ -125,6 +133,10 @@ class Mechanism:
         _check(_lib.chem_mech_query(h, C.byref(ns), C.byref(nr), C.byref(hsh)), "chem_mech_query")
         self.n_species, self.n_reactions, self.hash = ns.value, nr.value, hsh.value
         self.path = path
+        self.reserved = -1
+        self.auto_reserve = auto_reserve
+        if reserve:
+            chem_workspace_reserve(self, reserve)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -138,12 +150,18 @@ class Mechanism:
             pass
 
 
-def chem_mech_load(path: str) -> Mechanism:
-    return Mechanism(path)
+def chem_mech_load(path: str, reserve: int = 0) -> Mechanism:
+    return Mechanism(path, reserve=reserve)
 
 
 def chem_workspace_reserve(mech: Mechanism, max_cells: int) -> None:
     _check(_lib.chem_workspace_reserve(mech.handle, int(max_cells)), "chem_workspace_reserve")
+    mech.reserved = max(mech.reserved, int(max_cells))
+
+
+def _reserve_for(mech: Mechanism, n: int) -> None:
+    if mech.auto_reserve and n > mech.reserved:
+        chem_workspace_reserve(mech, n)
 
 
 def chem_set_kernel_timing(mech: Mechanism, on: bool = True) -> None:
@@ -168,6 +186,7 @@ def chem_integrate(mech: Mechanism, state, dt: float, opts: chem_opts | None = N
     if counts is not None:
         assert counts.numel() >= 2 * n and counts.element_size() == 4
     o = opts if opts is not None else make_opts()
+    _reserve_for(mech, n)
     _check(_lib.chem_integrate(mech.handle, _ptr(state), ld, n, float(dt), C.byref(o),
                                _stream(stream), _ptr(status), _ptr(counts)), "chem_integrate")
 
@@ -184,13 +203,14 @@ _lib.surrogate_grad.argtypes = [_P, _P, _P, C.c_int32, _P, C.POINTER(C.c_float),
 _lib.surrogate_infer.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_double, C.POINTER(C.c_double),
                                  C.c_int32, C.POINTER(chem_opts), _P, _P, _P, _P, _P,
                                  C.POINTER(C.c_int64)]
+_lib.surrogate_reserve.argtypes = [_P, C.c_int64]
 _lib.surrogate_save.argtypes = [_P, C.c_char_p]
 _lib.surrogate_load.argtypes = [_P, C.c_char_p, C.POINTER(_P)]
 _lib.surrogate_free.argtypes = [_P]
 _lib.surrogate_free.restype = None
 for _n in ("surrogate_create", "surrogate_query", "surrogate_get_params", "surrogate_set_params",
            "surrogate_make_pairs", "surrogate_train", "surrogate_forward", "surrogate_grad",
-           "surrogate_infer", "surrogate_save", "surrogate_load"):
+           "surrogate_infer", "surrogate_save", "surrogate_load", "surrogate_reserve"):
     getattr(_lib, _n).restype = C.c_int
 
 TRUST_HULL, TRUST_ELEM, TRUST_POS, TRUST_ENERGY, TRUST_NONFINITE = 1, 2, 4, 8, 16
@@ -207,6 +227,7 @@ class Surrogate:
                    "surrogate_create")
             handle = h
         self.handle = handle
+        self.reserved = -1
         ni, no, P = C.c_int32(), C.c_int32(), C.c_int64()
         _check(_lib.surrogate_query(self.handle, C.byref(ni), C.byref(no), C.byref(P)),
                "surrogate_query")
@@ -290,11 +311,20 @@ def surrogate_grad(s: Surrogate, Xn, Yn, grad=None, stream=None):
     return grad, loss.value
 
 
+def surrogate_reserve(s: Surrogate, max_cells: int) -> None:
+    _check(_lib.surrogate_reserve(s.handle, int(max_cells)), "surrogate_reserve")
+    s.reserved = max(s.reserved, int(max_cells))
+
+
 def surrogate_infer(s: Surrogate, mech: Mechanism, state, dt, trust, fallback=True, opts=None,
                     stream=None, trust_code=None, out_std=None, status=None, counts=None,
                     n_cells=None, want_count=False):
     ld = state.shape[1]
     n = ld if n_cells is None else int(n_cells)
+    if fallback:
+        _reserve_for(mech, n)
+        if mech.auto_reserve and n > s.reserved:
+            surrogate_reserve(s, n)
     tr = (C.c_double * 4)(*[float(x) for x in trust])
     o = opts if opts is not None else make_opts()
     cnt = C.c_int64(-1)
@@ -333,6 +363,7 @@ def chem_integrate_batched(mech: Mechanism, boxes, opts: chem_opts | None = None
                            stream=None) -> None:
     arr = make_boxes(boxes)
     o = opts if opts is not None else make_opts()
+    _reserve_for(mech, sum(int(arr[i].n_cells) for i in range(len(boxes))))
     _check(_lib.chem_integrate_batched(mech.handle, arr, len(boxes), C.byref(o),
                                        _stream(stream)), "chem_integrate_batched")
 
@@ -374,6 +405,7 @@ def chem_autotune(mech: Mechanism, boxes, base: chem_opts | None = None, reps: i
     arr = make_boxes(boxes)
     o = base if base is not None else make_opts()
     best = chem_opts()
+    _reserve_for(mech, sum(int(arr[i].n_cells) for i in range(len(boxes))))
     _check(_lib.chem_autotune(mech.handle, arr, len(boxes), C.byref(o), int(reps),
                               cache_path.encode() if cache_path else None, _stream(stream),
                               C.byref(best)), "chem_autotune")
@@ -396,6 +428,7 @@ def chem_react_conserved(mech: Mechanism, cons, dt: float, opts: chem_opts | Non
     if counts is not None:
         assert counts.numel() >= 2 * n and counts.element_size() == 4
     o = opts if opts is not None else make_opts()
+    _reserve_for(mech, n)
     _check(_lib.chem_react_conserved(mech.handle, _ptr(cons), ld, n, float(dt), C.byref(o),
                                      _stream(stream), _ptr(status), _ptr(counts)),
            "chem_react_conserved")
@@ -415,12 +448,12 @@ def chem_eval_exp(x, stream=None):
 
 _lib.chem_eval_math.restype = C.c_int
 _lib.chem_eval_math.argtypes = [C.c_int32, _P, _P, C.c_int64, _P]
-MATH_FNS = {"exp_cw": 0, "exp_estrin": 1, "log_atanh": 2, "exp_tab": 3}
+MATH_FNS = {"exp_cw": 0, "log_atanh": 2, "exp_tab": 3}
 
 
 def chem_eval_math(fn, x, stream=None):
     """fn(x) on the device with one of the integrators' own elementary
-    functions ("exp_cw", "exp_estrin", "log_atanh")."""
+    functions ("exp_cw", "log_atanh", "exp_tab")."""
     import torch
     y = torch.empty_like(x)
     _check(_lib.chem_eval_math(MATH_FNS[fn], x.data_ptr(), y.data_ptr(), x.numel(),
@@ -437,4 +470,4 @@ def exported_symbols():
             "surrogate_set_params", "surrogate_make_pairs", "surrogate_train", "surrogate_forward",
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
             "surrogate_free", "chem_eval_exp", "chem_eval_math", "chem_react_conserved",
-            "chem_set_kernel_timing", "chem_kernel_times"]
+            "chem_set_kernel_timing", "chem_kernel_times", "surrogate_reserve"]

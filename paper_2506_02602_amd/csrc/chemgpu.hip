@@ -82,8 +82,7 @@ __global__ void eval_math_kernel(int fn, const double* x, double* y, int64_t n) 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double v = x[i];
-  y[i] = fn == CHEM_MATH_EXP_ESTRIN ? exp_estrin(v)
-         : fn == CHEM_MATH_LOG_ATANH ? log_atanh(v)
+  y[i] = fn == CHEM_MATH_LOG_ATANH ? log_atanh(v)
          : fn == CHEM_MATH_EXP_TAB   ? exp_tab(v, E)
                                      : exp_cw(v);
 }
@@ -709,7 +708,9 @@ struct TailStore {
     b.key = q + 5 * cap; b.order = q + 6 * cap;
     return b;
   }
-  static size_t bytes(int64_t cap) { return 16 + (size_t)cap * (sizeof(double) + 7 * sizeof(int32_t)); }
+  static constexpr size_t bytes(int64_t cap) {
+    return 16 + (size_t)cap * (sizeof(double) + 7 * sizeof(int32_t));
+  }
 };
 
 // Device storage of the pool order (see OrderBuf): rank and order arrays of
@@ -725,8 +726,15 @@ struct OrderStore {
     b.order = b.rank + cap;
     return b;
   }
-  static size_t bytes(int64_t cap) { return 16 + (size_t)cap * 2 * sizeof(int32_t); }
+  static constexpr size_t bytes(int64_t cap) { return 16 + (size_t)cap * 2 * sizeof(int32_t); }
 };
+
+// Batched calls stage their box table through a ring of slots (pinned host
+// copy + device copy, kMaxBoxes entries each); a slot is reused once the call
+// that last used it has finished on the device, so a host wait happens only
+// when kBoxRing batched calls are still queued.
+constexpr int kMaxBoxes = 4096;
+constexpr int kBoxRing = 4;
 
 struct chem_mech_s {
   const MechEntry* entry;
@@ -734,17 +742,18 @@ struct chem_mech_s {
   OrderStore order;
   struct Tuned { int block, chunk, tail, cap, order; };
   std::map<int, Tuned> tuned;  // (size bucket, scheme) -> tuned launch
+  // workspace, all of it allocated by chem_workspace_reserve
   unsigned long long* d_next = nullptr;
-  BoxDesc* d_boxes = nullptr;
-  BoxDesc* h_boxes = nullptr;      // pinned staging for the box table
-  hipEvent_t boxes_copied = nullptr;
-  int32_t box_cap = 0;
+  BoxDesc* d_boxes = nullptr;      // kBoxRing slots of kMaxBoxes entries
+  BoxDesc* h_boxes = nullptr;      // pinned staging, same shape
+  hipEvent_t box_done[kBoxRing] = {};
+  int box_slot = 0;
   int64_t reserved = 0;
-  int device = 0;
-  int n_cu = 0;
+  bool fixed_ready = false;        // pool counter, box ring and events allocated
   double* d_prim = nullptr;        // primitive work state of chem_react_conserved
   int8_t* d_flag = nullptr;
-  int64_t prim_cap = 0;
+  int device = 0;
+  int n_cu = 0;
   // optional per-kernel timing of plain (not captured) calls: events around
   // the persistent launch, the tail sort, the cooperative launch and the
   // resumption launch of the last call
@@ -764,20 +773,7 @@ struct chem_graph_s {
 
 namespace {
 
-int ensure_pool(chem_mech m) {
-  if (m->d_next) return CHEM_OK;
-  hipError_t e = hipMalloc(&m->d_next, sizeof(unsigned long long));
-  if (e != hipSuccess) { m->d_next = nullptr; return hip_fail(e, "hipMalloc(pool counter)"); }
-  return CHEM_OK;
-}
-
-int ensure_tail(TailStore& ts, int64_t cap) {
-  if (cap <= ts.cap) return CHEM_OK;
-  if (ts.mem) {
-    hipError_t e = hipDeviceSynchronize();  // a queued call may still use the old records
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(tail records)");
-    (void)hipFree(ts.mem);
-  }
+int alloc_tail(TailStore& ts, int64_t cap) {
   ts.mem = nullptr;
   ts.cap = 0;
   hipError_t e = hipMalloc(&ts.mem, TailStore::bytes(cap));
@@ -786,13 +782,7 @@ int ensure_tail(TailStore& ts, int64_t cap) {
   return CHEM_OK;
 }
 
-int ensure_order(OrderStore& os, int64_t cap) {
-  if (cap <= os.cap) return CHEM_OK;
-  if (os.mem) {
-    hipError_t e = hipDeviceSynchronize();  // a queued call may still use the old arrays
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(pool order)");
-    (void)hipFree(os.mem);
-  }
+int alloc_order(OrderStore& os, int64_t cap) {
   os.mem = nullptr;
   os.cap = 0;
   hipError_t e = hipMalloc(&os.mem, OrderStore::bytes(cap));
@@ -801,26 +791,47 @@ int ensure_order(OrderStore& os, int64_t cap) {
   return CHEM_OK;
 }
 
-int ensure_box_table(chem_mech m, int32_t n) {
-  if (n <= m->box_cap) return CHEM_OK;
-  if (m->boxes_copied) {
-    // the previous table may still be read by a queued copy
-    hipError_t e = hipEventSynchronize(m->boxes_copied);
-    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(box table)");
+// The per-cell part of a mechanism's workspace (tail records, pool order,
+// primitive work state); teardown and reservation only.
+void free_cell_workspace(chem_mech m) {
+  if (m->tail.mem) (void)hipFree(m->tail.mem);
+  if (m->order.mem) (void)hipFree(m->order.mem);
+  if (m->d_prim) (void)hipFree(m->d_prim);
+  if (m->d_flag) (void)hipFree(m->d_flag);
+  m->tail = TailStore{};
+  m->order = OrderStore{};
+  m->d_prim = nullptr;
+  m->d_flag = nullptr;
+  m->reserved = 0;
+}
+
+// Pool counter, box-table ring and its events: sized independently of the
+// cell count.
+int alloc_fixed_workspace(chem_mech m) {
+  if (m->fixed_ready) return CHEM_OK;
+  hipError_t e = hipMalloc(&m->d_next, sizeof(unsigned long long));
+  if (e != hipSuccess) { m->d_next = nullptr; return hip_fail(e, "hipMalloc(pool counter)"); }
+  e = hipMalloc(&m->d_boxes, sizeof(BoxDesc) * kMaxBoxes * kBoxRing);
+  if (e != hipSuccess) { m->d_boxes = nullptr; return hip_fail(e, "hipMalloc(box table)"); }
+  e = hipHostMalloc(&m->h_boxes, sizeof(BoxDesc) * kMaxBoxes * kBoxRing, hipHostMallocDefault);
+  if (e != hipSuccess) { m->h_boxes = nullptr; return hip_fail(e, "hipHostMalloc(box table)"); }
+  for (hipEvent_t& ev : m->box_done) {
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) { ev = nullptr; return hip_fail(e, "hipEventCreate(box table)"); }
   }
-  if (m->d_boxes) (void)hipFree(m->d_boxes);
-  if (m->h_boxes) (void)hipHostFree(m->h_boxes);
-  m->d_boxes = nullptr; m->h_boxes = nullptr; m->box_cap = 0;
-  hipError_t e = hipMalloc(&m->d_boxes, sizeof(BoxDesc) * n);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(box table)");
-  e = hipHostMalloc(&m->h_boxes, sizeof(BoxDesc) * n, hipHostMallocDefault);
-  if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(box table)");
-  if (!m->boxes_copied) {
-    e = hipEventCreateWithFlags(&m->boxes_copied, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-  }
-  m->box_cap = n;
+  m->fixed_ready = true;
   return CHEM_OK;
+}
+
+// Calls that use the mechanism's own workspace need a reservation covering
+// their cells (and, for batched calls, at most kMaxBoxes boxes).
+int check_capacity(chem_mech m, int64_t cells, const char* where) {
+  if (m->fixed_ready && cells <= m->reserved) return CHEM_OK;
+  char msg[200];
+  snprintf(msg, sizeof msg, "%s: %lld cells but the workspace is reserved for %lld "
+           "(call chem_workspace_reserve first)", where, (long long)cells,
+           (long long)(m->fixed_ready ? m->reserved : 0));
+  return fail(CHEM_ECAPACITY, msg);
 }
 
 Control make_control(const chem_opts* o) {
@@ -971,7 +982,7 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
 // The integrator over a work pool with a given pool counter and tail store
 // (calls that may run concurrently on one mechanism each bring their own).
 int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
-                  unsigned long long* next, TailStore& tail, OrderStore* order) {
+                  unsigned long long* next, TailStore& tail, OrderStore* order, bool timed) {
   int block, chunk;
   pick_launch(m, a.total, o, &block, &chunk);
   if (m->entry->lds_per_lane() * block > 65536)
@@ -983,8 +994,8 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
   a.chunk = chunk > 0 ? chunk : kDefaultChunk;
   a.tail_steps = pick_tail(m, a.total, o);
   if (a.tail_steps > 0) {
-    int rc = ensure_tail(tail, std::max<int64_t>(a.total, m->reserved));
-    if (rc) return rc;
+    if (!tail.mem || a.total > tail.cap)
+      return fail(CHEM_ECAPACITY, "more cells than the reserved tail records");
     a.tail = tail.view();
     a.tail.cap = pick_cap(m, a.total, o);
   }
@@ -992,13 +1003,13 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
   const int omode = order && !a.total_dev ? pick_order(m, a.total, o) : 0;
   const bool ordered = omode != 0;
   if (ordered) {
-    int rc = ensure_order(*order, std::max<int64_t>(a.total, m->reserved));
-    if (rc) return rc;
+    if (!order->mem || a.total > order->cap)
+      return fail(CHEM_ECAPACITY, "more cells than the reserved pool order");
     ob = order->view();
     ob.mode = omode;
     ob.t_split = m->entry->t_split;
   }
-  const bool timed = m->timing && next == m->d_next;  // the mechanism's own pool only
+  timed = timed && m->timing;
   hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s,
                              ordered ? &ob : nullptr, timed);
   if (e != hipSuccess) return hip_fail(e, "launch integrator kernels");
@@ -1007,9 +1018,9 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
 }
 
 int run_pool(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s) {
-  int rc = ensure_pool(m);
+  int rc = check_capacity(m, a.total, "integrator");
   if (rc) return rc;
-  return run_pool_with(m, a, o, s, m->d_next, m->tail, &m->order);
+  return run_pool_with(m, a, o, s, m->d_next, m->tail, &m->order, true);
 }
 
 int grid_for(chem_mech m, int block, int64_t total, int scheme) {
@@ -1123,7 +1134,7 @@ const char* chem_strerror(int code) {
 const char* chem_last_error(void) { return g_err.c_str(); }
 
 int chem_eval_math(int32_t fn, const double* x, double* y, int64_t n, void* stream) {
-  if (fn != CHEM_MATH_EXP_CW && fn != CHEM_MATH_EXP_ESTRIN && fn != CHEM_MATH_LOG_ATANH &&
+  if (fn != CHEM_MATH_EXP_CW && fn != CHEM_MATH_LOG_ATANH &&
       fn != CHEM_MATH_EXP_TAB)
     return fail(CHEM_EINVAL, "chem_eval_math: unknown function");
   if (n < 0 || (n > 0 && (!x || !y))) return fail(CHEM_EINVAL, "chem_eval_math: bad argument");
@@ -1186,15 +1197,13 @@ void chem_mech_free(chem_mech m) {
   // teardown: errors have nowhere to go
   for (hipEvent_t& ev : m->tev)
     if (ev) (void)hipEventDestroy(ev);
-  if (m->boxes_copied) {
-    (void)hipEventSynchronize(m->boxes_copied);
-    (void)hipEventDestroy(m->boxes_copied);
-  }
+  for (hipEvent_t& ev : m->box_done)
+    if (ev) {
+      (void)hipEventSynchronize(ev);
+      (void)hipEventDestroy(ev);
+    }
+  free_cell_workspace(m);
   if (m->d_next) (void)hipFree(m->d_next);
-  if (m->tail.mem) (void)hipFree(m->tail.mem);
-  if (m->order.mem) (void)hipFree(m->order.mem);
-  if (m->d_prim) (void)hipFree(m->d_prim);
-  if (m->d_flag) (void)hipFree(m->d_flag);
   if (m->d_boxes) (void)hipFree(m->d_boxes);
   if (m->h_boxes) (void)hipHostFree(m->h_boxes);
   delete m;
@@ -1202,12 +1211,26 @@ void chem_mech_free(chem_mech m) {
 
 int chem_workspace_reserve(chem_mech m, int64_t max_cells) {
   if (!m || max_cells < 0) return fail(CHEM_EINVAL, "chem_workspace_reserve: bad argument");
-  int rc = ensure_pool(m);
+  int rc = alloc_fixed_workspace(m);
   if (rc) return rc;
-  m->reserved = std::max(m->reserved, max_cells);
-  rc = ensure_tail(m->tail, m->reserved);
-  if (rc) return rc;
-  return ensure_order(m->order, m->reserved);
+  if (max_cells <= m->reserved && m->tail.mem) return CHEM_OK;
+  // growing: calls still queued may use the old buffers
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(workspace)");
+  free_cell_workspace(m);
+  const int64_t cap = std::max<int64_t>(max_cells, 1);
+  if ((rc = alloc_tail(m->tail, cap)) != CHEM_OK || (rc = alloc_order(m->order, cap)) != CHEM_OK) {
+    free_cell_workspace(m);
+    return rc;
+  }
+  e = hipMalloc(&m->d_prim, sizeof(double) * (size_t)cap * (m->entry->ns + 3));
+  if (e == hipSuccess) e = hipMalloc(&m->d_flag, (size_t)cap);
+  if (e != hipSuccess) {
+    free_cell_workspace(m);
+    return hip_fail(e, "hipMalloc(primitive work state)");
+  }
+  m->reserved = max_cells;
+  return CHEM_OK;
 }
 
 int chem_set_kernel_timing(chem_mech m, int32_t on) {
@@ -1280,21 +1303,8 @@ int chem_react_conserved(chem_mech m, double* cons, int64_t ld, int64_t n_cells,
   if (n_cells == 0) return CHEM_OK;
   if (n_cells > 0x7fffffff) return fail(CHEM_EINVAL, "more than 2^31-1 cells in one call");
   hipStream_t s = (hipStream_t)stream;
-  if (n_cells > m->prim_cap) {
-    if (m->d_prim) {
-      hipError_t e = hipDeviceSynchronize();
-      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(primitive work state)");
-      (void)hipFree(m->d_prim);
-      (void)hipFree(m->d_flag);
-    }
-    m->d_prim = nullptr; m->d_flag = nullptr; m->prim_cap = 0;
-    const int64_t cap = std::max<int64_t>(n_cells, m->reserved);
-    hipError_t e = hipMalloc(&m->d_prim, sizeof(double) * (size_t)cap * (m->entry->ns + 3));
-    if (e != hipSuccess) { m->d_prim = nullptr; return hip_fail(e, "hipMalloc(primitive state)"); }
-    e = hipMalloc(&m->d_flag, (size_t)cap);
-    if (e != hipSuccess) { m->d_flag = nullptr; return hip_fail(e, "hipMalloc(Newton flags)"); }
-    m->prim_cap = cap;
-  }
+  rc = check_capacity(m, n_cells, "chem_react_conserved");
+  if (rc) return rc;
   hipError_t e = m->entry->launch_cons_to_prim(cons, ld, n_cells, m->d_prim, m->d_flag, s);
   if (e != hipSuccess) return hip_fail(e, "launch cons_to_prim");
   rc = chem_integrate(m, m->d_prim, n_cells, n_cells, dt, opts, stream, status, counts);
@@ -1315,26 +1325,34 @@ int chem_integrate_batched(chem_mech m, const chem_box* boxes, int32_t n_boxes,
   if (rc) return rc;
   if (total == 0) return CHEM_OK;
   hipStream_t s = (hipStream_t)stream;
-  rc = ensure_box_table(m, (int32_t)table.size());
+  rc = check_capacity(m, total, "chem_integrate_batched");
   if (rc) return rc;
-  // the staging buffer may still feed the previous call's copy
-  hipError_t e = hipEventSynchronize(m->boxes_copied);
+  if (table.size() > (size_t)kMaxBoxes)
+    return fail(CHEM_ECAPACITY, "chem_integrate_batched: more than 4096 non-empty boxes");
+  // a ring slot is free once the call that used it last has finished
+  const int slot = m->box_slot;
+  m->box_slot = (slot + 1) % kBoxRing;
+  hipError_t e = hipEventSynchronize(m->box_done[slot]);
   if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(box table)");
-  memcpy(m->h_boxes, table.data(), sizeof(BoxDesc) * table.size());
-  e = hipMemcpyAsync(m->d_boxes, m->h_boxes, sizeof(BoxDesc) * table.size(),
-                     hipMemcpyHostToDevice, s);
+  BoxDesc* h_tab = m->h_boxes + (size_t)slot * kMaxBoxes;
+  BoxDesc* d_tab = m->d_boxes + (size_t)slot * kMaxBoxes;
+  memcpy(h_tab, table.data(), sizeof(BoxDesc) * table.size());
+  e = hipMemcpyAsync(d_tab, h_tab, sizeof(BoxDesc) * table.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(box table)");
-  e = hipEventRecord(m->boxes_copied, s);
-  if (e != hipSuccess) return hip_fail(e, "hipEventRecord(box table)");
   PoolArgs a{};
   a.one = table[0];
-  a.boxes = m->d_boxes;
+  a.boxes = d_tab;
   a.n_boxes = (int32_t)table.size();
   a.total = total;
   a.c = make_control(opts);
   a.fixed_steps = opts ? opts->fixed_steps : 0;
   a.scheme = opts ? opts->scheme : SCHEME_LSRK;
-  return run_pool(m, a, opts, s);
+  rc = run_pool(m, a, opts, s);
+  // recorded even when the launch failed, so the slot never waits on a stale event
+  e = hipEventRecord(m->box_done[slot], s);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord(box table)");
+  return CHEM_OK;
 }
 
 int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_boxes,
@@ -1367,13 +1385,13 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   if (e != hipSuccess) return bail(e, "hipMalloc(graph pool counter)");
   const int tail_steps = pick_tail(m, total, opts);
   if (tail_steps > 0) {
-    rc = ensure_tail(g->tail, total);
+    rc = alloc_tail(g->tail, total);
     if (rc) { chem_graph_destroy(g); return rc; }
   }
   const int omode = pick_order(m, total, opts);
   const bool ordered = omode != 0;
   if (ordered) {
-    rc = ensure_order(g->order, total);
+    rc = alloc_order(g->order, total);
     if (rc) { chem_graph_destroy(g); return rc; }
   }
   e = hipMemcpy(g->d_boxes, table.data(), sizeof(BoxDesc) * table.size(), hipMemcpyHostToDevice);
@@ -1470,6 +1488,11 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
         }
         return CHEM_OK;
       }
+  }
+  // the trials are batched calls on the mechanism's own workspace
+  if (!m->fixed_ready || total > m->reserved) {
+    rc = chem_workspace_reserve(m, std::max<int64_t>(total, m->reserved));
+    if (rc) return rc;
   }
   // snapshot every box so trials can restore the caller's data
   std::vector<double*> snap(table.size(), nullptr);

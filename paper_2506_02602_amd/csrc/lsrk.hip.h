@@ -125,36 +125,6 @@ __device__ __forceinline__ double exp_cw(double x) {
   return ldexp(p, (int)n);
 }
 
-// e^x with a short dependency chain, for latency-bound code: the same
-// Cody-Waite reduction as exp_cw, then e^r = (1 + r) + r^2 Q(r) with Q the
-// degree-11 remainder of the Taylor series, evaluated by Estrin's scheme
-// (powers r^2, r^4, r^8 and paired coefficients: four FMA levels instead of
-// eleven), 1 + r split exactly into hi + lo so that the last addition is the
-// only rounding of the leading terms.  Within 1 ulp of a correctly rounded
-// exponential; same range behaviour as exp_cw.  Three more instructions than
-// exp_cw.
-__device__ __forceinline__ double exp_estrin(double x) {
-  constexpr double LOG2E = 1.4426950408889634;
-  constexpr double LN2_HI = 0.6931471805599453;
-  constexpr double LN2_LO = 2.3190468138462996e-17;
-  double n = rint(x * LOG2E);
-  n = fmax(fmin(n, 2100.0), -2100.0);
-  double r = fma(-n, LN2_HI, x);
-  r = fma(-n, LN2_LO, r);
-  const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
-  const double a0 = fma(r, 1.0 / 6.0, 0.5);
-  const double a1 = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-  const double a2 = fma(r, 1.0 / 5040.0, 1.0 / 720.0);
-  const double a3 = fma(r, 1.0 / 362880.0, 1.0 / 40320.0);
-  const double a4 = fma(r, 1.0 / 39916800.0, 1.0 / 3628800.0);
-  const double a5 = fma(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);
-  const double b0 = fma(a1, r2, a0), b1 = fma(a3, r2, a2), b2 = fma(a5, r2, a4);
-  const double q = fma(b2, r8, fma(b1, r4, b0));
-  const double hi = 1.0 + r;
-  const double lo = r - (hi - 1.0);
-  return ldexp(hi + fma(r2, q, lo), (int)n);
-}
-
 // 2^(j/64), j = 0..63: each the double nearest the exact value (hexadecimal
 // literals, so the table is bit-exact).  The kernels that use exp_tab stage it
 // in LDS.
@@ -186,7 +156,7 @@ static __constant__ double kExp2Frac[64] = {
 // (in LDS).  Error: the table entry's rounding (at most 2^-53 relative) plus
 // the final rounding, about 1 ulp at most on [-745, 709]; inf above, 0 or a
 // subnormal below, NaN through, like exp_cw.  18 VALU instructions and one
-// LDS read, against exp_estrin's 38.
+// LDS read.
 __device__ __forceinline__ double exp_tab(double x, const double* E) {
   constexpr double K = 92.33248261689366;            // 64 / ln 2
   constexpr double L_HI = 0.010830424696249145;        // ln2 / 64, nearest double

@@ -22,13 +22,16 @@ struct chem_surr_s {
   unsigned short *dZb1 = nullptr, *dZb2 = nullptr, *dZb3 = nullptr;
   float *Z1 = nullptr, *Z2 = nullptr, *Z3 = nullptr, *out = nullptr, *Yb = nullptr, *dZ = nullptr;
   float* part = nullptr;
+  float* fwd_tmp = nullptr;               // surrogate_forward's standardised chunk
   double* sse = nullptr;
   // inference fallback lists: cells failing the trust test after the network
   // (fb_list) and cells outside the training hull found before it (hull_list,
   // integrated on a side stream while the network runs), with the hull flags
+  // (all of them allocated by surrogate_reserve; surrogate_infer allocates nothing)
   int32_t* fb_list = nullptr;
   unsigned* fb_count = nullptr;
-  long fb_cap = 0;
+  int64_t reserved = 0;
+  bool side_ready = false;
   int32_t* hull_list = nullptr;
   unsigned* hull_count = nullptr;
   int8_t* hull_flag = nullptr;
@@ -60,10 +63,11 @@ hipError_t dalloc(T** p, long count) {
 void surr_free_batch(chem_surr s) {
   for (void* p : {(void*)s->X0, (void*)s->H1, (void*)s->H2, (void*)s->H3, (void*)s->dout,
                   (void*)s->dZb1, (void*)s->dZb2, (void*)s->dZb3, (void*)s->Z1, (void*)s->Z2,
-                  (void*)s->Z3, (void*)s->out, (void*)s->Yb, (void*)s->dZ, (void*)s->part})
+                  (void*)s->Z3, (void*)s->out, (void*)s->Yb, (void*)s->dZ, (void*)s->part,
+                  (void*)s->fwd_tmp})
     if (p) (void)hipFree(p);
   s->X0 = s->H1 = s->H2 = s->H3 = s->dout = s->dZb1 = s->dZb2 = s->dZb3 = nullptr;
-  s->Z1 = s->Z2 = s->Z3 = s->out = s->Yb = s->dZ = s->part = nullptr;
+  s->Z1 = s->Z2 = s->Z3 = s->out = s->Yb = s->dZ = s->part = s->fwd_tmp = nullptr;
   s->bcap = 0;
 }
 
@@ -81,6 +85,7 @@ int surr_ensure_batch(chem_surr s, int B) {
   A(dalloc(&s->out, (long)B * s->no)); A(dalloc(&s->Yb, (long)B * s->no));
   A(dalloc(&s->dZ, (long)B * H));
   A(dalloc(&s->part, (long)kSplits * H * std::max<long>(H, std::max(s->ni, s->no))));
+  A(dalloc(&s->fwd_tmp, (long)B * s->ni));
   if (e != hipSuccess) { surr_free_batch(s); return hip_fail(e, "hipMalloc(surrogate batch)"); }
   s->bcap = B;
   return CHEM_OK;
@@ -331,9 +336,8 @@ int surrogate_forward(chem_surr s, const float* X, int64_t n, float* out, void* 
   int rc = surr_ensure_batch(s, B);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  float* tmp = nullptr;
-  hipError_t e = dalloc(&tmp, (long)B * s->ni);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(forward tmp)");
+  float* tmp = s->fwd_tmp;
+  hipError_t e = hipSuccess;
   for (long c0 = 0; c0 < n && e == hipSuccess; c0 += B) {
     const int b = (int)std::min<long>(B, n - c0);
     e = hipMemcpyAsync(tmp, X + c0 * s->ni, sizeof(float) * b * s->ni, hipMemcpyDeviceToDevice, st);
@@ -346,7 +350,6 @@ int surrogate_forward(chem_surr s, const float* X, int64_t n, float* out, void* 
       e = hipMemcpyAsync(out + c0 * s->no, s->out, sizeof(float) * b * s->no, hipMemcpyDeviceToDevice, st);
   }
   const hipError_t es = hipStreamSynchronize(st);
-  (void)hipFree(tmp);
   if (e == hipSuccess) e = es;
   if (e != hipSuccess) return hip_fail(e, "surrogate_forward");
   return CHEM_OK;
@@ -416,10 +419,13 @@ int surrogate_train(chem_surr s, const float* X, const float* Y, int64_t n, int3
       if (e != hipSuccess) return hip_fail(e, "surrogate_train step");
       s->adam_t += 1;
       const double lr_t = lr * 0.5 * (1.0 + cos(3.14159265358979323846 * (double)t / (double)total));
-      const float c1 = (float)(1.0 - pow(0.9, (double)s->adam_t));
-      const float c2 = (float)(1.0 - pow(0.999, (double)s->adam_t));
+      // the decay rates are the FP32 values the moment updates use; the bias
+      // corrections 1 - beta^t are taken with those same values
+      const float b1 = 0.9f, b2 = 0.999f;
+      const float c1 = (float)(1.0 - pow((double)b1, (double)s->adam_t));
+      const float c2 = (float)(1.0 - pow((double)b2, (double)s->adam_t));
       hipLaunchKernelGGL(surr::adam_update, dim3((unsigned)((s->P + 255) / 256)), dim3(256), 0, st,
-                         s->theta, s->m, s->v, s->grad, s->P, (float)lr_t, 0.9f, 0.999f, c1, c2, 1e-8f,
+                         s->theta, s->m, s->v, s->grad, s->P, (float)lr_t, b1, b2, c1, c2, 1e-8f,
                          s->wbf);
     }
     if (loss_host) {
@@ -433,6 +439,37 @@ int surrogate_train(chem_surr s, const float* X, const float* Y, int64_t n, int3
   rc = surr_pack(s, st);
   if (rc) return rc;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "surrogate_train");
+  return CHEM_OK;
+}
+
+int surrogate_reserve(chem_surr s, int64_t max_cells) {
+  if (!s || max_cells < 0) return fail(CHEM_EINVAL, "surrogate_reserve: bad argument");
+  hipError_t e;
+  if (!s->side_ready) {
+    if ((e = dalloc(&s->hull_count, 1)) != hipSuccess) return hip_fail(e, "hipMalloc(hull count)");
+    if ((e = dalloc(&s->side_next, 1)) != hipSuccess) return hip_fail(e, "hipMalloc(pool counter)");
+    if ((e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+    if ((e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "hipStreamCreate(side)");
+    s->side_ready = true;
+  }
+  if (max_cells <= s->reserved && s->fb_list) return CHEM_OK;
+  // growing: calls still queued may use the old lists
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(surrogate)");
+  for (void* p : {(void*)s->fb_list, (void*)s->hull_list, (void*)s->hull_flag, s->side_tail.mem})
+    if (p) (void)hipFree(p);
+  s->fb_list = nullptr; s->hull_list = nullptr; s->hull_flag = nullptr;
+  s->side_tail = TailStore{};
+  s->reserved = 0;
+  const int64_t cap = std::max<int64_t>(max_cells, 1);
+  if ((e = dalloc(&s->fb_list, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(fallback list)");
+  if ((e = dalloc(&s->hull_list, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(hull list)");
+  if ((e = dalloc(&s->hull_flag, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(hull flags)");
+  int rc = alloc_tail(s->side_tail, cap);
+  if (rc) return rc;
+  s->reserved = max_cells;
   return CHEM_OK;
 }
 
@@ -451,24 +488,19 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
   if (!s->packed) return fail(CHEM_EINVAL, "surrogate_infer: weights not packed");
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
-  if (fallback && n_cells > s->fb_cap) {
-    for (void* p : {(void*)s->fb_list, (void*)s->hull_list, (void*)s->hull_flag})
-      if (p) (void)hipFree(p);
-    s->fb_list = nullptr; s->hull_list = nullptr; s->hull_flag = nullptr;
-    s->fb_cap = 0;
-    if ((e = dalloc(&s->fb_list, n_cells)) != hipSuccess) return hip_fail(e, "hipMalloc(fallback list)");
-    if ((e = dalloc(&s->hull_list, n_cells)) != hipSuccess) return hip_fail(e, "hipMalloc(hull list)");
-    if ((e = dalloc(&s->hull_flag, n_cells)) != hipSuccess) return hip_fail(e, "hipMalloc(hull flags)");
-    s->fb_cap = n_cells;
-  }
-  if (fallback && !s->side) {
-    if ((e = dalloc(&s->hull_count, 1)) != hipSuccess) return hip_fail(e, "hipMalloc(hull count)");
-    if ((e = dalloc(&s->side_next, 1)) != hipSuccess) return hip_fail(e, "hipMalloc(pool counter)");
-    if ((e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming)) != hipSuccess)
-      return hip_fail(e, "hipEventCreate");
-    if ((e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking)) != hipSuccess)
-      return hip_fail(e, "hipStreamCreate(side)");
+  if (fallback) {
+    // the hull cells run on the side stream with the surrogate's lists and
+    // tail records, the other failures on `stream` with the mechanism's
+    // workspace: both reservations must cover n_cells
+    if (!s->side_ready || n_cells > s->reserved) {
+      char msg[200];
+      snprintf(msg, sizeof msg, "surrogate_infer: %lld cells but the surrogate is reserved for "
+               "%lld (call surrogate_reserve first)", (long long)n_cells,
+               (long long)(s->side_ready ? s->reserved : 0));
+      return fail(CHEM_ECAPACITY, msg);
+    }
+    rc = check_capacity(m, n_cells, "surrogate_infer fallback");
+    if (rc) return rc;
   }
   hipLaunchKernelGGL(surr::zero_u32, dim3(1), dim3(1), 0, st, s->fb_count);
   if (fallback) hipLaunchKernelGGL(surr::zero_u32, dim3(1), dim3(1), 0, st, s->hull_count);
@@ -503,7 +535,9 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
       if ((e = hipStreamWaitEvent(s->side, s->ev_fork, 0)) != hipSuccess)
         return hip_fail(e, "hipStreamWaitEvent");
       PoolArgs ph = fallback_args(s->hull_list, s->hull_count);
-      rc = run_pool_with(m, ph, opts, s->side, s->side_next, s->side_tail, nullptr);
+      // with kernel timing on, this run (the fallback's larger part) is the
+      // one timed
+      rc = run_pool_with(m, ph, opts, s->side, s->side_next, s->side_tail, nullptr, true);
       if (rc) return rc;
       if ((e = hipEventRecord(s->ev_join, s->side)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
@@ -512,7 +546,7 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
     if (e != hipSuccess) return hip_fail(e, "launch surr_infer");
     if (fallback) {
       PoolArgs pa = fallback_args(s->fb_list, s->fb_count);
-      rc = run_pool(m, pa, opts, st);
+      rc = run_pool_with(m, pa, opts, st, m->d_next, m->tail, &m->order, false);
       if (rc) return rc;
       if ((e = hipStreamWaitEvent(st, s->ev_join, 0)) != hipSuccess)
         return hip_fail(e, "hipStreamWaitEvent");

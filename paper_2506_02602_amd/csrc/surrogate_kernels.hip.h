@@ -504,9 +504,11 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
       }
       if (a.trust_code) a.trust_code[cell] = code;
       if (code == 0) {
+        // a trusted cell's Y + dY >= -pos_tol; what lies below zero is
+        // written as zero, so no negative mass fraction reaches the state
         a.state[cell] = T1;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) a.state[(k + 1) * a.ld + cell] = Y1[k];
+        for (int k = 0; k < NS; ++k) a.state[(k + 1) * a.ld + cell] = fmax(Y1[k], 0.0);
       } else {
         fall = true;
       }

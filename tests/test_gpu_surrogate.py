@@ -55,6 +55,20 @@ def _rel_fro(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _output_units(out, ref, cache, theta):
+    """Element-wise distance of network outputs from the oracle's, in units of
+    the output's BF16 rounding scale S = 2^-7 sum_k |W4_ik| |h3_k|: what the
+    output moves by if every last-layer activation h3_k (a BF16 value, so
+    one ulp is at most 2^-7 of it) moved by one ulp.  The kernel and the
+    oracle round the same quantities to BF16; they differ where an FP32
+    activation lies within the kernel's SiLU error of a BF16 rounding
+    boundary (one ulp there) and by FP32 summation order, both far below S.
+    A wrong weight, index or term moves an output by O(S * 2^7)."""
+    p = mo.unpack(theta, I, O)
+    S = 2.0 ** -7 * (np.abs(cache["H"][3]) @ np.abs(mo.bf16(p["W4"])).T)
+    return np.abs(out - ref) / S
+
+
 def test_fused_inference_matches_oracle(cg, gm9, omech9, mech9_path):
     """MLP outputs of the fused kernel vs the BF16-emulating oracle; trust
     decisions identical given the same network outputs; trusted cells get
@@ -77,10 +91,12 @@ def test_fused_inference_matches_oracle(cg, gm9, omech9, mech9_path):
     torch.cuda.synchronize()
     out_gpu = os_.cpu().numpy().astype(np.float64)
     z = (X - norm["mu_in"]) / norm["sd_in"]
-    out_ref, _ = mo.forward(theta.astype(np.float64), z, I, O)
-    err = _rel_fro(out_gpu, out_ref)
-    print(f"[surrogate] fused forward rel Frobenius err {err:.2e}", flush=True)
-    assert err < 5e-3
+    out_ref, cache = mo.forward(theta.astype(np.float64), z, I, O)
+    u = _output_units(out_gpu, out_ref, cache, theta.astype(np.float64))
+    print(f"[surrogate] fused forward: {u.size} outputs, max {u.max():.3f} rounding units, "
+          f"{(u > 0.1).sum()} above 0.1, rel Frobenius {_rel_fro(out_gpu, out_ref):.2e}",
+          flush=True)
+    assert u.max() <= 1.0
     codes_ref = mo.trust_codes(omech9, state, 1e-7, z, out_gpu.astype(np.float32), norm, trust)
     codes = tc.cpu().numpy()
     assert np.array_equal(codes, codes_ref)
@@ -88,8 +104,10 @@ def test_fused_inference_matches_oracle(cg, gm9, omech9, mech9_path):
     new = g.cpu().numpy()
     inc = out_gpu * norm["sd_out"] + norm["mu_out"]
     ok = codes == 0
-    assert np.allclose(new[0, ok], state[0, ok] + inc[ok, 0], rtol=1e-14)
-    assert np.allclose(new[1:10, ok], state[1:10, ok] + inc[ok, 1:].T, rtol=1e-13, atol=1e-18)
+    want = mo.trusted_update(state[:, ok], inc[ok])
+    assert np.allclose(new[0, ok], want[0], rtol=1e-14)
+    assert np.allclose(new[1:10, ok], want[1:], rtol=1e-13, atol=1e-18)
+    assert (new[1:10, ok] >= 0.0).all()                 # clipped at zero
     assert np.array_equal(new[:, ~ok], state[:, ~ok])
 
 
@@ -104,10 +122,11 @@ def test_generic_forward_matches_oracle(cg, gm9, mech9_path):
     Xf = X.astype(np.float32)
     out = cg.surrogate_forward(s, to_gpu(Xf)).cpu().numpy().astype(np.float64)
     z32 = (Xf - nm[:I]) / nm[I:2 * I]                  # the kernel standardises in FP32
-    ref, _ = mo.forward(theta.astype(np.float64), z32.astype(np.float64), I, O)
-    err = _rel_fro(out, ref)
-    print(f"[surrogate] training-path forward rel Frobenius err {err:.2e}", flush=True)
-    assert err < 5e-3
+    ref, cache = mo.forward(theta.astype(np.float64), z32.astype(np.float64), I, O)
+    u = _output_units(out, ref, cache, theta.astype(np.float64))
+    print(f"[surrogate] training-path forward: max {u.max():.3f} rounding units, "
+          f"rel Frobenius {_rel_fro(out, ref):.2e}", flush=True)
+    assert u.max() <= 1.0
 
 
 def test_gradients_match_oracle(cg, gm9):
@@ -131,29 +150,41 @@ def test_gradients_match_oracle(cg, gm9):
 
 
 def test_one_adam_step_matches_oracle(cg, gm9):
-    """With the identity normaliser one training step on one batch equals the
-    oracle's Adam step from the oracle gradient (the first Adam step is
-    -lr g/(|g|+eps), i.e. about -lr sign(g))."""
+    """One training step equals the oracle's Adam step (FP64) applied to the
+    kernel's own gradient of the same batch, for every parameter, to the
+    rounding of the FP32 update.  The batch repeats one sample, so the
+    epoch's permutation of its rows cannot change the gradient's summation
+    (the training step's gradient is then bitwise surrogate_grad's); the
+    gradient itself is held to the oracle's in test_gradients_match_oracle."""
+    import torch
     rng = np.random.Generator(np.random.PCG64(8))
     B = 256
-    X = rng.standard_normal((B, I)).astype(np.float32)
-    Y = rng.standard_normal((B, O)).astype(np.float32)
+    X = np.repeat(rng.standard_normal((1, I)), B, axis=0).astype(np.float32)
+    Y = np.repeat(rng.standard_normal((1, O)), B, axis=0).astype(np.float32)
     s = cg.Surrogate(gm9, seed=6)
     theta0, _ = s.get_params()
     ident = np.concatenate([np.zeros(I), np.ones(I), np.zeros(O), np.ones(O),
                             np.full(I, -10.0), np.full(I, 10.0)]).astype(np.float32)
     s.set_params(norm=ident)
+    g_gpu, _ = cg.surrogate_grad(s, to_gpu(X), to_gpu(Y))
+    g_gpu = g_gpu.cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
     cg.surrogate_train(s, to_gpu(X), to_gpu(Y), epochs=1, batch=B, lr=1e-3, seed=1)
     theta1, _ = s.get_params()
-    g_ref, _ = mo.backward(theta0.astype(np.float64), X.astype(np.float64), Y.astype(np.float64), I, O)
-    th_ref, _, _ = mo.adam_step(theta0.astype(np.float64), g_ref, np.zeros_like(g_ref),
-                                np.zeros_like(g_ref), 1, lr=1e-3)
-    d_gpu = theta1.astype(np.float64) - theta0
-    d_ref = th_ref - theta0
-    close = np.abs(d_gpu - d_ref) <= 1e-5
-    print(f"[surrogate] adam step: {close.mean() * 100:.3f} % of parameters within 1e-5", flush=True)
-    assert close.mean() > 0.99
-    assert np.abs(d_gpu).max() <= 1.001e-3
+    # the kernel's decay rates are FP32 numbers (0.9f, 0.999f), used both in
+    # the moment updates and in the bias corrections
+    th_ref, _, _ = mo.adam_step(theta0.astype(np.float64), g_gpu, np.zeros_like(g_gpu),
+                                np.zeros_like(g_gpu), 1, lr=1e-3,
+                                beta1=float(np.float32(0.9)), beta2=float(np.float32(0.999)))
+    # FP32 master weights: the update is rounded to FP32 once, and the FP32
+    # step arithmetic (a few roundings of a value <= lr) adds below 1e-9
+    ulp = np.spacing(np.abs(th_ref).astype(np.float32)).astype(np.float64)
+    err = np.abs(theta1.astype(np.float64) - th_ref)
+    print(f"[surrogate] adam step: max {np.max(err / (ulp + 1e-9)):.3f} (FP32 ulp + 1e-9) "
+          f"over {err.size} parameters", flush=True)
+    assert (err <= ulp + 1e-9).all()
+    d = theta1.astype(np.float64) - theta0
+    assert np.abs(d).max() <= 1.001e-3 and np.count_nonzero(d) > err.size // 2
 
 
 def test_training_reduces_loss(cg, gm9):

@@ -74,8 +74,10 @@ def test_surrogate_beats_plain_within_error_targets(trained):
     assert float(eT.max()) <= 1e-3 and float(eY.max()) <= 1e-4
     assert n_fb / n < 0.2
     # the handful of fallback cells are the stiffest ones: their sequential
-    # steps add a fixed latency after inference, so the margin grows with the
-    # field (about 1.6x at 256^3 in the benchmark)
+    # steps add a fixed latency after inference.  On this field every cell
+    # is a trajectory state (no out-of-hull cells); the benchmark's 256^3
+    # field adds 10 % reacting-front states outside the training hull, whose
+    # FP64 fallback dominates there and keeps the gain near 1.1x
     assert t_plain / t_surr > 1.1
 
 
