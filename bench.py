@@ -1,25 +1,44 @@
-"""Throughput of the per-cell FP64 chemistry integrator on one MI355X.
+"""Throughput of one flow step of the per-cell chemistry path on one MI355X:
+plain FP64 vs surrogate+fallback.
 
-One step = one flow step of the whole hot path over one workload; the
-default is the 1024 x 1024 reacting-front field (1,048,576 cells of the
-9-species / 21-reaction mechanism, dt = 1e-7 s, rtol 1e-8, atol 1e-10): every
-cell is advanced by dt with the LSRK4(3)5 two-register scheme and WRMS
-control, in the persistent compacting kernel, launched as one captured HIP
-graph.  Inputs are resident in HBM; each timed step first restores the
-pristine field with a device-to-device copy (inside the timed region) so
-every step integrates the same input.  --workload selects the other fields
-(AMR hierarchy, stress fields, the hot-cell throughput probe).
+Default workload: the 256^3 evaluation field (16,777,216 cells of the seeded
+9-species / 21-reaction H/O/N mechanism; 90 % states of held-out
+stoichiometric H2/O2/N2 ignition trajectories in smooth 3-D blobs, 10 %
+reacting-front states, cold and hot, outside the surrogate's training hull),
+dt = 1e-7 s, rtol 1e-8, atol 1e-10.  Set-up, untimed: training pairs from the
+FP64 integrator (4096 cells integrated through ignition), the surrogate
+trained on the GPU by its own kernels, trust thresholds chosen on held-out
+trajectories, the field built on the GPU.  Timed, each step from the same
+pristine field (a device-to-device restore before every step, outside the
+HIP-event interval):
 
-Prints one JSON line.  --gpus N with N > 1 is refused: the integrator runs on
-one GPU per process (cells are independent; sharding them over GPUs is
-described in the design notes, not built).
+* plain FP64: every cell advanced by dt with the LSRK4(3)5 two-register
+  scheme and WRMS control (persistent compacting kernel, cooperative tail),
+  the batched call captured in one HIP graph;
+* surrogate+fallback: features, BF16-MFMA network and FP64 trust test for
+  every cell; trusted cells take the network's increment, the others are
+  integrated by the FP64 path in the same call.
+
+`value` is the surrogate+fallback rate in cells/s (cells over the mean
+HIP-event time of the step on the launch stream); the plain FP64 rate, the
+speedup, the fallback fraction and the trusted cells' error against FP64 sit
+beside it.  `roofline` is the surrogate+fallback step's dominant kernel,
+`plain_fp64.roofline` the plain step's.  The 1024 x 1024 reacting-front field
+is measured as well (`front`).  `--workload` selects another field as the
+headline instead (front, AMR hierarchy, stress fields, divergence fields).
+
+Prints one JSON line.  --gpus N with N > 1 is refused: the path runs on one
+GPU per process (cells are independent; sharding them over GPUs is described
+in the design notes, not built).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -29,6 +48,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "chem-integrated cells/s per flow step: plain FP64 vs surrogate+fallback"
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+# algorithmic flops of one surrogate evaluation: 2 (12*128 + 128*128 + 128*128 + 128*10)
+SURROGATE_FLOPS_PER_CELL = 2 * (12 * 128 + 2 * 128 * 128 + 128 * 10)
 
 
 def log(msg):
@@ -46,7 +68,7 @@ def parse():
     ap.add_argument("--scheme", default="lsrk", choices=["lsrk", "rkf45", "ros4"],
                     help="lsrk: the paper's two-register LSRK4(3)5; rkf45: the full-storage "
                          "Runge-Kutta-Fehlberg 4(5) comparison scheme; ros4: the implicit "
-                         "(Rosenbrock) comparator")
+                         "(Rosenbrock) comparator (fields other than the surrogate field)")
     ap.add_argument("--tail", type=int, default=0,
                     help="steps after which a cell moves to the cooperative kernel "
                          "(0 = default, < 0 = never)")
@@ -54,35 +76,31 @@ def parse():
                     help="most handed-over cells per CU the cooperative kernel takes "
                          "(0 = default, < 0 = no limit)")
     ap.add_argument("--pool-order", type=int, default=0,
-                    help="deal cells expected to be slow over the first claims (1), keep the "
-                         "pool order (-1), or the tuned choice (0)")
+                    help="deal cells expected to be slow over the first claims (1), group "
+                         "by NASA-7 range (2), keep the pool order (-1), or the tuned choice (0)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--workload", default="front",
-                    choices=["front", "front_hot_tiled", "amr", "stress9", "stress32", "cells",
-                             "diverge_a1", "diverge_a01"])
+    ap.add_argument("--workload", default="surrogate256",
+                    choices=["surrogate256", "front", "front_hot_tiled", "amr", "stress9",
+                             "stress32", "cells", "diverge_a1", "diverge_a01"])
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2506_02602_amd",
                                                          "tuning_gfx950.json"),
                     help="autotuner cache (JSON, keyed by mechanism hash, size bucket, GPU "
                          "architecture); a hit skips the sweep; 'none' = always sweep")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (block/chunk/hand-off from the library defaults)")
-    ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the surrogate+fallback leg on the 256^3 evaluation field")
+    ap.add_argument("--no-front", action="store_true",
+                    help="with the surrogate field as headline, skip the front-field leg")
     ap.add_argument("--surrogate-epochs", type=int, default=12)
     return ap.parse_args()
 
 
-# HBM bytes of one flow step (persistent + cooperative kernel, the timed
-# launches of this bench with the committed tuning), from two rocprofv3
-# --pmc runs, FETCH_SIZE then WRITE_SIZE, each scaled by what the counter
+# HBM bytes per launch of the dominant kernels, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE) of this bench, each scaled by what the counter
 # reads for the restore copy of known size in the same run (FETCH_SIZE
 # reports 0.5002 of the copied bytes, WRITE_SIZE 1.000).  Keyed by a digest of
 # the kernel sources the counters were taken on; any change nulls it.
-TRAFFIC = {"front": ("5c9d19c03c3dbae1", 232.9e6,
-                     {"lsrk_persistent": 203.20e6, "lsrk_coop": 29.54e6}),
-           "stress9": ("5c9d19c03c3dbae1", 3605.3e6,
-                       {"lsrk_persistent": 3518.15e6, "lsrk_coop": 0.04e6})}
+TRAFFIC = {}
 
 
 def kernel_digest():
@@ -100,109 +118,20 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-PEAK_BF16_MFMA_TFLOPS = 2500.0
-# algorithmic flops of one surrogate evaluation: 2 (12*128 + 128*128 + 128*128 + 128*10)
-SURROGATE_FLOPS_PER_CELL = 2 * (12 * 128 + 2 * 128 * 128 + 128 * 10)
-
-
-def surrogate_leg(args):
-    """Config-5 comparison: train the surrogate on FP64 trajectory pairs, tune
-    the trust thresholds on held-out trajectories, then time plain FP64 and
-    surrogate+fallback on the 256^3 evaluation field (each timed step restores
-    the pristine field first) and judge the trusted cells against FP64."""
-    import torch
-    from paper_2506_02602_amd import chemgpu as cg, surrogate as sg, workloads as wl
-    m = cg.chem_mech_load(wl.mech_file("mech9"))
-    t0 = time.perf_counter()
-    ds = sg.build_dataset(m)
-    t_data = time.perf_counter() - t0
-    log(f"surrogate: {int(ds['X'].shape[0])} training pairs in {t_data:.1f} s; training")
-    n_pairs = int(ds["X"].shape[0])
-    s = cg.Surrogate(m, seed=11)
-    t0 = time.perf_counter()
-    loss = cg.surrogate_train(s, ds["X"], ds["Y"], epochs=args.surrogate_epochs, batch=4096,
-                              lr=3e-3, seed=2)
-    t_train = time.perf_counter() - t0
-    log("surrogate: tuning trust thresholds")
-    trust, tstats = sg.tune_trust(s, m, sg.validation_states(ds))
-    if trust is None:
-        trust = (0.0, 1e-6, 1e-7, 0.05)
-    del ds
-    torch.cuda.empty_cache()
-    log("surrogate: building the 256^3 evaluation field")
-    field, out_mask = sg.inference_field(m)
-    n = field.shape[1]
-    work = torch.empty_like(field)
-    # one launch configuration for both paths: the autotuner's choice on the
-    # evaluation field itself (the fallback integrates a subset of it)
-    base = cg.make_opts(rtol=wl.RTOL, atol=wl.ATOL)
-    cache = None if args.tune_cache == "none" else args.tune_cache
-    opts = cg.chem_autotune(m, [dict(state=field, dt=wl.DT_FLOW)], base, reps=1, cache_path=cache)
-    log(f"surrogate: launch block {opts.block_size} chunk {opts.chunk_steps} "
-        f"hand-off {opts.tail_steps}")
-    ref = field.clone()
-    cg.chem_integrate(m, ref, wl.DT_FLOW, opts)
-    stream = torch.cuda.current_stream()
-    K = max(1, min(args.steps, 5))
-
-    def timed(fn):
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(K)]
-        work.copy_(field)
-        fn()                                   # warm-up
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for a, b in ev:
-            work.copy_(field)
-            a.record(stream)
-            fn()
-            b.record(stream)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / K, float(np.mean([a.elapsed_time(b) for a, b in ev]))
-
-    t_plain, k_plain = timed(lambda: cg.chem_integrate(m, work, wl.DT_FLOW, opts))
-    t_surr, k_surr = timed(lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True,
-                                                      opts=opts))
-    t_inf, k_inf = timed(lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=False))
-    tc = torch.zeros(n, dtype=torch.int32, device="cuda")
-    work.copy_(field)
-    n_fb = cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True, trust_code=tc,
-                              want_count=True, opts=opts)
-    ok = tc == 0
-    eT, eY = sg.errors(work[:, ok], ref[:, ok], m.n_species)
-    idx = torch.randperm(int(ok.sum()), device="cuda")[:2000000]
-    q = lambda x: float(torch.quantile(x[idx].float(), 0.999))
-    fb = ~ok
-    fT, fY = sg.errors(work[:, fb], ref[:, fb], m.n_species)
-    achieved = SURROGATE_FLOPS_PER_CELL * n / (k_inf * 1e-3) / 1e12
-    return {
-        "workload": "256^3 = 16,777,216 cells: 90% held-out H2/O2/N2 ignition-trajectory states "
-                    "in smooth 3-D blobs, 10% reacting-front states outside the training hull; "
-                    "dt 1e-7 s; 9-species mechanism",
-        "cells": n,
-        "plain_fp64_cells_per_s": n / t_plain, "surrogate_fallback_cells_per_s": n / t_surr,
-        "speedup": t_plain / t_surr,
-        "launch": {"block_size": opts.block_size, "chunk_steps": opts.chunk_steps,
-                   "tail_steps": opts.tail_steps},
-        "ms_plain": 1e3 * t_plain, "ms_surrogate_fallback": 1e3 * t_surr,
-        "ms_inference_only": k_inf,
-        "fallback_fraction": n_fb / n,
-        "trust": {"hull_margin": trust[0], "elem_tol": trust[1], "pos_tol": trust[2],
-                  "energy_tol_K": trust[3], "validation": tstats},
-        "trusted_error_vs_fp64": {"max_rel_T": float(eT.max()), "p999_rel_T": q(eT),
-                                  "max_abs_Y": float(eY.max()), "p999_abs_Y": q(eY)},
-        "fallback_cells_max_diff_vs_plain": {"rel_T": float(fT.max()) if fb.any() else 0.0,
-                                             "abs_Y": float(fY.max()) if fb.any() else 0.0},
-        "train": {"pairs": n_pairs, "epochs": args.surrogate_epochs, "batch": 4096,
-                  "first_loss": float(loss[0]), "final_loss": float(loss[-1]),
-                  "data_s": t_data, "train_s": t_train},
-        "roofline_inference": {"bound": "mfma", "achieved": achieved,
-                               "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                               "frac": achieved / PEAK_BF16_MFMA_TFLOPS},
-    }
+def traffic(workload, kernel):
+    rec = TRAFFIC.get(workload)
+    if not rec or rec[0] != kernel_digest():
+        return None
+    return rec[1].get(kernel)
 
 
 WORKLOADS = {
+    "surrogate256": "256^3 = 16,777,216 cells: 90% states of held-out stoichiometric H2/O2/N2 "
+                    "ignition trajectories in smooth 3-D blobs, 10% reacting-front states (cold "
+                    "300 K / 1 atm and hot 1500-3000 K / 5-30 atm) outside the training hull; "
+                    "seeded 9-species 21-reaction H/O/N mechanism; dt 1e-7 s, rtol 1e-8, "
+                    "atol 1e-10; plain FP64 LSRK vs 12-128-128-128-10 SiLU MLP (BF16 MFMA) with "
+                    "FP64 trust test and FP64 fallback",
     "front": "reacting front 1024x1024 (1,048,576 cells), 2% hot band 1500-3000 K / 5-30 atm, "
              "rest 300 K / 1 atm; seeded 9-species 21-reaction H/O/N mechanism; dt 1e-7 s, "
              "rtol 1e-8, atol 1e-10; plain FP64 LSRK with active-cell compaction",
@@ -250,64 +179,145 @@ def load_workload(name):
     return path, [dict(state=wl.cells_uniform(path), dt=wl.DT_FLOW, n_sub=1)]
 
 
-def cpu_baseline(boxes, path, threads, target_s=10.0):
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    cells drawn uniformly (seed 123) from the concatenated boxes, each
-    integrated over its box's n_sub sub-calls of dt, in chunks of 4096 until
-    about target_s seconds of host time have been spent (the whole sample is
-    cycled again if it is used up first)."""
+# ------------------------------------------------------------ host / oracle
+def host_info():
+    """lscpu model and core counts of this host, and the CPUs this process may use."""
+    info = {"model": None, "sockets": None, "cores_per_socket": None, "threads_per_core": None}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "Model name":
+                info["model"] = v
+            elif k == "Socket(s)":
+                info["sockets"] = int(v)
+            elif k == "Core(s) per socket":
+                info["cores_per_socket"] = int(v)
+            elif k == "Thread(s) per core":
+                info["threads_per_core"] = int(v)
+            elif k == "CPU(s)":
+                info["logical_cpus"] = int(v)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    if info["sockets"] and info["cores_per_socket"]:
+        info["physical_cores"] = info["sockets"] * info["cores_per_socket"]
+    info["cpus_allowed"] = len(os.sched_getaffinity(0))
+    info["omp_num_threads_env"] = os.environ.get("OMP_NUM_THREADS")
+    return info
+
+
+def oracle_threads(host, asked):
+    """All physical cores this process may use: the CPUs it is allowed to run
+    on, at most one per physical core, at most OMP_NUM_THREADS (the host's
+    share for one GPU) when that is set."""
+    if asked:
+        return asked
+    n = host["cpus_allowed"]
+    if host.get("physical_cores"):
+        n = min(n, host["physical_cores"])
+    env = host.get("omp_num_threads_env")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def native_oracle():
+    """The oracle built for this host (-O3 -march=native, no FP contraction)
+    in a temporary directory; falls back to the portable build."""
+    import oracle
+    try:
+        oracle.use_native_build(tempfile.mkdtemp(prefix="chemgpu_oracle_"))
+        return "gcc -O3 -march=native -ffp-contract=off -fno-fast-math -fopenmp"
+    except (OSError, subprocess.CalledProcessError, RuntimeError) as e:
+        log(f"native oracle build failed ({e}); using the portable build")
+        return "gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp (portable build)"
+
+
+def time_oracle(om, state, dt, n_sub, threads):
+    s = np.array(state)
+    t0 = time.perf_counter()
+    for _ in range(n_sub):
+        om.integrate(s, dt, nthreads=threads)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_strata(path, strata, threads, build, host, one_thread_frac=0.125):
+    """The oracle on a stratified sample of a field: strata is a list of
+    (name, cells in the field, sampled states [N+3, k], dt, n_sub).  Each
+    stratum's sample is timed on `threads` threads and its per-cell time
+    weighted back to the whole field; a fixed fraction of every sample is
+    timed again on one thread."""
     import oracle
     om = oracle.Mech(path)
-    sizes = np.array([b["state"].shape[1] for b in boxes])
-    n = int(sizes.sum())
-    rng = np.random.Generator(np.random.PCG64(123))
-    pick = rng.permutation(n)[:262144]
-    starts = np.concatenate([[0], np.cumsum(sizes)])
-    box_of = np.searchsorted(starts, pick, side="right") - 1
-    done = 0
-    t0 = time.perf_counter()
-    el = 0.0
-    while el < target_s:
-        for c0 in range(0, len(pick), 4096):
-            sel, bsel = pick[c0:c0 + 4096], box_of[c0:c0 + 4096]
-            for bi in np.unique(bsel):
-                b = boxes[bi]
-                s = np.ascontiguousarray(b["state"][:, sel[bsel == bi] - starts[bi]])
-                for _ in range(b.get("n_sub", 1)):
-                    om.integrate(s, b["dt"], nthreads=threads)
-            done += len(sel)
-            el = time.perf_counter() - t0
-            if el >= target_s:
-                break
-    return {"value": done / el, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} cells drawn uniformly (seed 123) from the same workload, one flow "
-                      f"step each (with the box's sub-calls), in chunks of 4096: {el:.1f} s wall "
-                      f"on {threads} host threads"}
+    t_all = t_one = 0.0
+    total = sampled = 0
+    parts = []
+    for name, n_field, st, dt, n_sub in strata:
+        k = st.shape[1]
+        if k == 0:
+            continue
+        el = time_oracle(om, st, dt, n_sub, threads)
+        k1 = max(1, int(k * one_thread_frac))
+        el1 = time_oracle(om, st[:, :k1], dt, n_sub, 1)
+        t_all += el / k * n_field
+        t_one += el1 / k1 * n_field
+        total += n_field
+        sampled += k
+        parts.append(f"{name}: {k} of {n_field} cells, {el:.2f} s on {threads} threads, "
+                     f"{k1} cells {el1:.2f} s on 1 thread")
+    return {"value": total / t_all, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": total / t_one,
+            "per_core": total / t_all / threads,
+            "sample": "stratified sample of the same field, every sampled cell one flow step "
+                      "(with its sub-calls); per-stratum time per cell weighted back to the "
+                      "whole field (an extrapolation): " + "; ".join(parts),
+            "oracle_build": build, "host": host}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: the integrator runs on one GPU (asked for --gpus {args.gpus}); "
-              "the chemistry step needs no cross-GPU exchange, see the design notes",
-              file=sys.stderr)
-        sys.exit(2)
+# ------------------------------------------------------------- FP64 boxes
+def dominant_fp64(kt, per_cell_steps, tail, cap, n_cu, flops_per_step):
+    """The larger of the per-lane kernel (with its resumption launch) and the
+    cooperative kernel, with its algorithmic FP64 rate: a cell still stepping
+    after the hand-off point takes its remaining steps in the cooperative
+    kernel when the list fits the cap, else in the per-lane resumption."""
+    coop_steps = 0
+    if tail > 0:
+        over = per_cell_steps[per_cell_steps > tail]
+        if cap < 0 or over.size <= cap * n_cu:
+            coop_steps = int((over - tail).sum())
+    total = int(per_cell_steps.sum())
+    pers_ms = kt["persistent"] + kt["resume"]
+    if kt["coop"] > pers_ms:
+        dom, dom_ms, dom_steps = "lsrk_coop", kt["coop"], coop_steps
+    else:
+        dom, dom_ms, dom_steps = "lsrk_persistent", pers_ms, total - coop_steps
+    ach = dom_steps * flops_per_step / (dom_ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "launch_ms": dom_ms,
+            "rk_steps_per_launch": dom_steps}
+
+
+def measure_boxes(args, workload, hboxes=None, path=None, steps=None):
+    """One flow step of a field given as boxes, captured in one graph; the
+    flow step's HIP-event time, the dominant kernel's FP64 roofline, per-cell
+    step counts.  Returns a dict."""
     import torch
     from paper_2506_02602_amd import chemgpu, codegen, workloads as wl
-
-    path, hboxes = load_workload(args.workload)
+    if hboxes is None:
+        path, hboxes = load_workload(workload)
+    K = steps or args.steps
     n = int(sum(b["state"].shape[1] for b in hboxes))
     dev = torch.device("cuda:0")
     boxes, pristine = [], []
     for b in hboxes:
-        st = torch.from_numpy(b["state"]).to(dev)
+        st = b["state"] if torch.is_tensor(b["state"]) else torch.from_numpy(b["state"]).to(dev)
         nb = st.shape[1]
         pristine.append(st.clone())
         boxes.append(dict(state=st, dt=b["dt"], n_sub=b.get("n_sub", 1), level=b.get("level", 0),
                           status=torch.zeros(nb, dtype=torch.int32, device=dev),
                           counts=torch.zeros(2 * nb, dtype=torch.int32, device=dev)))
-    mech = chemgpu.chem_mech_load(path)
-    chemgpu.chem_workspace_reserve(mech, n)
+    mech = chemgpu.chem_mech_load(path, reserve=n)
     base = chemgpu.make_opts(rtol=wl.RTOL, atol=wl.ATOL, chunk_steps=args.chunk,
                              block_size=args.block, tail_steps=args.tail, scheme=args.scheme,
                              tail_cap=args.tail_cap, pool_order=args.pool_order)
@@ -318,29 +328,23 @@ def main():
             b["state"].copy_(p)
 
     tuned = None
-    log(f"workload {args.workload}: {n} cells in {len(boxes)} boxes")
+    log(f"{workload}: {n} cells in {len(boxes)} boxes")
     if not args.no_autotune and not (args.chunk or args.block):
-        log("autotuning block, chunk and hand-off")
-        # small workloads launch in milliseconds: time each candidate 3 times
         cache = None if args.tune_cache == "none" else args.tune_cache
         tb = chemgpu.chem_autotune(mech, boxes, base, reps=3 if n <= 2_000_000 else 1,
                                    cache_path=cache)
         tuned = {"block_size": tb.block_size, "chunk_steps": tb.chunk_steps,
                  "tail_steps": tb.tail_steps, "tail_cap": tb.tail_cap,
                  "pool_order": tb.pool_order}
-    log(f"launch {tuned}; untimed pass with per-cell counters")
-    # one untimed pass with per-cell counters for the flop count
+    log(f"{workload}: launch {tuned}; untimed pass with per-cell counters")
     restore()
     chemgpu.chem_integrate_batched(mech, boxes, base)
     torch.cuda.synchronize()
     st = np.concatenate([b["status"].cpu().numpy() for b in boxes])
     cn = np.concatenate([b["counts"].cpu().numpy().reshape(2, -1) for b in boxes], axis=1)
     total_steps = int(cn.sum())
-    m = codegen.parse(path)
-    flops_per_step = codegen.step_flops(m, args.scheme)
-    flops_per_launch = total_steps * flops_per_step
+    flops_per_step = codegen.step_flops(codegen.parse(path), args.scheme)
 
-    # the timed launches: one graph holding the whole batched call
     tboxes = [dict(b, status=None, counts=None) for b in boxes]
     graph = chemgpu.chem_graph_capture_batched(mech, tboxes, base)
     for _ in range(max(args.warmup, 1)):
@@ -348,10 +352,10 @@ def main():
         graph.launch()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    log(f"timing {args.steps} steps")
+          for _ in range(K)]
+    log(f"{workload}: timing {K} steps")
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(K):
         restore()
         ev[k][0].record(stream)
         graph.launch(stream)
@@ -361,22 +365,13 @@ def main():
     graph.close()
     kern_all = np.array([a.elapsed_time(b) for a, b in ev])
     kern_ms = float(np.mean(kern_all))
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = n * args.steps / elapsed
-    achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
-    rec = TRAFFIC.get(args.workload) if args.scheme == "lsrk" else None
-    current = bool(rec) and rec[0] == kernel_digest()
 
-    # The dominant kernel, timed live: the same flow step as plain calls with
+    # the dominant kernel, timed live: the same flow step as plain calls with
     # the library's per-kernel timing (HIP events around each launch, on the
-    # launch stream).  Its algorithmic flops: a cell still stepping after
-    # the hand-off point takes its remaining steps in the cooperative kernel
-    # when the list fits the cap, else in the resumption launch of the
-    # per-lane kernel.
-    log("per-kernel timing")
+    # launch stream)
     chemgpu.chem_set_kernel_timing(mech, True)
     recs = []
-    for _ in range(max(3, min(args.steps, 10))):
+    for _ in range(max(3, min(K, 10))):
         restore()
         chemgpu.chem_integrate_batched(mech, tboxes, base)
         recs.append(chemgpu.chem_kernel_times(mech))
@@ -385,67 +380,312 @@ def main():
     eff = tuned or {}
     tail = args.tail or eff.get("tail_steps", 0)
     cap = args.tail_cap or eff.get("tail_cap", 0) or 64   # 0: the library's default, 64 per CU
-    per_cell = cn.sum(axis=0)
-    coop_steps = 0
-    if args.scheme == "lsrk" and tail > 0:
-        over = per_cell[per_cell > tail]
-        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-        if cap < 0 or over.size <= cap * n_cu:
-            coop_steps = int((over - tail).sum())
-    pers_ms = kt["persistent"] + kt["resume"]
-    if kt["coop"] > pers_ms:
-        dom, dom_ms, dom_steps = "lsrk_coop", kt["coop"], coop_steps
-    else:
-        dom, dom_ms, dom_steps = "lsrk_persistent", pers_ms, total_steps - coop_steps
-    dom_achieved = dom_steps * flops_per_step / (dom_ms * 1e-3) / 1e12
-    dom_traffic = rec[2].get(dom) if current and len(rec) > 2 else None
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    roof = dominant_fp64(kt, cn.sum(axis=0), tail if args.scheme == "lsrk" else 0, cap, n_cu,
+                         flops_per_step)
+    roof["traffic"] = traffic(workload, roof["kernel"]) if args.scheme == "lsrk" else None
+    achieved = total_steps * flops_per_step / (kern_ms * 1e-3) / 1e12
     nv = mech.n_species + 1
     out = {
-        "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
-                   "cells": n, "boxes": len(boxes),
-                   "scheme": args.scheme,
-                   "chunk_steps": args.chunk, "block_size": args.block, "tail_steps": args.tail,
-                   "tail_cap": args.tail_cap, "pool_order": args.pool_order,
-                   "autotuned": tuned},
-        # the dominant kernel: its algorithmic flops per launch over its mean
-        # launch time (traffic: its HBM bytes per launch from the counters)
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": dom_achieved,
-                     "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": dom_achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": dom_traffic,
-                     "launch_ms": dom_ms, "rk_steps_per_launch": dom_steps},
-        # the whole flow step (all its launches) against the HIP-event time of
-        # the graph launch
+        "cells": n, "boxes": len(boxes), "scheme": args.scheme,
+        "value": n / (kern_ms * 1e-3),
+        "ms_per_step": kern_ms,
+        "kernel_ms_p10_p50_p90": [float(np.percentile(kern_all, q)) for q in (10, 50, 90)],
+        "wall_ms_per_step_incl_restore": elapsed * 1e3 / K,
+        "autotuned": tuned,
+        "roofline": roof,
         "roofline_flow_step": {"bound": "alu", "achieved": achieved,
                                "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                               "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-                               "traffic": rec[1] if current else None},
+                               "frac": achieved / PEAK_FP64_VECTOR_TFLOPS},
         "kernel_times_ms": kt,
         # per flow step: read (T, Y, rho, h), write (T, Y, h) of every cell
         "hbm_algorithmic_bytes": n * 8 * ((nv + 2) + (nv + 1)),
-        "kernel_ms": kern_ms,
-        "kernel_ms_p10_p50_p90": [float(np.percentile(kern_all, q)) for q in (10, 50, 90)],
-        "steps_per_flow_step": {"total_rk_steps": total_steps,
-                                "rejected": int(cn[1].sum()),
+        "steps_per_flow_step": {"total_rk_steps": total_steps, "rejected": int(cn[1].sum()),
                                 "max_per_cell": int(cn.sum(axis=0).max()),
                                 "status_nonzero": int((st != 0).sum())},
         "flops_per_rk_step": flops_per_step,
     }
     sub_calls = int(sum(b["state"].shape[1] * b.get("n_sub", 1) for b in hboxes))
     if sub_calls != n:
-        out["cell_subcalls_per_s"] = sub_calls * args.steps / elapsed
-    if not args.no_cpu:
-        threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
-        log(f"oracle on {threads} host threads")
-        out["cpu_baseline"] = cpu_baseline(hboxes, path, threads)
-    if not args.no_surrogate and args.workload == "front":
-        del boxes, pristine, tboxes
-        torch.cuda.empty_cache()
-        log("surrogate leg")
-        out["surrogate"] = surrogate_leg(args)
+        out["cell_subcalls_per_s"] = sub_calls / (kern_ms * 1e-3)
+    mech.close()
+    return out
+
+
+def cpu_baseline_boxes(hboxes, path, threads, build, host, target_s=10.0):
+    """The oracle on a bounded sample of a field given as boxes: cells drawn
+    uniformly (seed 123) from the concatenated boxes, each integrated over its
+    box's sub-calls, in chunks of 4096 until about target_s seconds."""
+    import oracle
+    om = oracle.Mech(path)
+    sizes = np.array([b["state"].shape[1] for b in hboxes])
+    n = int(sizes.sum())
+    rng = np.random.Generator(np.random.PCG64(123))
+    pick = rng.permutation(n)[:262144]
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    box_of = np.searchsorted(starts, pick, side="right") - 1
+
+    def run(cells, nthreads, budget):
+        done, el, t0 = 0, 0.0, time.perf_counter()
+        while el < budget:
+            for c0 in range(0, len(pick), cells):
+                sel, bsel = pick[c0:c0 + cells], box_of[c0:c0 + cells]
+                for bi in np.unique(bsel):
+                    b = hboxes[bi]
+                    s = np.ascontiguousarray(b["state"][:, sel[bsel == bi] - starts[bi]])
+                    for _ in range(b.get("n_sub", 1)):
+                        om.integrate(s, b["dt"], nthreads=nthreads)
+                done += len(sel)
+                el = time.perf_counter() - t0
+                if el >= budget:
+                    break
+        return done, el
+    done, el = run(4096, threads, target_s)
+    done1, el1 = run(256, 1, target_s / 4)
+    return {"value": done / el, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": done1 / el1, "per_core": done / el / threads,
+            "sample": f"{done} cells drawn uniformly (seed 123) from the same workload, one flow "
+                      f"step each (with the box's sub-calls), in chunks of 4096: {el:.1f} s wall "
+                      f"on {threads} host threads; {done1} cells in {el1:.1f} s on 1 thread",
+            "oracle_build": build, "host": host}
+
+
+# ------------------------------------------------------- surrogate field
+def surrogate_field(args):
+    """The 256^3 field: plain FP64 and surrogate+fallback, each timed from the
+    pristine field.  Returns (result dict, field strata for the CPU baseline)."""
+    import torch
+    from paper_2506_02602_amd import chemgpu as cg, codegen, surrogate as sg, workloads as wl
+    path = wl.mech_file("mech9")
+    m = cg.chem_mech_load(path)
+    t0 = time.perf_counter()
+    ds = sg.build_dataset(m)
+    t_data = time.perf_counter() - t0
+    n_pairs = int(ds["X"].shape[0])
+    log(f"surrogate: {n_pairs} training pairs in {t_data:.1f} s; training")
+    s = cg.Surrogate(m, seed=11)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = cg.surrogate_train(s, ds["X"], ds["Y"], epochs=args.surrogate_epochs, batch=4096,
+                              lr=3e-3, seed=2)
+    t_train = time.perf_counter() - t0
+    train_flops = 3.0 * SURROGATE_FLOPS_PER_CELL * (n_pairs // 4096) * 4096 * args.surrogate_epochs
+    log("surrogate: tuning trust thresholds")
+    trust, tstats = sg.tune_trust(s, m, sg.validation_states(ds))
+    if trust is None:
+        trust = (0.0, 1e-6, 1e-7, 0.05)
+    del ds
+    torch.cuda.empty_cache()
+    log("surrogate: building the 256^3 evaluation field")
+    field, out_mask = sg.inference_field(m)
+    n = field.shape[1]
+    cg.chem_workspace_reserve(m, n)
+    cg.surrogate_reserve(s, n)
+    work = torch.empty_like(field)
+    base = cg.make_opts(rtol=wl.RTOL, atol=wl.ATOL)
+    cache = None if args.tune_cache == "none" else args.tune_cache
+    opts = cg.chem_autotune(m, [dict(state=field, dt=wl.DT_FLOW)], base, reps=1, cache_path=cache)
+    launch = {"block_size": opts.block_size, "chunk_steps": opts.chunk_steps,
+              "tail_steps": opts.tail_steps, "tail_cap": opts.tail_cap,
+              "pool_order": opts.pool_order}
+    log(f"surrogate: launch {launch}")
+    stream = torch.cuda.current_stream()
+    K = args.steps
+    flops_per_step = codegen.step_flops(codegen.parse(path), "lsrk")
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def timed(fn, k=K):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(k)]
+        for _ in range(max(args.warmup, 1)):
+            work.copy_(field)
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a, b in ev:
+            work.copy_(field)
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / k
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        return float(ms.mean()), ms, wall
+
+    # plain FP64: the batched call captured in one graph (as the other fields)
+    ref = field.clone()
+    stc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    cnc = torch.zeros(2 * n, dtype=torch.int32, device="cuda")
+    cg.chem_integrate(m, ref, wl.DT_FLOW, opts, status=stc, counts=cnc)
+    torch.cuda.synchronize()
+    plain_counts = cnc.view(2, n).cpu().numpy()
+    graph = cg.chem_graph_capture_batched(m, [dict(state=work, dt=wl.DT_FLOW)], opts)
+    log(f"surrogate field: timing {K} plain FP64 steps")
+    k_plain, k_plain_all, w_plain = timed(lambda: graph.launch(stream))
+    graph.close()
+    cg.chem_set_kernel_timing(m, True)
+    recs = []
+    for _ in range(3):
+        work.copy_(field)
+        cg.chem_integrate(m, work, wl.DT_FLOW, opts)
+        recs.append(cg.chem_kernel_times(m))
+    kt_plain = {k: float(np.mean([r[k] for r in recs])) for k in recs[0]}
+    cg.chem_set_kernel_timing(m, False)
+    per_cell = plain_counts.sum(axis=0)
+    roof_plain = dominant_fp64(kt_plain, per_cell, opts.tail_steps, opts.tail_cap or 64, n_cu,
+                               flops_per_step)
+    roof_plain["traffic"] = traffic("surrogate256_plain", roof_plain["kernel"])
+    plain_ach = int(per_cell.sum()) * flops_per_step / (k_plain * 1e-3) / 1e12
+
+    # surrogate + fallback
+    log(f"surrogate field: timing {K} surrogate+fallback steps")
+    k_surr, k_surr_all, w_surr = timed(
+        lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True, opts=opts))
+    k_inf, k_inf_all, _ = timed(
+        lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=False))
+    tc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    fst = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    fcn = torch.zeros(2 * n, dtype=torch.int32, device="cuda")
+    cg.chem_set_kernel_timing(m, True)
+    recs = []
+    for r in range(3):
+        work.copy_(field)
+        n_fb = cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True, opts=opts,
+                                  trust_code=tc, status=fst, counts=fcn, want_count=True)
+        recs.append(cg.chem_kernel_times(m))
+    cg.chem_set_kernel_timing(m, False)
+    kt_fb = {k: float(np.mean([r[k] for r in recs])) for k in recs[0]}
+    # the timed FP64 run is the one over the cells outside the hull (code 1)
+    tcn = tc.cpu().numpy()
+    hull = tcn == 1
+    fb_steps = fcn.view(2, n).cpu().numpy().sum(axis=0)
+    roof_fb = dominant_fp64(kt_fb, fb_steps[hull], opts.tail_steps, opts.tail_cap or 64, n_cu,
+                            flops_per_step)
+    roof_fb["traffic"] = traffic("surrogate256_fallback", roof_fb["kernel"])
+    inf_ach = SURROGATE_FLOPS_PER_CELL * n / (k_inf * 1e-3) / 1e12
+    roof_inf = {"bound": "mfma", "kernel": "surr_infer", "achieved": inf_ach,
+                "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": inf_ach / PEAK_BF16_MFMA_TFLOPS, "launch_ms": k_inf,
+                "cells_per_launch": n, "traffic": traffic("surrogate256_inference", "surr_infer")}
+    # the surrogate step's dominant kernel: the longer of the FP64 fallback's
+    # dominant kernel and the network
+    dom = roof_fb if roof_fb["launch_ms"] >= k_inf else roof_inf
+
+    # accuracy of the trusted cells against the plain FP64 result
+    ok = torch.from_numpy(tcn == 0).cuda()
+    eT, eY = sg.errors(work[:, ok], ref[:, ok], m.n_species)
+    idx = torch.randperm(int(ok.sum()), device="cuda")[:2000000]
+    q = lambda x: float(torch.quantile(x[idx].float(), 0.999))
+    fb = ~ok
+    fT, fY = sg.errors(work[:, fb], ref[:, fb], m.n_species)
+    neg = int((work[1:m.n_species + 1, ok] < 0).sum())
+    res = {
+        "cells": n,
+        "value": n / (k_surr * 1e-3),
+        "ms_per_step": k_surr,
+        "kernel_ms_p10_p50_p90": [float(np.percentile(k_surr_all, p)) for p in (10, 50, 90)],
+        "wall_ms_per_step_incl_restore": 1e3 * w_surr,
+        "speedup_vs_plain_fp64": k_plain / k_surr,
+        "fallback_fraction": n_fb / n,
+        "roofline": dom,
+        "roofline_inference": roof_inf,
+        "roofline_fallback_fp64": roof_fb,
+        "kernel_times_fallback_ms": kt_fb,
+        "fallback_rk_steps": {"hull_cells": int(hull.sum()),
+                              "hull_rk_steps": int(fb_steps[hull].sum()),
+                              "other_fallback_cells": int((tcn > 1).sum()),
+                              "other_rk_steps": int(fb_steps[tcn > 1].sum())},
+        "ms_inference_only": k_inf,
+        "plain_fp64": {
+            "cells_per_s": n / (k_plain * 1e-3), "ms_per_step": k_plain,
+            "kernel_ms_p10_p50_p90": [float(np.percentile(k_plain_all, p)) for p in (10, 50, 90)],
+            "wall_ms_per_step_incl_restore": 1e3 * w_plain,
+            "roofline": roof_plain,
+            "roofline_flow_step": {"bound": "alu", "achieved": plain_ach,
+                                   "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": plain_ach / PEAK_FP64_VECTOR_TFLOPS},
+            "kernel_times_ms": kt_plain,
+            "steps_per_flow_step": {"total_rk_steps": int(per_cell.sum()),
+                                    "rejected": int(plain_counts[1].sum()),
+                                    "max_per_cell": int(per_cell.max())},
+            "flops_per_rk_step": flops_per_step},
+        "launch": launch,
+        "trust": {"hull_margin": trust[0], "elem_tol": trust[1], "pos_tol": trust[2],
+                  "energy_tol_K": trust[3], "validation": tstats},
+        "trusted_error_vs_fp64": {"max_rel_T": float(eT.max()), "p999_rel_T": q(eT),
+                                  "max_abs_Y": float(eY.max()), "p999_abs_Y": q(eY),
+                                  "negative_Y_entries": neg},
+        "fallback_cells_max_diff_vs_plain": {"rel_T": float(fT.max()) if fb.any() else 0.0,
+                                             "abs_Y": float(fY.max()) if fb.any() else 0.0},
+        "train": {"pairs": n_pairs, "epochs": args.surrogate_epochs, "batch": 4096,
+                  "first_loss": float(loss[0]), "final_loss": float(loss[-1]),
+                  "data_s": t_data, "train_s": t_train,
+                  "achieved_tflops": train_flops / t_train / 1e12},
+    }
+    # strata for the CPU baseline: trajectory states, cold and hot front states
+    T = field[0]
+    strata_masks = [("trajectory states", ~out_mask), ("front states, cold", out_mask & (T < 1000.0)),
+                    ("front states, hot", out_mask & (T >= 1000.0))]
+    rng = np.random.Generator(np.random.PCG64(321))
+    strata = []
+    for name, mk in strata_masks:
+        idx_all = torch.nonzero(mk).flatten()
+        cnt = int(idx_all.numel())
+        k = min(cnt, 65536) if "hot" in name else max(1, cnt // 100)
+        pick = torch.from_numpy(np.sort(rng.choice(cnt, k, replace=False))).cuda()
+        st = field[:, idx_all[pick]].cpu().numpy()
+        strata.append((name, cnt, np.ascontiguousarray(st), wl.DT_FLOW, 1))
+    del work, ref, field
+    s.close()
+    m.close()
+    torch.cuda.empty_cache()
+    return res, strata, path
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: the chemistry path runs on one GPU (asked for --gpus {args.gpus}); "
+              "the chemistry step needs no cross-GPU exchange, see the design notes",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch  # noqa: F401
+    host = host_info()
+    threads = oracle_threads(host, args.cpu_threads)
+    build = None if args.no_cpu else native_oracle()
+    out = {"metric": METRIC, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "surrogate256":
+        res, strata, path = surrogate_field(args)
+        out.update({"value": res["value"], "ms_per_step": res["ms_per_step"],
+                    "dtype": "f64+bf16",
+                    "config": {"workload": WORKLOADS["surrogate256"], "name": "surrogate256",
+                               "cells": res["cells"], "path": "surrogate+fallback",
+                               "launch": res["launch"]},
+                    "roofline": res["roofline"]})
+        out["surrogate_fallback"] = {k: v for k, v in res.items()
+                                     if k not in ("plain_fp64", "roofline")}
+        out["plain_fp64"] = res["plain_fp64"]
+        if not args.no_cpu:
+            log(f"oracle on {threads} host threads (stratified sample of the 256^3 field)")
+            out["cpu_baseline"] = cpu_baseline_strata(path, strata, threads, build, host)
+        if not args.no_front:
+            log("front field")
+            out["front"] = measure_boxes(args, "front")
+    else:
+        path, hboxes = load_workload(args.workload)
+        res = measure_boxes(args, args.workload, hboxes, path)
+        out.update({"value": res["value"], "ms_per_step": res["ms_per_step"],
+                    "dtype": "f64",
+                    "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
+                               "cells": res["cells"], "boxes": res["boxes"],
+                               "scheme": res["scheme"], "autotuned": res["autotuned"]},
+                    "roofline": res["roofline"]})
+        out["detail"] = {k: v for k, v in res.items() if k != "roofline"}
+        if not args.no_cpu:
+            log(f"oracle on {threads} host threads")
+            out["cpu_baseline"] = cpu_baseline_boxes(hboxes, path, threads, build, host)
     print(json.dumps(out), flush=True)
 
 
