@@ -21,7 +21,7 @@
  * Handles are not thread-safe; calls on one handle must not overlap.
  *
  * Device memory: the integration calls (chem_integrate, chem_integrate_batched,
- * chem_react_conserved, surrogate_infer) allocate
+ * chem_react_conserved, surrogate_infer, chem_integrate_noalloc) allocate
  * nothing and never synchronise the device (chem_integrate_batched's host
  * wait on its staging ring is described there).  Their workspace is
  * allocated up front by chem_workspace_reserve (and surrogate_reserve); a
@@ -113,8 +113,9 @@ typedef struct {
  * generated for it at build time, keyed by the FNV-1a 64 hash of the file's
  * bytes.  *out receives a handle to free with chem_mech_free.  The handle
  * belongs to the device current at this call (every later call on it must
- * run with that device current).  Allocates no device memory (see
- * chem_workspace_reserve). */
+ * run with that device current); the first load on a device also looks up
+ * that device's address of chem_integrate_noalloc's scratch array.  Allocates
+ * no device memory (see chem_workspace_reserve). */
 int chem_mech_load(const char *path, chem_mech *out);
 
 /* Species count N, reaction count and content hash of a loaded mechanism. */
@@ -145,7 +146,7 @@ int chem_workspace_reserve(chem_mech m, int64_t max_cells);
  * call on m records HIP events on its stream around each launch of the flow
  * step, and so does surrogate_infer with fallback around the FP64 run of the
  * cells outside the training hull, on its side stream (creating the events
- * on first use; captured graphs are not timed);
+ * on first use; captured graphs and chem_integrate_noalloc are not timed);
  * on == 0 stops it.  chem_kernel_times then waits for the last such call and
  * writes n >= 4 durations in ms: [0] the persistent per-lane kernel, [1] the
  * tail-list sort, [2] the cooperative kernel, [3] the per-lane resumption of
@@ -166,6 +167,23 @@ int chem_kernel_times(chem_mech m, float *ms, int32_t n);
  */
 int chem_integrate(chem_mech m, double *state, int64_t ld, int64_t n_cells, double dt,
                    const chem_opts *opts, void *stream, int32_t *status, int32_t *counts);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * flow step as chem_integrate, same arguments, results and per-cell outputs,
+ * bitwise equal, with no allocation and no workspace reservation.  Its
+ * scratch memory (work-pool counter, tail records, pool order) is a fixed
+ * device array inside the library, one copy per GPU, sized for at most
+ * 1,048,576 cells (46 MB, held from the first chem_mech_load on that GPU
+ * until the process ends); CHEM_ECAPACITY for more cells.  Every call on one
+ * GPU shares that array, whatever the handle: calls that overlap on one GPU
+ * (two streams, or two host threads) race and give wrong results.  Each call
+ * clears the counters it uses (kernels, no memset) before its integration.
+ * Enqueued on `stream`; no host synchronisation.
+ */
+int chem_integrate_noalloc(chem_mech m, double *state, int64_t ld, int64_t n_cells, double dt,
+                           const chem_opts *opts, void *stream, int32_t *status, int32_t *counts);
 
 /*
  * The reaction step of an operator-split flow solver (paper Sec. 2.2.1: the

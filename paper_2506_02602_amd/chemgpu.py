@@ -191,6 +191,30 @@ def chem_integrate(mech: Mechanism, state, dt: float, opts: chem_opts | None = N
                                _stream(stream), _ptr(status), _ptr(counts)), "chem_integrate")
 
 
+_lib.chem_integrate_noalloc.argtypes = [_P, _P, C.c_int64, C.c_int64, C.c_double,
+                                        C.POINTER(chem_opts), _P, _P, _P]
+_lib.chem_integrate_noalloc.restype = C.c_int
+NOALLOC_MAX_CELLS = 1 << 20
+
+
+def chem_integrate_noalloc(mech: Mechanism, state, dt: float, opts: chem_opts | None = None,
+                           stream=None, status=None, counts=None, n_cells=None) -> None:
+    """As chem_integrate, on the library's fixed scratch array (no workspace,
+    no allocation; at most NOALLOC_MAX_CELLS cells; calls overlapping on one
+    GPU race)."""
+    ld = state.shape[1]
+    n = ld if n_cells is None else int(n_cells)
+    assert state.dtype.itemsize == 8 and state.is_contiguous() and state.shape[0] == mech.n_species + 3
+    if status is not None:
+        assert status.numel() >= n and status.element_size() == 4
+    if counts is not None:
+        assert counts.numel() >= 2 * n and counts.element_size() == 4
+    o = opts if opts is not None else make_opts()
+    _check(_lib.chem_integrate_noalloc(mech.handle, _ptr(state), ld, n, float(dt), C.byref(o),
+                                       _stream(stream), _ptr(status), _ptr(counts)),
+           "chem_integrate_noalloc")
+
+
 _lib.surrogate_create.argtypes = [_P, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_P)]
 _lib.surrogate_query.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
 _lib.surrogate_get_params.argtypes = [_P, _P, _P]
@@ -470,4 +494,5 @@ def exported_symbols():
             "surrogate_set_params", "surrogate_make_pairs", "surrogate_train", "surrogate_forward",
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
             "surrogate_free", "chem_eval_exp", "chem_eval_math", "chem_react_conserved",
-            "chem_set_kernel_timing", "chem_kernel_times", "surrogate_reserve"]
+            "chem_set_kernel_timing", "chem_kernel_times", "surrogate_reserve",
+            "chem_integrate_noalloc"]

@@ -736,6 +736,32 @@ struct OrderStore {
 constexpr int kMaxBoxes = 4096;
 constexpr int kBoxRing = 4;
 
+namespace {
+
+// Scratch memory of chem_integrate_noalloc: the pool counter, the tail
+// records and the pool order of one call on up to kNoAllocMaxCells cells, in
+// a fixed device array (one copy per GPU, held until the process ends).
+// Host code never passes `scratch` itself to a kernel or a copy: the array's
+// device address comes from hipGetSymbolAddress, once per device, at the
+// first chem_mech_load on that device (g_scratch_ptr).
+constexpr int64_t kNoAllocMaxCells = int64_t(1) << 20;
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kScratchTailOff = 256;
+constexpr size_t kScratchOrderOff = kScratchTailOff + round256(TailStore::bytes(kNoAllocMaxCells));
+constexpr size_t kScratchBytes = kScratchOrderOff + round256(OrderStore::bytes(kNoAllocMaxCells));
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
 struct chem_mech_s {
   const MechEntry* entry;
   TailStore tail;
@@ -754,6 +780,7 @@ struct chem_mech_s {
   int8_t* d_flag = nullptr;
   int device = 0;
   int n_cu = 0;
+  void* scratch = nullptr;         // this device's copy of `scratch` (chem_integrate_noalloc)
   // optional per-kernel timing of plain (not captured) calls: events around
   // the persistent launch, the tail sort, the cooperative launch and the
   // resumption launch of the last call
@@ -1180,6 +1207,25 @@ int chem_mech_load(const char* path, chem_mech* out) {
   if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
   e = hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
   if (e != hipSuccess) { delete m; return hip_fail(e, "hipDeviceGetAttribute"); }
+  if (m->device < 0 || m->device >= kMaxDevices) {
+    delete m;
+    return fail(CHEM_EUNSUPPORTED, "chem_mech_load: device ordinal beyond 63");
+  }
+  {
+    // this device's address of the no-allocation scratch array, looked up
+    // once per device with that device current
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[m->device]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        delete m;
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+      }
+      g_scratch_ptr[m->device] = ptr;
+    }
+    m->scratch = g_scratch_ptr[m->device];
+  }
   *out = m;
   return CHEM_OK;
 }
@@ -1288,6 +1334,52 @@ int chem_integrate(chem_mech m, double* state, int64_t ld, int64_t n_cells, doub
     return CHEM_OK;
   }
   return run_pool(m, a, opts, s);
+}
+
+int chem_integrate_noalloc(chem_mech m, double* state, int64_t ld, int64_t n_cells, double dt,
+                           const chem_opts* opts, void* stream, int32_t* status, int32_t* counts) {
+  if (!m) return fail(CHEM_EINVAL, "chem_integrate_noalloc: null mechanism");
+  if (n_cells < 0 || ld < n_cells)
+    return fail(CHEM_EINVAL, "chem_integrate_noalloc: need 0 <= n_cells <= ld");
+  if (!(dt > 0) || !std::isfinite(dt))
+    return fail(CHEM_EINVAL, "chem_integrate_noalloc: dt must be finite and > 0");
+  if (n_cells > 0 && !state) return fail(CHEM_EINVAL, "chem_integrate_noalloc: null state");
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (n_cells > kNoAllocMaxCells)
+    return fail(CHEM_ECAPACITY, "chem_integrate_noalloc: more than 1048576 cells");
+  if (n_cells == 0) return CHEM_OK;
+  if (!m->scratch) return fail(CHEM_EHIP, "chem_integrate_noalloc: no scratch address for this device");
+  hipStream_t s = (hipStream_t)stream;
+  PoolArgs a{};
+  a.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts, nullptr};
+  a.boxes = nullptr;
+  a.n_boxes = 1;
+  a.total = n_cells;
+  a.c = make_control(opts);
+  a.fixed_steps = opts ? opts->fixed_steps : 0;
+  a.scheme = opts ? opts->scheme : SCHEME_LSRK;
+  int block, chunk;
+  pick_launch(m, n_cells, opts, &block, &chunk);
+  if (chunk < 0) {
+    rc = check_scheme_launch(m, opts, block);
+    if (rc) return rc;
+    hipError_t e = m->entry->launch_direct(a, block, s);
+    if (e != hipSuccess) return hip_fail(e, "launch lsrk_direct");
+    return CHEM_OK;
+  }
+  // the same kernels as chem_integrate, on this device's scratch array: the
+  // pool counter at its start, then the tail records and the pool order
+  // (every counter is cleared by a kernel at the start of the call)
+  unsigned char* base = static_cast<unsigned char*>(m->scratch);
+  TailStore ts;
+  ts.mem = base + kScratchTailOff;
+  ts.cap = kNoAllocMaxCells;
+  OrderStore os;
+  os.mem = base + kScratchOrderOff;
+  os.cap = kNoAllocMaxCells;
+  return run_pool_with(m, a, opts, s, reinterpret_cast<unsigned long long*>(base), ts, &os,
+                       false);
 }
 
 int chem_react_conserved(chem_mech m, double* cons, int64_t ld, int64_t n_cells, double dt,
