@@ -92,6 +92,10 @@ def parse():
     ap.add_argument("--no-front", action="store_true",
                     help="with the surrogate field as headline, skip the front-field leg")
     ap.add_argument("--surrogate-epochs", type=int, default=12)
+    ap.add_argument("--surrogate-file", default="",
+                    help="if the file exists, load the trained surrogate and its trust "
+                         "thresholds from it (and FILE.trust.json) instead of training; "
+                         "otherwise train and save there (for profiling runs)")
     return ap.parse_args()
 
 
@@ -458,24 +462,41 @@ def surrogate_field(args):
     from paper_2506_02602_amd import chemgpu as cg, codegen, surrogate as sg, workloads as wl
     path = wl.mech_file("mech9")
     m = cg.chem_mech_load(path)
-    t0 = time.perf_counter()
-    ds = sg.build_dataset(m)
-    t_data = time.perf_counter() - t0
-    n_pairs = int(ds["X"].shape[0])
-    log(f"surrogate: {n_pairs} training pairs in {t_data:.1f} s; training")
-    s = cg.Surrogate(m, seed=11)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss = cg.surrogate_train(s, ds["X"], ds["Y"], epochs=args.surrogate_epochs, batch=4096,
-                              lr=3e-3, seed=2)
-    t_train = time.perf_counter() - t0
-    train_flops = 3.0 * SURROGATE_FLOPS_PER_CELL * (n_pairs // 4096) * 4096 * args.surrogate_epochs
-    log("surrogate: tuning trust thresholds")
-    trust, tstats = sg.tune_trust(s, m, sg.validation_states(ds))
-    if trust is None:
-        trust = (0.0, 1e-6, 1e-7, 0.05)
-    del ds
-    torch.cuda.empty_cache()
+    sfile = args.surrogate_file
+    if sfile and os.path.exists(sfile):
+        s = cg.surrogate_load(m, sfile)
+        with open(sfile + ".trust.json") as f:
+            saved = json.load(f)
+        trust, tstats, train_rec = tuple(saved["trust"]), saved["validation"], saved["train"]
+        log(f"surrogate: loaded from {sfile}")
+    else:
+        t0 = time.perf_counter()
+        ds = sg.build_dataset(m)
+        t_data = time.perf_counter() - t0
+        n_pairs = int(ds["X"].shape[0])
+        log(f"surrogate: {n_pairs} training pairs in {t_data:.1f} s; training")
+        s = cg.Surrogate(m, seed=11)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = cg.surrogate_train(s, ds["X"], ds["Y"], epochs=args.surrogate_epochs, batch=4096,
+                                  lr=3e-3, seed=2)
+        t_train = time.perf_counter() - t0
+        train_flops = (3.0 * SURROGATE_FLOPS_PER_CELL * (n_pairs // 4096) * 4096 *
+                       args.surrogate_epochs)
+        log("surrogate: tuning trust thresholds")
+        trust, tstats = sg.tune_trust(s, m, sg.validation_states(ds))
+        if trust is None:
+            trust = (0.0, 1e-6, 1e-7, 0.05)
+        train_rec = {"pairs": n_pairs, "epochs": args.surrogate_epochs, "batch": 4096,
+                     "first_loss": float(loss[0]), "final_loss": float(loss[-1]),
+                     "data_s": t_data, "train_s": t_train,
+                     "achieved_tflops": train_flops / t_train / 1e12}
+        if sfile:
+            cg.surrogate_save(s, sfile)
+            with open(sfile + ".trust.json", "w") as f:
+                json.dump({"trust": list(trust), "validation": tstats, "train": train_rec}, f)
+        del ds
+        torch.cuda.empty_cache()
     log("surrogate: building the 256^3 evaluation field")
     field, out_mask = sg.inference_field(m)
     n = field.shape[1]
@@ -617,10 +638,7 @@ def surrogate_field(args):
                                   "negative_Y_entries": neg},
         "fallback_cells_max_diff_vs_plain": {"rel_T": float(fT.max()) if fb.any() else 0.0,
                                              "abs_Y": float(fY.max()) if fb.any() else 0.0},
-        "train": {"pairs": n_pairs, "epochs": args.surrogate_epochs, "batch": 4096,
-                  "first_loss": float(loss[0]), "final_loss": float(loss[-1]),
-                  "data_s": t_data, "train_s": t_train,
-                  "achieved_tflops": train_flops / t_train / 1e12},
+        "train": train_rec,
     }
     # strata for the CPU baseline: trajectory states, cold and hot front states
     T = field[0]
