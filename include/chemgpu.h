@@ -406,7 +406,7 @@ const char *chem_last_error(void);
 
 /* Diagnostics: y[i] = e^x[i] for i < n (device arrays, caller-owned), with
  * the exponential the rate evaluation uses (Cody-Waite reduction and a
- * degree-13 polynomial; within 1 ulp of the correctly rounded value), so it
+ * degree-11 Chebyshev polynomial; within 1 ulp of the correctly rounded value), so it
  * can be checked against a reference.  Enqueued on `stream`. */
 int chem_eval_exp(const double *x, double *y, int64_t n, void *stream);
 

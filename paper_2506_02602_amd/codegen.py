@@ -11,9 +11,19 @@ parameter and NASA-7 coefficient is a literal:
   coefficient from a scalar register; a Horner chain costs two vector moves
   per coefficient for its accumulator), with a wave-coherent branch on
   T < Tmid (one branch per distinct Tmid);
-* forward rate k_f = exp(ln A + b ln T - Ea/(R T)), reverse rate
-  k_r = k_f / K_c computed as exp(ln k_f + sum_k nu_k g_k/RT - dnu ln(P/(R T)))
-  (the exponential is the device's own ``exp_cw``, within 1 ulp);
+* forward rate k_f = exp(ln A + b ln T - Ea/(R T)); reverse rate
+  k_r = k_f / K_c = k_f prod_k exp(g_k/RT)^nu_k (R T/P)^dnu, from one
+  exponential per species, E_k = exp(g_k/RT), and its reciprocal, shared by
+  every reaction (N exponentials instead of one per reaction); the factors
+  of each reaction are multiplied in an order whose partial products stay
+  within the double range for every T from 200 K to 6000 K, checked here
+  on the NASA-7 fits; a reaction for which no such order is found keeps
+  exp(ln k_f + sum_k nu_k g_k/RT - dnu ln(P/(R T))).  The choice is made
+  per reaction at build time, so every lane runs the same arithmetic
+  whatever its neighbours hold.  Below 200 K (outside the fits' validity)
+  a factorised product may overflow: the step then has a non-finite error
+  and is rejected (the exponential is the device's own ``exp_cw``, within
+  1 ulp);
 * progress q_j = [M]_j (k_f prod c^nu' - k_r prod c^nu''), integer powers as
   products; production rates accumulated straight into N registers;
 * dY_k/dt = W_k wdot_k / rho and the constant-volume adiabatic dT/dt.
@@ -168,11 +178,148 @@ def _thermo(species):
     return L
 
 
+# Lowest temperature for which the factorised reverse rates are range-checked.
+T_FACTOR_MIN = 200.0
+# Largest |ln| a partial product of a reverse rate may reach (the double
+# range ends near e^709).
+LN_PARTIAL_MAX = 650.0
+
+
+def _g_rt(s: dict, T: float) -> float:
+    """g/RT of one species from its NASA-7 fit (the range T < Tmid is low)."""
+    a = s["lo"] if T < s["Tmid"] else s["hi"]
+    return (a[0] * (1.0 - math.log(T)) - (a[1] * T / 2 + a[2] * T * T / 6 + a[3] * T ** 3 / 12 +
+                                          a[4] * T ** 4 / 20) + a[5] / T - a[6])
+
+
+def _check_temperatures(m: dict) -> list:
+    """T grid for the range check: log-spaced over [T_FACTOR_MIN, 6000 K] plus
+    both sides of every NASA-7 range switch."""
+    ts = list(T_FACTOR_MIN * (6000.0 / T_FACTOR_MIN) ** (i / 400.0) for i in range(401))
+    for sp in m["species"]:
+        ts += [sp["Tmid"] * (1 - 1e-9), sp["Tmid"] * (1 + 1e-9)]
+    return sorted(ts)
+
+
+def _nu(rx: dict) -> dict:
+    nu = {}
+    for k, v in rx["reac"].items():
+        nu[k] = nu.get(k, 0) - v
+    for k, v in rx["prod"].items():
+        nu[k] = nu.get(k, 0) + v
+    return {k: v for k, v in nu.items() if v != 0}
+
+
+def _chain(start: list, factors: list, ts: list):
+    """Greedy multiplication order of `factors` (C name, per-T ln function)
+    onto a running product whose ln is `start` on the grid `ts`: at each step
+    the factor that keeps the running ln nearest zero at the grid's coldest
+    point (the largest magnitudes).  None if a partial product leaves
+    e^+-LN_PARTIAL_MAX anywhere on the grid."""
+    order, run, rest = [], list(start), list(factors)
+    while rest:
+        j = min(range(len(rest)), key=lambda i: abs(run[0] + rest[i][1](ts[0])))
+        f = rest.pop(j)
+        run = [r + f[1](T) for r, T in zip(run, ts)]
+        if max(abs(r) for r in run) > LN_PARTIAL_MAX:
+            return None
+        order.append(f[0])
+    return order
+
+
+def _reverse_factors(m: dict, rx: dict, inverses: bool):
+    """The factors of k_r = k_f prod_k E_k^nu_k (RT/P)^dnu, E_k = exp(g_k/RT),
+    in multiplication orders whose partial products stay within
+    e^+-LN_PARTIAL_MAX on the check grid; None if none passes.  With
+    `inverses` the factors of species with nu_k < 0 are reciprocals Ei_k
+    (shared, one per species) and the result is one product chain [names];
+    without, those factors form a second chain and k_r = first * rcp(second):
+    (names, names)."""
+    sp = m["species"]
+    lnP = math.log(m["pstd"] / R_CGS)
+    ts = _check_temperatures(m)
+    lkf = [math.log(rx["A"]) + rx["b"] * math.log(T) - rx["Ea"] / (R_J * T) for T in ts]
+    num, den = [], []
+    for k, v in sorted(_nu(rx).items()):
+        if v > 0:
+            num += [(f"E{k}", (lambda T, k=k: _g_rt(sp[k], T)))] * v
+        elif inverses:
+            num += [(f"Ei{k}", (lambda T, k=k: -_g_rt(sp[k], T)))] * (-v)
+        else:
+            den += [(f"E{k}", (lambda T, k=k: _g_rt(sp[k], T)))] * (-v)
+    dnu = sum(_nu(rx).values())
+    if dnu:
+        # (RT/P)^dnu: RTP = RT/P for dnu > 0, PRT = P/RT for dnu < 0
+        name, sign = ("RTP", -1.0) if dnu > 0 else ("PRT", 1.0)
+        num += [(name, (lambda T, sg=sign: sg * (lnP - math.log(T))))] * abs(dnu)
+    a = _chain(lkf, num, ts)
+    if inverses:
+        return a
+    b = _chain([0.0] * len(ts), den, ts) if den else []
+    return None if a is None or b is None else (a, b)
+
+
+# Mechanisms with more species than this keep only E_k live through the
+# reaction section and divide once per reaction (register pressure); smaller
+# ones also keep the reciprocals Ei_k and only multiply.
+FACTOR_INVERSES_MAX_N = 16
+
+
 def _prod_expr(coef: str, side: dict) -> str:
     terms = [coef]
     for k, nu in sorted(side.items()):
         terms += [f"c{k}"] * nu
     return " * ".join(terms)
+
+
+def _rate_lines(m: dict, orders: list) -> list:
+    """Rates of progress and their accumulation into w_k; reaction j's k_r
+    from its factor order (see _reverse_factors), or through its own
+    exponential when orders[j] is None."""
+    L = []
+    for j, rx in enumerate(m["reactions"]):
+        L.append(f"    {{  // reaction {j}")
+        e = [lit(math.log(rx["A"]))]
+        if rx["b"] != 0.0:
+            e.append(f"{lit(rx['b'])} * lnT")
+        if rx["Ea"] != 0.0:
+            e.append(f"- {lit(rx['Ea'] / R_J)} * invT")
+        L.append(f"      const double lkf = {' + '.join(e).replace('+ -', '-')};")
+        L.append("      const double kf = exp_cw(lkf);")
+        nu = _nu(rx)
+        dnu = sum(nu.values())
+        if isinstance(orders[j], tuple):
+            num, den = orders[j]
+            d = f" * rcp_nr({' * '.join(den)})" if den else ""
+            L.append(f"      const double kr = {' * '.join(['kf'] + num)}{d};")
+        elif orders[j] is not None:
+            L.append(f"      const double kr = {' * '.join(['kf'] + orders[j])};")
+        else:
+            gterms = []
+            for k, v in sorted(nu.items()):
+                sign = "+" if v > 0 else "-"
+                mag = abs(v)
+                gterms.append(f" {sign} {'' if mag == 1 else lit(float(mag)) + ' * '}g{k}")
+            if dnu != 0:
+                sign = "-" if dnu > 0 else "+"
+                mag = abs(dnu)
+                gterms.append(f" {sign} {'' if mag == 1 else lit(float(mag)) + ' * '}lnPRT")
+            L.append(f"      const double kr = exp_cw(lkf{''.join(gterms)});")
+        q = f"{_prod_expr('kf', rx['reac'])} - {_prod_expr('kr', rx['prod'])}"
+        if rx["tb"]:
+            mt = " + ".join(f"{lit(a)} * c{k}" for k, a in enumerate(rx["eff"]))
+            L.append(f"      const double q = ({mt}) * ({q});")
+        else:
+            L.append(f"      const double q = {q};")
+        for k, v in sorted(nu.items()):
+            if v == 1:
+                L.append(f"      w{k} += q;")
+            elif v == -1:
+                L.append(f"      w{k} -= q;")
+            else:
+                L.append(f"      w{k} += {lit(float(v))} * q;")
+        L.append("    }")
+    return L
 
 
 def gen_rhs(m: dict) -> str:
@@ -197,49 +344,20 @@ def gen_rhs(m: dict) -> str:
     L.append("    double den = 0.0;  // sum_k c_k (cp_k/R - 1)")
     L += _thermo(sp)
     L.append("    double " + ", ".join(f"w{k} = 0.0" for k in range(N)) + ";")
-    for j, rx in enumerate(m["reactions"]):
-        L.append(f"    {{  // reaction {j}")
-        e = [lit(math.log(rx["A"]))]
-        if rx["b"] != 0.0:
-            e.append(f"{lit(rx['b'])} * lnT")
-        if rx["Ea"] != 0.0:
-            e.append(f"- {lit(rx['Ea'] / R_J)} * invT")
-        L.append(f"      const double lkf = {' + '.join(e).replace('+ -', '-')};")
-        L.append("      const double kf = exp_cw(lkf);")
-        nu = {}
-        for k, v in rx["reac"].items():
-            nu[k] = nu.get(k, 0) - v
-        for k, v in rx["prod"].items():
-            nu[k] = nu.get(k, 0) + v
-        dnu = sum(nu.values())
-        gterms = []
-        for k, v in sorted(nu.items()):
-            if v == 0:
-                continue
-            sign = "+" if v > 0 else "-"
-            mag = abs(v)
-            gterms.append(f" {sign} {'' if mag == 1 else lit(float(mag)) + ' * '}g{k}")
-        if dnu != 0:
-            sign = "-" if dnu > 0 else "+"
-            mag = abs(dnu)
-            gterms.append(f" {sign} {'' if mag == 1 else lit(float(mag)) + ' * '}lnPRT")
-        L.append(f"      const double kr = exp_cw(lkf{''.join(gterms)});")
-        q = f"{_prod_expr('kf', rx['reac'])} - {_prod_expr('kr', rx['prod'])}"
-        if rx["tb"]:
-            mt = " + ".join(f"{lit(a)} * c{k}" for k, a in enumerate(rx["eff"]))
-            L.append(f"      const double q = ({mt}) * ({q});")
-        else:
-            L.append(f"      const double q = {q};")
-        for k, v in sorted(nu.items()):
-            if v == 0:
-                continue
-            if v == 1:
-                L.append(f"      w{k} += q;")
-            elif v == -1:
-                L.append(f"      w{k} -= q;")
-            else:
-                L.append(f"      w{k} += {lit(float(v))} * q;")
-        L.append("    }")
+    inv = N <= FACTOR_INVERSES_MAX_N
+    orders = [_reverse_factors(m, rx, inv) for rx in m["reactions"]]
+    need = sorted({f for o in orders if o for f in (o if inv else o[0] + o[1])})
+    for k in range(N):
+        if f"E{k}" in need or f"Ei{k}" in need:
+            L.append(f"    const double E{k} = exp_cw(g{k});")
+        if f"Ei{k}" in need:
+            L.append(f"    const double Ei{k} = rcp_nr(E{k});")
+    C = m["pstd"] / R_CGS
+    if "PRT" in need:
+        L.append(f"    const double PRT = {lit(C)} * invT;")
+    if "RTP" in need:
+        L.append(f"    const double RTP = {lit(1.0 / C)} * T;")
+    L += _rate_lines(m, orders)
     num = " + ".join(f"(h{k} - 1.0) * w{k}" for k in range(N))
     L.append(f"    const double num = {num};")
     L.append("    f[0] = -T * num * rcp_nr(den);")
@@ -570,9 +688,13 @@ def gen_coop(m: dict, tag: str) -> tuple[str, str]:
 
 
 def op_counts(m: dict) -> dict:
-    """Algorithmic FP64 operation counts of one RHS evaluation as generated.
+    """Algorithmic FP64 operation counts of one RHS evaluation: the method's
+    arithmetic as the paper states it, with k_f and k_r = k_f / K_c each
+    through an exponential per reaction (the generated code evaluates K_c
+    from N shared per-species exponentials instead, which changes the
+    instruction count, not this figure).
 
-    Counted per the expressions above (FMA-able pairs count as 2 flops):
+    Counted per expression (FMA-able pairs count as 2 flops):
     thermo 13 FMA + 4 mul/add per species (one range), concentrations 2 mul,
     per reaction: lkf (up to 2 FMA), kr exponent (1 add per nu term), products,
     third-body sum (1 FMA per species), accumulation (1 add per nu term),
