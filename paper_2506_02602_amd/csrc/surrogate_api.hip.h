@@ -208,7 +208,7 @@ int surrogate_create(chem_mech mech, int32_t hidden, int32_t depth, uint64_t see
   A(dalloc(&s->theta, s->P)); A(dalloc(&s->m, s->P)); A(dalloc(&s->v, s->P));
   A(dalloc(&s->grad, s->P)); A(dalloc(&s->wbf, s->P));
   A(dalloc(&s->norm, 4L * s->ni + 2L * s->no));
-  A(dalloc(&s->wpack, H * kc1 * 32 + 2 * H * H + (long)ot4 * 16 * H));
+  A(dalloc(&s->wpack, surr::packed_weight_elems(kc1, ot4)));
   A(dalloc(&s->bpack, 3 * H + ot4 * 16));
   A(dalloc(&s->sse, 1));
   A(dalloc(&s->fb_count, 1));
@@ -541,8 +541,7 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
       if (rc) return rc;
       if ((e = hipEventRecord(s->ev_join, s->side)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    const int grid = std::max(1, std::min<int>((int)((n_cells + 511) / 512), m->n_cu));
-    e = m->entry->launch_surr_infer(a, grid, st);
+    e = m->entry->launch_surr_infer(a, m->n_cu, st);
     if (e != hipSuccess) return hip_fail(e, "launch surr_infer");
     if (fallback) {
       PoolArgs pa = fallback_args(s->fb_list, s->fb_count);

@@ -252,25 +252,40 @@ __device__ __forceinline__ int packed_feature(int c) {
   return 32 * kc + (j < 4 ? 4 * gg + j : 16 + 4 * gg + (j - 4));
 }
 
-// theta (FP32 master, natural layout) -> BF16 packed weights + FP32 biases
+// Row strides (in BF16 elements) of the packed weights as they sit in LDS:
+// each row is padded by one 16-byte chunk to an odd number of chunks, so
+// the 16 rows that a wave's 16-byte operand reads touch (r16 = 0..15, one
+// chunk each) start on 16 different bank groups: no bank conflicts,
+// whether the LDS serves 8 or 16 such reads per clock.
+constexpr int kRowPad = 8;
+__host__ __device__ constexpr int w1_ld(int kc1) { return kc1 * 32 + kRowPad; }
+constexpr int kWLd = HID + kRowPad;
+__host__ __device__ constexpr long packed_weight_elems(int kc1, int ot4) {
+  return (long)HID * w1_ld(kc1) + 2L * HID * kWLd + (long)ot4 * 16 * kWLd;
+}
+
+// theta (FP32 master, natural layout) -> BF16 packed weights (padded rows,
+// padding zero) + FP32 biases
 __global__ void pack_weights(const float* theta, int ni, int no, int kc1, int ot4,
                              unsigned short* wp, float* bp) {
-  const long w1 = (long)HID * kc1 * 32, w2 = (long)HID * HID, w4 = (long)ot4 * 16 * HID;
+  const int l1 = w1_ld(kc1);
+  const long w1 = (long)HID * l1, w2 = (long)HID * kWLd, w4 = (long)ot4 * 16 * kWLd;
   const long oW1 = 0, ob1 = (long)HID * ni, oW2 = ob1 + HID, ob2 = oW2 + (long)HID * HID;
   const long oW3 = ob2 + HID, ob3 = oW3 + (long)HID * HID, oW4 = ob3 + HID, ob4 = oW4 + (long)no * HID;
   const long total = w1 + 2 * w2 + w4 + 3 * HID + ot4 * 16;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (long)gridDim.x * blockDim.x) {
     if (i < w1) {
-      const long row = i / (kc1 * 32), k = i % (kc1 * 32);
+      const long row = i / l1, k = i % l1;
       wp[i] = k < ni ? f2bf(theta[oW1 + row * ni + k]) : (unsigned short)0;
     } else if (i < w1 + 2 * w2) {
-      const long j = i - w1, which = j / w2, jj = j % w2, row = jj / HID, c = jj % HID;
+      const long j = i - w1, which = j / w2, jj = j % w2, row = jj / kWLd, c = jj % kWLd;
       const long base = which == 0 ? oW2 : oW3;
-      wp[i] = f2bf(theta[base + row * HID + packed_feature((int)c)]);
+      wp[i] = c < HID ? f2bf(theta[base + row * HID + packed_feature((int)c)]) : (unsigned short)0;
     } else if (i < w1 + 2 * w2 + w4) {
-      const long jj = i - w1 - 2 * w2, row = jj / HID, c = jj % HID;
-      wp[i] = row < no ? f2bf(theta[oW4 + row * HID + packed_feature((int)c)]) : (unsigned short)0;
+      const long jj = i - w1 - 2 * w2, row = jj / kWLd, c = jj % kWLd;
+      wp[i] = row < no && c < HID ? f2bf(theta[oW4 + row * HID + packed_feature((int)c)])
+                                  : (unsigned short)0;
     } else {
       const long b = i - (w1 + 2 * w2 + w4);
       float v;
@@ -295,19 +310,32 @@ struct InferArgs {
 
 enum { TRUST_HULL = 1, TRUST_ELEM = 2, TRUST_POS = 4, TRUST_ENERGY = 8, TRUST_NONFINITE = 16 };
 
+// LDS of one inference block: the packed weights and biases (shared), then
+// one staging area per wave with one row per cell of the wave's 64: first
+// the cell's BF16 features, later (once they are in registers) its FP32
+// network outputs.  The row length CELL_B is an odd number of 16-byte
+// chunks, so the 16-byte reads and writes of 16 consecutive cells fall on
+// distinct banks.  The MLP runs on the 64 cells in two halves of 32, which
+// halves the accumulator registers (64 per lane instead of 128) at the
+// price of reading every weight twice per tile; with the lower register
+// count three waves share each SIMD instead of two.
 template <class M>
 struct InferShape {
   static constexpr int NS = M::NS, NI = NS + 3, NO = NS + 1;
   static constexpr int KC1 = (NI + 31) / 32, OT4 = (NO + 15) / 16;
-  static constexpr int WAVES = NS <= 15 ? 8 : 4, THREADS = WAVES * 64;
-  static constexpr long W1 = (long)HID * KC1 * 32, W2 = (long)HID * HID, W4 = (long)OT4 * 16 * HID;
+  static constexpr int W1_LD = w1_ld(KC1);
+  static constexpr long W1 = (long)HID * W1_LD, W2 = (long)HID * kWLd, W4 = (long)OT4 * 16 * kWLd;
   static constexpr long WTOT = W1 + 2 * W2 + W4;
   static constexpr long BTOT = 3 * HID + OT4 * 16;
-  static constexpr long F_WAVE = (long)KC1 * 32 * 64 * 2;        // bytes per wave
-  static constexpr long O_WAVE = (long)OT4 * 16 * 64 * 4;
+  static constexpr int F_CHUNKS = KC1 * 4, O_CHUNKS = OT4 * 4;     // 16-byte chunks per cell
+  static constexpr int CELL_CHUNKS = (F_CHUNKS > O_CHUNKS ? F_CHUNKS : O_CHUNKS) | 1;
+  static constexpr int CELL_B = CELL_CHUNKS * 16;
+  static constexpr long STAGE = 64L * CELL_B;                         // bytes per wave
   static constexpr long F_OFF = WTOT * 2 + BTOT * 4;
-  static constexpr long O_OFF = F_OFF + WAVES * F_WAVE;
-  static constexpr long BYTES = O_OFF + WAVES * O_WAVE;
+  static constexpr int WAVES = NS <= 15 ? 12 : 4, THREADS = WAVES * 64;
+  static constexpr long BYTES = F_OFF + WAVES * STAGE;
+  static_assert(WTOT % 8 == 0 && F_OFF % 16 == 0, "16-byte LDS alignment");
+  static_assert(BYTES <= 160 * 1024, "inference block exceeds the LDS");
 };
 
 // Orders this wave's LDS writes before its later LDS reads of other lanes'
@@ -336,8 +364,7 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
   const unsigned short* sW4 = sW3 + S::W2;
   float* sB = reinterpret_cast<float*>(smem + S::WTOT * 2);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
-  unsigned short* sF = reinterpret_cast<unsigned short*>(smem + S::F_OFF + wave * S::F_WAVE);
-  float* sO = reinterpret_cast<float*>(smem + S::O_OFF + wave * S::O_WAVE);
+  unsigned char* stage = smem + S::F_OFF + wave * S::STAGE;
   {
     const uint4* src = reinterpret_cast<const uint4*>(a.wpack);
     uint4* dst = reinterpret_cast<uint4*>(sW);
@@ -384,84 +411,89 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
           f[k] = z;
         }
       }
+      // this lane's row of the staging area: its features, zero-padded,
+      // as 16-byte stores
 #pragma unroll
-      for (int k = 0; k < KC1 * 32; ++k)
-        sF[k * 64 + lane] = (valid && k < NI) ? d2bf(f[k < NI ? k : 0]) : (unsigned short)0;
+      for (int q = 0; q < KC1 * 4; ++q) {
+        v8s v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int k = 8 * q + j;
+          v[j] = (short)((valid && k < NI) ? d2bf(f[k < NI ? k : 0]) : (unsigned short)0);
+        }
+        *reinterpret_cast<v8s*>(stage + lane * S::CELL_B + 16 * q) = v;
+      }
     }
     wave_sync();
-    // ---- stage 1: the MLP on this wave's 64 cells (4 column tiles of 16)
-    {
-      f32x4 acc[8][4];
-      v8s bn[4][4];
-#pragma unroll
-      for (int ot = 0; ot < 8; ++ot)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // ---- stage 1: the MLP on this wave's 64 cells, in two halves of 32
+    // (two column tiles of 16 each).  Each layer's bias is the C operand of
+    // its first MFMA of every output tile, so the accumulators start from
+    // the bias instead of zero.
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+      unsigned char* hs = stage + half * 32 * S::CELL_B;
+      f32x4 acc[8][2];
+      v8s bn[4][2];
 #pragma unroll
       for (int kc = 0; kc < KC1; ++kc) {
-        v8s b1[4];
+        v8s b1[2];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            b1[ct][j] = (short)sF[(kc * 32 + 8 * g + j) * 64 + ct * 16 + r16];
+        for (int ct = 0; ct < 2; ++ct)
+          b1[ct] = *reinterpret_cast<const v8s*>(hs + (ct * 16 + r16) * S::CELL_B + kc * 64 + 16 * g);
 #pragma unroll
         for (int ot = 0; ot < 8; ++ot) {
-          const v8s aw = *reinterpret_cast<const v8s*>(sW1 + (ot * 16 + r16) * (KC1 * 32) + kc * 32 + 8 * g);
+          const v8s aw = *reinterpret_cast<const v8s*>(sW1 + (ot * 16 + r16) * S::W1_LD + kc * 32 + 8 * g);
+          f32x4 bv;
+          if (kc == 0) bv = *reinterpret_cast<const f32x4*>(sB + ot * 16 + 4 * g);
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = mfma(aw, b1[ct], acc[ot][ct]);
+          for (int ct = 0; ct < 2; ++ct) acc[ot][ct] = mfma(aw, b1[ct], kc == 0 ? bv : acc[ot][ct]);
         }
       }
 #pragma unroll
       for (int layer = 0; layer < 3; ++layer) {
-        const float* bias = sB + layer * HID;
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc)
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct)
+          for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               const int ot = 2 * kc + (j >> 2), i = j & 3;
-              const float zv = acc[ot][ct][i] + bias[ot * 16 + 4 * g + i];
-              bn[kc][ct][j] = (short)f2bf(silu_fast(zv));
+              bn[kc][ct][j] = (short)f2bf(silu_fast(acc[ot][ct][i]));
             }
         if (layer == 2) break;
         const unsigned short* Wl = layer == 0 ? sW2 : sW3;
-#pragma unroll
-        for (int ot = 0; ot < 8; ++ot)
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const float* bias = sB + (layer + 1) * HID;
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc)
 #pragma unroll
           for (int ot = 0; ot < 8; ++ot) {
-            const v8s aw = *reinterpret_cast<const v8s*>(Wl + (ot * 16 + r16) * HID + kc * 32 + 8 * g);
+            const v8s aw = *reinterpret_cast<const v8s*>(Wl + (ot * 16 + r16) * kWLd + kc * 32 + 8 * g);
+            f32x4 bv;
+            if (kc == 0) bv = *reinterpret_cast<const f32x4*>(bias + ot * 16 + 4 * g);
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[ot][ct] = mfma(aw, bn[kc][ct], acc[ot][ct]);
+            for (int ct = 0; ct < 2; ++ct)
+              acc[ot][ct] = mfma(aw, bn[kc][ct], kc == 0 ? bv : acc[ot][ct]);
           }
       }
-      f32x4 acc4[OT4][4];
-#pragma unroll
-      for (int ot = 0; ot < OT4; ++ot)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc4[ot][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+      f32x4 acc4[OT4][2];
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc)
 #pragma unroll
         for (int ot = 0; ot < OT4; ++ot) {
-          const v8s aw = *reinterpret_cast<const v8s*>(sW4 + (ot * 16 + r16) * HID + kc * 32 + 8 * g);
+          const v8s aw = *reinterpret_cast<const v8s*>(sW4 + (ot * 16 + r16) * kWLd + kc * 32 + 8 * g);
+          f32x4 bv;
+          if (kc == 0) bv = *reinterpret_cast<const f32x4*>(sB + 3 * HID + ot * 16 + 4 * g);
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc4[ot][ct] = mfma(aw, bn[kc][ct], acc4[ot][ct]);
+          for (int ct = 0; ct < 2; ++ct)
+            acc4[ot][ct] = mfma(aw, bn[kc][ct], kc == 0 ? bv : acc4[ot][ct]);
         }
+      // outputs 16 ot + 4 g + (0..3) of cell 16 ct + r16, over that cell's
+      // features (already in registers: the MFMAs above consumed them)
 #pragma unroll
       for (int ot = 0; ot < OT4; ++ot)
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int o = ot * 16 + 4 * g + i;
-            sO[o * 64 + ct * 16 + r16] = acc4[ot][ct][i] + sB[3 * HID + o];
-          }
+        for (int ct = 0; ct < 2; ++ct)
+          *reinterpret_cast<f32x4*>(hs + (ct * 16 + r16) * S::CELL_B + ot * 64 + 16 * g) = acc4[ot][ct];
     }
     wave_sync();
     // ---- stage 2: de-standardise and trust-test this lane's cell (FP64)
@@ -471,7 +503,7 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
       bool fin = true;
 #pragma unroll
       for (int k = 0; k < NO; ++k) {
-        const float o = sO[k * 64 + lane];
+        const float o = reinterpret_cast<const float*>(stage + lane * S::CELL_B)[k];
         if (a.out_std) a.out_std[cell * NO + k] = o;
         inc[k] = (double)o * (double)sd_out[k] + (double)mu_out[k];
         fin = fin && isfinite(inc[k]);
@@ -611,6 +643,9 @@ hipError_t launch_surr_infer(const surr::InferArgs& a, int grid, hipStream_t s) 
                         (int)S::BYTES);
     attr = true;
   }
+  // at most `grid` blocks (one per CU), fewer when the cells do not fill them
+  const long need = (a.n + S::THREADS - 1) / S::THREADS;
+  grid = (int)(need < grid ? (need > 0 ? need : 1) : grid);
   hipLaunchKernelGGL(surr::surr_infer<M>, dim3(grid), dim3(S::THREADS), S::BYTES, s, a);
   return hipGetLastError();
 }
