@@ -280,26 +280,36 @@ def cpu_baseline_strata(path, strata, threads, build, host, one_thread_frac=0.12
 
 
 # ------------------------------------------------------------- FP64 boxes
-def dominant_fp64(kt, per_cell_steps, tail, cap, n_cu, flops_per_step):
-    """The larger of the per-lane kernel (with its resumption launch) and the
-    cooperative kernel, with its algorithmic FP64 rate: a cell still stepping
-    after the hand-off point takes its remaining steps in the cooperative
-    kernel when the list fits the cap, else in the per-lane resumption."""
-    coop_steps = 0
-    if tail > 0:
-        over = per_cell_steps[per_cell_steps > tail]
-        if cap < 0 or over.size <= cap * n_cu:
-            coop_steps = int((over - tail).sum())
-    total = int(per_cell_steps.sum())
+def dominant_fp64(kt, total_steps, coop_steps, flops_per_step):
+    """The longer of the per-lane kernel (with its resumption launch) and the
+    cooperative kernel, with its algorithmic FP64 rate: its RK steps (the
+    cooperative kernel counts the steps it takes, chem_tail_stats; the
+    per-lane launches take the rest) x flops per step over its HIP-event
+    duration."""
     pers_ms = kt["persistent"] + kt["resume"]
     if kt["coop"] > pers_ms:
         dom, dom_ms, dom_steps = "lsrk_coop", kt["coop"], coop_steps
     else:
-        dom, dom_ms, dom_steps = "lsrk_persistent", pers_ms, total - coop_steps
+        dom, dom_ms, dom_steps = "lsrk_persistent", pers_ms, total_steps - coop_steps
     ach = dom_steps * flops_per_step / (dom_ms * 1e-3) / 1e12
     return {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
             "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "launch_ms": dom_ms,
             "rk_steps_per_launch": dom_steps}
+
+
+def timed_kernels(cg, mech, run, reps):
+    """Per-kernel HIP-event durations (means over reps calls of run()) and the
+    cooperative kernel's step count of the last call."""
+    cg.chem_set_kernel_timing(mech, True)
+    recs, tail = [], None
+    try:
+        for _ in range(reps):
+            run()
+            recs.append(cg.chem_kernel_times(mech))
+            tail = cg.chem_tail_stats(mech)
+    finally:
+        cg.chem_set_kernel_timing(mech, False)
+    return {k: float(np.mean([r[k] for r in recs])) for k in recs[0]}, tail
 
 
 def measure_boxes(args, workload, hboxes=None, path=None, steps=None):
@@ -372,21 +382,12 @@ def measure_boxes(args, workload, hboxes=None, path=None, steps=None):
 
     # the dominant kernel, timed live: the same flow step as plain calls with
     # the library's per-kernel timing (HIP events around each launch, on the
-    # launch stream)
-    chemgpu.chem_set_kernel_timing(mech, True)
-    recs = []
-    for _ in range(max(3, min(K, 10))):
+    # launch streams)
+    def one():
         restore()
         chemgpu.chem_integrate_batched(mech, tboxes, base)
-        recs.append(chemgpu.chem_kernel_times(mech))
-    chemgpu.chem_set_kernel_timing(mech, False)
-    kt = {k: float(np.mean([r[k] for r in recs])) for k in recs[0]}
-    eff = tuned or {}
-    tail = args.tail or eff.get("tail_steps", 0)
-    cap = args.tail_cap or eff.get("tail_cap", 0) or 64   # 0: the library's default, 64 per CU
-    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    roof = dominant_fp64(kt, cn.sum(axis=0), tail if args.scheme == "lsrk" else 0, cap, n_cu,
-                         flops_per_step)
+    kt, tstats = timed_kernels(chemgpu, mech, one, max(3, min(K, 10)))
+    roof = dominant_fp64(kt, total_steps, tstats["cooperative_steps"], flops_per_step)
     roof["traffic"] = traffic(workload, roof["kernel"]) if args.scheme == "lsrk" else None
     achieved = total_steps * flops_per_step / (kern_ms * 1e-3) / 1e12
     nv = mech.n_species + 1
@@ -402,6 +403,7 @@ def measure_boxes(args, workload, hboxes=None, path=None, steps=None):
                                "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                "frac": achieved / PEAK_FP64_VECTOR_TFLOPS},
         "kernel_times_ms": kt,
+        "tail_list": tstats,
         # per flow step: read (T, Y, rho, h), write (T, Y, h) of every cell
         "hbm_algorithmic_bytes": n * 8 * ((nv + 2) + (nv + 1)),
         "steps_per_flow_step": {"total_rk_steps": total_steps, "rejected": int(cn[1].sum()),
@@ -513,7 +515,6 @@ def surrogate_field(args):
     stream = torch.cuda.current_stream()
     K = args.steps
     flops_per_step = codegen.step_flops(codegen.parse(path), "lsrk")
-    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
 
     def timed(fn, k=K):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -544,16 +545,12 @@ def surrogate_field(args):
     log(f"surrogate field: timing {K} plain FP64 steps")
     k_plain, k_plain_all, w_plain = timed(lambda: graph.launch(stream))
     graph.close()
-    cg.chem_set_kernel_timing(m, True)
-    recs = []
-    for _ in range(3):
+    def plain_once():
         work.copy_(field)
         cg.chem_integrate(m, work, wl.DT_FLOW, opts)
-        recs.append(cg.chem_kernel_times(m))
-    kt_plain = {k: float(np.mean([r[k] for r in recs])) for k in recs[0]}
-    cg.chem_set_kernel_timing(m, False)
+    kt_plain, tail_plain = timed_kernels(cg, m, plain_once, 3)
     per_cell = plain_counts.sum(axis=0)
-    roof_plain = dominant_fp64(kt_plain, per_cell, opts.tail_steps, opts.tail_cap or 64, n_cu,
+    roof_plain = dominant_fp64(kt_plain, int(per_cell.sum()), tail_plain["cooperative_steps"],
                                flops_per_step)
     roof_plain["traffic"] = traffic("surrogate256_plain", roof_plain["kernel"])
     plain_ach = int(per_cell.sum()) * flops_per_step / (k_plain * 1e-3) / 1e12
@@ -567,20 +564,20 @@ def surrogate_field(args):
     tc = torch.zeros(n, dtype=torch.int32, device="cuda")
     fst = torch.full((n,), -1, dtype=torch.int32, device="cuda")
     fcn = torch.zeros(2 * n, dtype=torch.int32, device="cuda")
-    cg.chem_set_kernel_timing(m, True)
-    recs = []
-    for r in range(3):
+    fb_count = [0]
+
+    def surr_once():
         work.copy_(field)
-        n_fb = cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True, opts=opts,
-                                  trust_code=tc, status=fst, counts=fcn, want_count=True)
-        recs.append(cg.chem_kernel_times(m))
-    cg.chem_set_kernel_timing(m, False)
-    kt_fb = {k: float(np.mean([r[k] for r in recs])) for k in recs[0]}
+        fb_count[0] = cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True,
+                                         opts=opts, trust_code=tc, status=fst, counts=fcn,
+                                         want_count=True)
+    kt_fb, tail_fb = timed_kernels(cg, m, surr_once, 3)
+    n_fb = fb_count[0]
     # the timed FP64 run is the one over the cells outside the hull (code 1)
     tcn = tc.cpu().numpy()
     hull = tcn == 1
     fb_steps = fcn.view(2, n).cpu().numpy().sum(axis=0)
-    roof_fb = dominant_fp64(kt_fb, fb_steps[hull], opts.tail_steps, opts.tail_cap or 64, n_cu,
+    roof_fb = dominant_fp64(kt_fb, int(fb_steps[hull].sum()), tail_fb["cooperative_steps"],
                             flops_per_step)
     roof_fb["traffic"] = traffic("surrogate256_fallback", roof_fb["kernel"])
     inf_ach = SURROGATE_FLOPS_PER_CELL * n / (k_inf * 1e-3) / 1e12
@@ -612,6 +609,7 @@ def surrogate_field(args):
         "roofline_inference": roof_inf,
         "roofline_fallback_fp64": roof_fb,
         "kernel_times_fallback_ms": kt_fb,
+        "tail_list_fallback": tail_fb,
         "fallback_rk_steps": {"hull_cells": int(hull.sum()),
                               "hull_rk_steps": int(fb_steps[hull].sum()),
                               "other_fallback_cells": int((tcn > 1).sum()),
@@ -626,6 +624,7 @@ def surrogate_field(args):
                                    "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                    "frac": plain_ach / PEAK_FP64_VECTOR_TFLOPS},
             "kernel_times_ms": kt_plain,
+            "tail_list": tail_plain,
             "steps_per_flow_step": {"total_rk_steps": int(per_cell.sum()),
                                     "rejected": int(plain_counts[1].sum()),
                                     "max_per_cell": int(per_cell.max())},

@@ -150,11 +150,16 @@ int chem_workspace_reserve(chem_mech m, int64_t max_cells);
  * on == 0 stops it.  chem_kernel_times then waits for the last such call and
  * writes n >= 4 durations in ms: [0] the persistent per-lane kernel, [1] the
  * tail-list sort, [2] the cooperative kernel, [3] the per-lane resumption of
- * the tail list (0 for those the call did not launch).  CHEM_EINVAL for a
- * null argument, n < 4, or no timed call since timing was last set.
+ * the tail list, and with n >= 5 [4] the whole flow step (0 for what the
+ * call did not launch).  chem_tail_stats waits the same way and
+ * writes n >= 3 counts of that call: [0] cells handed over to the tail list,
+ * [1] of them finished by the cooperative kernel, [2] the steps (accepted +
+ * rejected) the cooperative kernel took.  CHEM_EINVAL for a null argument, n
+ * too small, or no timed call since timing was last set.
  */
 int chem_set_kernel_timing(chem_mech m, int32_t on);
 int chem_kernel_times(chem_mech m, float *ms, int32_t n);
+int chem_tail_stats(chem_mech m, int64_t *out, int32_t n);
 
 /*
  * Advance n_cells cells by dt (paper Eq. 20-22), in place.

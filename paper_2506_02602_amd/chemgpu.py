@@ -169,10 +169,24 @@ def chem_set_kernel_timing(mech: Mechanism, on: bool = True) -> None:
 
 
 def chem_kernel_times(mech: Mechanism) -> dict:
-    """Durations (ms) of the last timed call's launches (waits for it)."""
-    ms = (C.c_float * 4)()
-    _check(_lib.chem_kernel_times(mech.handle, ms, 4), "chem_kernel_times")
-    return {"persistent": ms[0], "tail_sort": ms[1], "coop": ms[2], "resume": ms[3]}
+    """Durations (ms) of the last timed call's launches (waits for it);
+    `total` the whole flow step."""
+    ms = (C.c_float * 5)()
+    _check(_lib.chem_kernel_times(mech.handle, ms, 5), "chem_kernel_times")
+    return {"persistent": ms[0], "tail_sort": ms[1], "coop": ms[2], "resume": ms[3],
+            "total": ms[4]}
+
+
+_lib.chem_tail_stats.argtypes = [_P, C.POINTER(C.c_int64), C.c_int32]
+_lib.chem_tail_stats.restype = C.c_int
+
+
+def chem_tail_stats(mech: Mechanism) -> dict:
+    """Tail list of the last timed call: cells handed over, of them finished
+    by the cooperative kernel, and the steps that kernel took."""
+    out = (C.c_int64 * 3)()
+    _check(_lib.chem_tail_stats(mech.handle, out, 3), "chem_tail_stats")
+    return {"handed_over": out[0], "cooperative": out[1], "cooperative_steps": out[2]}
 
 
 def chem_integrate(mech: Mechanism, state, dt: float, opts: chem_opts | None = None,
@@ -495,4 +509,4 @@ def exported_symbols():
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
             "surrogate_free", "chem_eval_exp", "chem_eval_math", "chem_react_conserved",
             "chem_set_kernel_timing", "chem_kernel_times", "surrogate_reserve",
-            "chem_integrate_noalloc"]
+            "chem_integrate_noalloc", "chem_tail_stats"]

@@ -88,10 +88,13 @@ __global__ void eval_math_kernel(int fn, const double* x, double* y, int64_t n) 
 }
 
 __global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
-                           unsigned long long* tail_next) {
+                           unsigned long long* tail_next, unsigned long long* tail_next2,
+                           unsigned long long* coop_steps) {
   *next = 0ull;
   if (tail_count) *tail_count = 0u;
   if (tail_next) *tail_next = 0ull;
+  if (tail_next2) *tail_next2 = 0ull;
+  if (coop_steps) *coop_steps = 0ull;
 }
 
 // Order of the tail list.  The cooperative kernel's groups claim handed-over
@@ -111,14 +114,20 @@ __device__ __forceinline__ int32_t tail_key(double rem, double h) {
   return k >= (double)(kTailBuckets - 1) ? kTailBuckets - 1 : (int32_t)k;
 }
 
-// Counting sort of the records by key, largest first, into tb.order (one
-// block).  Cells with equal keys keep no particular order: each cell's
-// integration does not depend on when or by which group it runs.  Does
-// nothing when the list is empty or is resumed one cell per lane.
+// Which kernel finishes the tail list (one block): when it holds at most
+// tb.cap cells the cooperative kernel takes all of them (split = count) and
+// they are counting-sorted by key into tb.order, largest first; otherwise
+// the per-lane resumption takes all of them (split = 0).  Several lanes per
+// cell only pay while the tail is short next to the chip, and the choice
+// depends only on the list's length, so on the input.  Cells with equal keys
+// keep no particular order: each cell's integration does not depend on when
+// or by which group it runs.
 __global__ __launch_bounds__(1024) void tail_order(TailBuf tb) {
   __shared__ unsigned int off[kTailBuckets];
   const unsigned int count = *tb.count;
-  if (count == 0u || count > (unsigned int)tb.cap) return;
+  const bool coop = count > 0u && count <= (unsigned int)tb.cap;
+  if (threadIdx.x == 0) *tb.split = coop ? count : 0u;
+  if (!coop) return;
   for (int k = threadIdx.x; k < kTailBuckets; k += blockDim.x) off[k] = 0u;
   __syncthreads();
   for (unsigned int r = threadIdx.x; r < count; r += blockDim.x) atomicAdd(&off[tb.key[r]], 1u);
@@ -298,9 +307,9 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   int bx = 0;
   int64_t total = a.total_dev ? (int64_t)*a.total_dev : a.total;
   if (a.resume) {
-    // resume tail records only when there are too many for the cooperative kernel
+    // resume the tail records when the cooperative kernel does not take them
     const unsigned int cnt = *a.tail.count;
-    total = cnt > (unsigned int)a.tail.cap ? (int64_t)cnt : 0;
+    total = *a.tail.split < cnt ? (int64_t)cnt : 0;
   }
 
   // claim the first B items
@@ -315,16 +324,18 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
     if (tid >= free_from) {
       const int64_t g = s_base + (tid - free_from);
       item = -1;
-      if (g < total && a.resume) {
+      if (a.resume) {
         // a cell handed over at tail_steps: its state and hint are in its
         // rows, its progress in record g
-        item = a.tail.item[g];
-        bx = find_box(a, item);
-        const BoxDesc& bd = box_ref(a, bx);
-        load_cell<M>(bd, cell_index(bd, item), u, rho, h);
-        t = a.tail.t[g];
-        nacc = a.tail.nacc[g]; nrej = a.tail.nrej[g];
-        sub = a.tail.sub[g]; base = a.tail.base[g];
+        if (g < total) {
+          item = a.tail.item[g];
+          bx = find_box(a, item);
+          const BoxDesc& bd = box_ref(a, bx);
+          load_cell<M>(bd, cell_index(bd, item), u, rho, h);
+          t = a.tail.t[g];
+          nacc = a.tail.nacc[g]; nrej = a.tail.nrej[g];
+          sub = a.tail.sub[g]; base = a.tail.base[g];
+        }
       } else if (g < total) {
         item = a.order ? (int64_t)a.order[g] : g;
         if (item < 0 || item >= total) item = -1;
@@ -599,7 +610,9 @@ template <class M>
 hipError_t launch_persistent(const PoolArgs& a, int block, int grid, hipStream_t s) {
   hipLaunchKernelGGL(pool_reset, dim3(1), dim3(1), 0, s, a.next,
                      a.tail_steps > 0 ? a.tail.count : nullptr,
-                     a.tail_steps > 0 ? a.tail.next : nullptr);
+                     a.tail_steps > 0 ? a.tail.next : nullptr,
+                     a.tail_steps > 0 ? a.tail.next2 : nullptr,
+                     a.tail_steps > 0 ? a.tail.coop_steps : nullptr);
   if (a.scheme == SCHEME_ROS4) {
     if constexpr (M::HAS_JAC) {
       if (block > 256) return hipErrorInvalidConfiguration;
@@ -695,21 +708,25 @@ uint64_t fnv1a64(const std::vector<char>& d) {
 struct TailStore {
   void* mem = nullptr;
   int64_t cap = 0;
-  // [next u64][count u32][pad][t: cap doubles]
-  // [item, nacc, nrej, sub, base, key, order: cap int32 each]
+  // [next u64][count u32][split u32][next2 u64][coop_steps u64][pad]
+  // [t: cap doubles][item, nacc, nrej, sub, base, key, order: cap int32 each]
+  static constexpr size_t kHead = 32;
   TailBuf view() const {
     TailBuf b{};
     char* p = static_cast<char*>(mem);
     b.next = reinterpret_cast<unsigned long long*>(p);
     b.count = reinterpret_cast<unsigned int*>(p + 8);
-    b.t = reinterpret_cast<double*>(p + 16);
-    int32_t* q = reinterpret_cast<int32_t*>(p + 16 + sizeof(double) * cap);
+    b.split = reinterpret_cast<unsigned int*>(p + 12);
+    b.next2 = reinterpret_cast<unsigned long long*>(p + 16);
+    b.coop_steps = reinterpret_cast<unsigned long long*>(p + 24);
+    b.t = reinterpret_cast<double*>(p + kHead);
+    int32_t* q = reinterpret_cast<int32_t*>(p + kHead + sizeof(double) * cap);
     b.item = q; b.nacc = q + cap; b.nrej = q + 2 * cap; b.sub = q + 3 * cap; b.base = q + 4 * cap;
     b.key = q + 5 * cap; b.order = q + 6 * cap;
     return b;
   }
   static constexpr size_t bytes(int64_t cap) {
-    return 16 + (size_t)cap * (sizeof(double) + 7 * sizeof(int32_t));
+    return kHead + (size_t)cap * (sizeof(double) + 7 * sizeof(int32_t));
   }
 };
 
@@ -787,6 +804,7 @@ struct chem_mech_s {
   bool timing = false;
   bool timed_last = false;
   hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const TailStore* timed_tail = nullptr;  // the tail records of the last timed call
 };
 
 struct chem_graph_s {
@@ -958,10 +976,11 @@ void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int
 int grid_for(chem_mech m, int block, int64_t total, int scheme);
 
 // The flow step's launches: pool reset + persistent kernel, then, with a
-// hand-off point, the ordering of the tail list, the cooperative kernel and
-// the per-lane resumption of the list (exactly one of the last two does
-// work, chosen by the list's length against a.tail.cap: several lanes per
-// cell only pay while the tail is short next to the chip).
+// hand-off point, tail_order, the cooperative kernel and the per-lane
+// resumption of the list (exactly one of the last two does work, chosen by
+// the list's length against a.tail.cap).  Timed calls record m->tev: [0]
+// before the persistent kernel, [1] after it, [2] after tail_order, [3]
+// after the cooperative kernel, [4] after the resumption.
 hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_t s,
                        const OrderBuf* ob, bool timed = false) {
   hipError_t e;
@@ -997,7 +1016,7 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
   PoolArgs r = a;
   r.resume = 1;
   r.tail_steps = 0;
-  r.next = a.tail.next;
+  r.next = a.tail.next2;
   r.total_dev = nullptr;
   r.order = nullptr;
   e = m->entry->launch_persistent(r, block, grid, s);
@@ -1040,7 +1059,10 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
   hipError_t e = launch_step(m, a, block, grid_for(m, block, a.total, a.scheme), s,
                              ordered ? &ob : nullptr, timed);
   if (e != hipSuccess) return hip_fail(e, "launch integrator kernels");
-  if (timed) m->timed_last = true;
+  if (timed) {
+    m->timed_last = true;
+    m->timed_tail = a.tail_steps > 0 ? &tail : nullptr;
+  }
   return CHEM_OK;
 }
 
@@ -1298,11 +1320,38 @@ int chem_kernel_times(chem_mech m, float* ms, int32_t n) {
   if (!m->timed_last) return fail(CHEM_EINVAL, "chem_kernel_times: no timed call since timing was set");
   hipError_t e = hipEventSynchronize(m->tev[4]);
   if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(kernel timing)");
+  // persistent, tail_order, cooperative, resumption
   for (int k = 0; k < 4; ++k) {
     ms[k] = 0.0f;
     e = hipEventElapsedTime(&ms[k], m->tev[k], m->tev[k + 1]);
     if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime(kernel timing)");
   }
+  if (n >= 5) {
+    ms[4] = 0.0f;
+    e = hipEventElapsedTime(&ms[4], m->tev[0], m->tev[4]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime(kernel timing)");
+  }
+  return CHEM_OK;
+}
+
+int chem_tail_stats(chem_mech m, int64_t* out, int32_t n) {
+  if (!m || !out || n < 3) return fail(CHEM_EINVAL, "chem_tail_stats: bad argument");
+  if (!m->timed_last) return fail(CHEM_EINVAL, "chem_tail_stats: no timed call since timing was set");
+  hipError_t e = hipEventSynchronize(m->tev[4]);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(tail stats)");
+  out[0] = out[1] = out[2] = 0;
+  if (!m->timed_tail) return CHEM_OK;
+  unsigned char head[TailStore::kHead];
+  e = hipMemcpy(head, m->timed_tail->mem, sizeof head, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(tail stats)");
+  unsigned int count, split;
+  unsigned long long steps;
+  memcpy(&count, head + 8, 4);
+  memcpy(&split, head + 12, 4);
+  memcpy(&steps, head + 24, 8);
+  out[0] = count;
+  out[1] = split;
+  out[2] = (int64_t)steps;
   return CHEM_OK;
 }
 

@@ -40,8 +40,8 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   double* E = smem + C::ND;
   int* I = reinterpret_cast<int*>(smem + C::ND + 64);
   double* scr = smem + C::ND + 64 + C::NI / 2;
-  const unsigned int count = *a.tail.count;
-  if (count > (unsigned int)a.tail.cap) return;  // resumed one per lane instead
+  const unsigned int count = *a.tail.split;  // the records this kernel takes (tail_order)
+  if (count == 0u) return;
   const int tid = threadIdx.x;
   for (int i = tid; i < C::ND; i += blockDim.x) D[i] = C::dtab()[i];
   for (int i = tid; i < C::NI; i += blockDim.x) I[i] = C::itab()[i];
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   double dt = 0.0;
   int n_sub = 1;
   double uT = 0.0, uk = 0.0, rho = 1.0, inv_rho = 1.0, h = 0.0, t = 0.0;
-  int nacc = 0, nrej = 0, sub = 0, base = 0;
+  int nacc = 0, nrej = 0, sub = 0, base = 0, n0 = 0;
 #pragma unroll 1
   for (;;) {
     if (idle) break;
@@ -98,6 +98,7 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
       t = a.tail.t[r];
       nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
       sub = a.tail.sub[r]; base = a.tail.base[r];
+      n0 = nacc + nrej;
       have = true;
     }
     Control c = a.c;
@@ -115,6 +116,7 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
         st[(N + 2) * ld + i] = h;
         if (status) status[i] = code;
         if (counts) { counts[i] = nacc; counts[nbox + i] = nrej; }
+        atomicAdd(a.tail.coop_steps, (unsigned long long)(nacc + nrej - n0));
       }
       have = false;
     }

@@ -304,12 +304,16 @@ def test_kernel_timing_reports_each_launch(cg, gm9, mech9_path):
         cg.chem_kernel_times(gm9)
     on = run_gpu(gm9, s0, wl.DT_FLOW, **kw)
     kt = cg.chem_kernel_times(gm9)
+    st = cg.chem_tail_stats(gm9)
     cg.chem_set_kernel_timing(gm9, False)
     off = run_gpu(gm9, s0, wl.DT_FLOW, **kw)
     assert all(np.array_equal(x, y) for x, y in zip(on, off))
-    assert set(kt) == {"persistent", "tail_sort", "coop", "resume"}
+    assert set(kt) == {"persistent", "tail_sort", "coop", "resume", "total"}
     assert all(v >= 0.0 for v in kt.values())
     assert kt["persistent"] > 0.0 and kt["coop"] > 0.0
+    assert abs(kt["total"] - (kt["persistent"] + kt["tail_sort"] + kt["coop"] + kt["resume"])) < 0.05
+    assert st["cooperative"] == st["handed_over"] > 0      # no cap: it takes the whole list
+    assert st["cooperative_steps"] > 0
 
 
 def test_front_field_in_the_timed_launch(cg, omech9, mech9_path):

@@ -265,15 +265,22 @@ def test_tail_cells_match_oracle(gmech9, omech9, mech9_path, tail):
 
 
 @pytest.mark.parametrize("cap", [0, 1])
-def test_long_tail_list_resumes_per_lane(gmech9, mech9_path, cap):
+def test_long_tail_list_resumes_per_lane(chemgpu, gmech9, mech9_path, cap):
     """More handed-over cells than the cooperative kernel takes (default 64
     per CU, or 1): the list is resumed one cell per lane, bitwise the result
-    of never handing over."""
+    of never handing over, and the cooperative kernel takes no step."""
     s0, hot = wl.front_2d(mech9_path, nx=1024, ny=1024, seed=37)
     s1 = np.ascontiguousarray(np.tile(s0[:, hot], (1, 2)))       # ~42,000 stiff cells
     ref, rst, rcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=-1)
-    g, gst, gcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=1, tail_cap=cap)
+    chemgpu.chem_set_kernel_timing(gmech9, True)
+    try:
+        g, gst, gcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=1, tail_cap=cap)
+        stats = chemgpu.chem_tail_stats(gmech9)
+    finally:
+        chemgpu.chem_set_kernel_timing(gmech9, False)
     assert np.array_equal(g, ref) and np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
+    assert 0 < stats["handed_over"] <= s1.shape[1]
+    assert stats["cooperative"] == 0 and stats["cooperative_steps"] == 0
 
 
 def test_long_tail_list_without_cap(gmech9, omech9, mech9_path):
