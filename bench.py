@@ -512,6 +512,12 @@ def surrogate_field(args):
               "tail_steps": opts.tail_steps, "tail_cap": opts.tail_cap,
               "pool_order": opts.pool_order}
     log(f"surrogate: launch {launch}")
+    # the fallback's launch, tuned on whole surrogate steps over this field
+    fb_opts = cg.surrogate_autotune(s, m, field, wl.DT_FLOW, trust, base, reps=1, cache_path=cache)
+    launch_fb = {"block_size": fb_opts.block_size, "chunk_steps": fb_opts.chunk_steps,
+                 "tail_steps": fb_opts.tail_steps, "tail_cap": fb_opts.tail_cap,
+                 "pool_order": fb_opts.pool_order}
+    log(f"surrogate: fallback launch {launch_fb}")
     stream = torch.cuda.current_stream()
     K = args.steps
     flops_per_step = codegen.step_flops(codegen.parse(path), "lsrk")
@@ -558,7 +564,7 @@ def surrogate_field(args):
     # surrogate + fallback
     log(f"surrogate field: timing {K} surrogate+fallback steps")
     k_surr, k_surr_all, w_surr = timed(
-        lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True, opts=opts))
+        lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True, opts=fb_opts))
     k_inf, k_inf_all, _ = timed(
         lambda: cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=False))
     tc = torch.zeros(n, dtype=torch.int32, device="cuda")
@@ -569,7 +575,7 @@ def surrogate_field(args):
     def surr_once():
         work.copy_(field)
         fb_count[0] = cg.surrogate_infer(s, m, work, wl.DT_FLOW, trust, fallback=True,
-                                         opts=opts, trust_code=tc, status=fst, counts=fcn,
+                                         opts=fb_opts, trust_code=tc, status=fst, counts=fcn,
                                          want_count=True)
     kt_fb, tail_fb = timed_kernels(cg, m, surr_once, 3)
     n_fb = fb_count[0]
@@ -630,6 +636,7 @@ def surrogate_field(args):
                                     "max_per_cell": int(per_cell.max())},
             "flops_per_rk_step": flops_per_step},
         "launch": launch,
+        "launch_fallback": launch_fb,
         "trust": {"hull_margin": trust[0], "elem_tol": trust[1], "pos_tol": trust[2],
                   "energy_tol_K": trust[3], "validation": tstats},
         "trusted_error_vs_fp64": {"max_rel_T": float(eT.max()), "p999_rel_T": q(eT),

@@ -27,8 +27,8 @@
  * allocated up front by chem_workspace_reserve (and surrogate_reserve); a
  * call on more cells than the reservation holds returns CHEM_ECAPACITY and
  * enqueues nothing.  Only the set-up calls allocate: chem_workspace_reserve,
- * surrogate_create/reserve/train/grad/forward, chem_autotune and
- * chem_graph_capture_batched.
+ * surrogate_create/reserve/train/grad/forward, chem_autotune,
+ * surrogate_autotune and chem_graph_capture_batched.
  */
 #ifndef CHEMGPU_H
 #define CHEMGPU_H
@@ -367,10 +367,10 @@ int surrogate_grad(chem_surr s, const float *Xn, const float *Yn, int32_t B, flo
 
 /*
  * Allocate what surrogate_infer with fallback needs for up to max_cells
- * cells: the fallback and hull lists and flags (9 B per cell), the side
- * stream's pool counter and tail records (36 B per cell), the side stream
- * and two events.  Growing it first waits for the whole device.  CHEM_EINVAL
- * for a null handle or max_cells < 0.
+ * cells: the fallback list and the out-of-hull flags (5 B per cell; the
+ * fallback's integration uses the mechanism's workspace).  Growing it
+ * first waits for the whole device.  CHEM_EINVAL for a null handle or
+ * max_cells < 0.
  */
 int surrogate_reserve(chem_surr s, int64_t max_cells);
 
@@ -382,7 +382,10 @@ int surrogate_reserve(chem_surr s, int64_t max_cells);
  * allows Y + dY down to -pos_tol, the write clips it to 0).  Untrusted cells keep their
  * state and, if `fallback` is non-zero, are integrated from it by the FP64
  * LSRK path (opts as for chem_integrate) in the same stream, with no host
- * round trip: a device-side list feeds the persistent kernel.  Optional
+ * round trip: cells outside the training hull are listed by a pass ahead of
+ * the network (which skips them), the network appends the cells failing
+ * the rest of the test, and one pool of the persistent kernel takes the
+ * device-side list.  Optional
  * device outputs: trust_code int32[n] (CHEM_TRUST_* bits), out_std
  * float[n][N+1] (raw network outputs), status / counts (as chem_integrate,
  * written for fallback cells only).  n_fallback_host (may be NULL) receives
@@ -395,6 +398,26 @@ int surrogate_infer(chem_surr s, chem_mech m, double *state, int64_t ld, int64_t
                     const double trust[4], int32_t fallback, const chem_opts *opts, void *stream,
                     int32_t *trust_code, float *out_std, int32_t *status, int32_t *counts,
                     int64_t *n_fallback_host);
+
+/*
+ * Tune the launch of surrogate_infer's FP64 fallback (block_size,
+ * chunk_steps, tail_steps, tail_cap, pool_order of `opts`) for this state
+ * block by the search of chem_autotune, each trial a whole
+ * surrogate_infer(fallback = 1) call on the block as it is on entry (the
+ * launch is chosen on the surrogate step itself: the fallback pool's cells
+ * sit scattered in the block, in the order the list was built).  The
+ * block is restored after every trial and on return.  `base` gives rtol,
+ * atol, max_steps and the scheme, and any launch field it fixes.  A cache
+ * entry (key hash:size-bucket:arch:surrogate, file as for chem_autotune)
+ * is returned without tuning; otherwise the result is appended to it.  The
+ * result goes to *best only (the mechanism's tuned table is for plain
+ * integrations).  A set-up call: reserves what the trials need, allocates a
+ * snapshot of the block and synchronises `stream`.  CHEM_EINVAL for null
+ * arguments, n_cells <= 0 or ld < n_cells.
+ */
+int surrogate_autotune(chem_surr s, chem_mech m, double *state, int64_t ld, int64_t n_cells,
+                       double dt, const double trust[4], const chem_opts *base, int32_t reps,
+                       const char *cache_path, void *stream, chem_opts *best);
 
 /* Save / load parameters and normaliser (binary; tied to the mechanism hash). */
 int surrogate_save(chem_surr s, const char *path);

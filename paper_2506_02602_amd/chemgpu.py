@@ -242,6 +242,9 @@ _lib.surrogate_infer.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_double, C
                                  C.c_int32, C.POINTER(chem_opts), _P, _P, _P, _P, _P,
                                  C.POINTER(C.c_int64)]
 _lib.surrogate_reserve.argtypes = [_P, C.c_int64]
+_lib.surrogate_autotune.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_double,
+                                    C.POINTER(C.c_double), C.POINTER(chem_opts), C.c_int32,
+                                    C.c_char_p, _P, C.POINTER(chem_opts)]
 _lib.surrogate_save.argtypes = [_P, C.c_char_p]
 _lib.surrogate_load.argtypes = [_P, C.c_char_p, C.POINTER(_P)]
 _lib.surrogate_free.argtypes = [_P]
@@ -371,6 +374,25 @@ def surrogate_infer(s: Surrogate, mech: Mechanism, state, dt, trust, fallback=Tr
                                 _ptr(out_std), _ptr(status), _ptr(counts),
                                 C.byref(cnt) if want_count else None), "surrogate_infer")
     return cnt.value if want_count else None
+
+
+def surrogate_autotune(s: Surrogate, mech: Mechanism, state, dt, trust, base=None, reps=3,
+                       cache_path=None, stream=None, n_cells=None) -> chem_opts:
+    """Launch for surrogate_infer's FP64 fallback, tuned on whole surrogate
+    steps over `state` (restored on return)."""
+    ld = state.shape[1]
+    n = ld if n_cells is None else int(n_cells)
+    tr = (C.c_double * 4)(*[float(x) for x in trust])
+    o = base if base is not None else make_opts()
+    best = chem_opts()
+    _reserve_for(mech, n)
+    if mech.auto_reserve and n > s.reserved:
+        surrogate_reserve(s, n)
+    _check(_lib.surrogate_autotune(s.handle, mech.handle, state.data_ptr(), ld, n, float(dt), tr,
+                                   C.byref(o), int(reps),
+                                   cache_path.encode() if cache_path else None, _stream(stream),
+                                   C.byref(best)), "surrogate_autotune")
+    return best
 
 
 def surrogate_save(s: Surrogate, path: str) -> None:
@@ -509,4 +531,4 @@ def exported_symbols():
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
             "surrogate_free", "chem_eval_exp", "chem_eval_math", "chem_react_conserved",
             "chem_set_kernel_timing", "chem_kernel_times", "surrogate_reserve",
-            "chem_integrate_noalloc", "chem_tail_stats"]
+            "chem_integrate_noalloc", "chem_tail_stats", "surrogate_autotune"]

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -202,10 +203,12 @@ __global__ __launch_bounds__(kOrderBlock) void order_rank(PoolArgs a, int ns, Or
   const int64_t first = (int64_t)blockIdx.x * kOrderBlock * kOrderRounds;
   bool heavy[kOrderRounds];
   unsigned long long bh[kOrderRounds], bl[kOrderRounds];
+  // the pool's size: fixed, or (a list built on the device) read here
+  const int64_t total = a.total_dev ? (int64_t)*a.total_dev : a.total;
 #pragma unroll
   for (int r = 0; r < kOrderRounds; ++r) {
     const int64_t g = first + (int64_t)r * kOrderBlock + threadIdx.x;
-    const bool valid = g < a.total;
+    const bool valid = g < total;
     heavy[r] = false;
     if (valid) {
       const BoxDesc& bd = box_ref(a, find_box(a, g));
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(kOrderBlock) void order_rank(PoolArgs a, int ns, Or
 #pragma unroll
   for (int r = 0; r < kOrderRounds; ++r) {
     const int64_t g = first + (int64_t)r * kOrderBlock + threadIdx.x;
-    if (g >= a.total) continue;
+    if (g >= total) continue;
     ob.rank[g] = heavy[r]
                      ? (int32_t)(base_h + off_h[r][wave] + (unsigned int)__popcll(bh[r] & below))
                      : -(int32_t)(base_l + off_l[r][wave] + (unsigned int)__popcll(bl[r] & below)) - 1;
@@ -253,7 +256,9 @@ __global__ __launch_bounds__(kOrderBlock) void order_rank(PoolArgs a, int ns, Or
 
 // Position of every item in the order (a bijection of [0, total)): by range,
 // class 0 then class 1, each in pool order; dealt, as described above.
-__global__ __launch_bounds__(256) void order_place(int64_t total, int R, int B, OrderBuf ob) {
+__global__ __launch_bounds__(256) void order_place(int64_t total, const unsigned int* total_dev,
+                                                   int R, int B, OrderBuf ob) {
+  if (total_dev) total = (int64_t)*total_dev;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int64_t H = ob.counts[0];
@@ -986,14 +991,17 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
   hipError_t e;
   a.order = nullptr;
   hipEvent_t* tv = timed ? m->tev : nullptr;
-  if (ob && a.total > 0 && !a.total_dev && !a.resume) {
-    // the dealt pool order: R = the resident blocks (the grid), B = block
+  if (ob && a.total > 0 && !a.resume) {
+    // the pool order (for a pool whose size is counted on the device, the
+    // kernels are sized by a.total, its upper bound, and read the count):
+    // R = the resident blocks (the grid), B = block
     const int64_t per = (int64_t)kOrderBlock * kOrderRounds;
     const unsigned rg = (unsigned)((a.total + per - 1) / per);
     const unsigned og = (unsigned)((a.total + 255) / 256);
     hipLaunchKernelGGL(order_reset, dim3(1), dim3(1), 0, s, ob->counts);
     hipLaunchKernelGGL(order_rank, dim3(rg), dim3(kOrderBlock), 0, s, a, m->entry->ns, *ob);
-    hipLaunchKernelGGL(order_place, dim3(og), dim3(256), 0, s, a.total, grid, block, *ob);
+    hipLaunchKernelGGL(order_place, dim3(og), dim3(256), 0, s, a.total, a.total_dev, grid, block,
+                       *ob);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     a.order = ob->order;
   }
@@ -1046,7 +1054,7 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
     a.tail.cap = pick_cap(m, a.total, o);
   }
   OrderBuf ob{};
-  const int omode = order && !a.total_dev ? pick_order(m, a.total, o) : 0;
+  const int omode = order ? pick_order(m, a.total, o) : 0;
   const bool ordered = omode != 0;
   if (ordered) {
     if (!order->mem || a.total > order->cap)
@@ -1160,6 +1168,183 @@ int write_cache(const char* path, const std::vector<TuneEntry>& v) {
   fprintf(f, "]}\n");
   fclose(f);
   if (rename(tmp.c_str(), path) != 0) return fail(CHEM_EINVAL, std::string("cannot replace ") + path);
+  return CHEM_OK;
+}
+
+// The launch search shared by chem_autotune and surrogate_autotune.
+// time_one(t, &ms) runs one call with launch t (from the caller's pristine
+// data) and times it.  Fills the best launch of the search into `best`
+// (launch fields only) and its median time into *best_ms.
+using TimeOne = std::function<int(const chem_opts&, float*)>;
+
+int tune_search(chem_mech m, const chem_opts& o, int reps, const TimeOne& time_one,
+                chem_opts* best, double* best_ms_out) {
+  int rc;
+  // median time of `reps` calls of one configuration (after one untimed call)
+  auto trial = [&](const chem_opts& t, double* med) -> int {
+    std::vector<float> ms;
+    for (int r = 0; r <= reps; ++r) {
+      float el = 0;
+      const int trc = time_one(t, &el);
+      if (trc != CHEM_OK) return trc;
+      if (r > 0) ms.push_back(el);
+    }
+    std::sort(ms.begin(), ms.end());
+    *med = ms[ms.size() / 2];
+    return CHEM_OK;
+  };
+  // Coordinate descent: chunk at the default block, block at the best
+  // chunk, chunk again at the best block, then the hand-off point for the
+  // best pair, then hand-off point and cooperative cap together (an early
+  // hand-off only pays when the cap lets the cooperative kernel take the
+  // longer list), then the two pool orders, then block and chunk once more
+  // at the final hand-off, cap and order.  Each sweep keeps the incumbent
+  // unless a candidate is faster.  Finally the fastest few launches seen
+  // are timed again, round-robin and with more calls each, so that one
+  // noisy trial (a clock ramp, other work on the device) does not decide.
+  const int blocks[] = {64, 128, 192, 256, 384, 512};
+  const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
+  const int tails[] = {4, 8, 16, 32, 64, 128, 256, 512, -1};
+  const int pair_tails[] = {4, 8, 16, 32, 64};
+  // below this many ms per call the (block, chunk) plane is swept whole
+  constexpr double kTuneGridMs = 50.0;
+  struct Seen { int b, c, tl, cap, ord; double ms; };
+  std::vector<Seen> seen;
+  const int caps[] = {kDefaultTailCap, 128, 256, -1};
+  double best_ms = 1e300;
+  int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
+  int best_tail = o.tail_steps != 0 ? o.tail_steps : kDefaultTail;
+  int best_cap = o.tail_cap != 0 ? o.tail_cap : kDefaultTailCap;
+  int best_order = o.pool_order != 0 ? o.pool_order : -1;
+  const bool tune_tail = o.tail_steps == 0 && o.fixed_steps == 0 && o.scheme == SCHEME_LSRK;
+  const bool tune_cap = tune_tail && o.tail_cap == 0;
+  auto consider = [&](int b, int c, int tl, int cap, int ord) -> int {
+    if (m->entry->lds_per_lane() * b > 65536) return CHEM_OK;
+    if (o.scheme == SCHEME_ROS4 && b > 256) return CHEM_OK;
+    chem_opts t = o;
+    t.block_size = b;
+    t.chunk_steps = c;
+    t.tail_steps = tl;
+    t.tail_cap = cap;
+    t.pool_order = ord;
+    double med = 0;
+    const int trc = trial(t, &med);
+    if (trc != CHEM_OK) return trc;
+    seen.push_back({b, c, tl, cap, ord, med});
+    if (med < best_ms) {
+      best_ms = med; best_block = b; best_chunk = c; best_tail = tl; best_cap = cap;
+      best_order = ord;
+    }
+    return CHEM_OK;
+  };
+  rc = CHEM_OK;
+  const int o0 = best_order;
+  {
+    // untimed calls first: the first launches after start-up run slow
+    // (clocks ramping), which would penalise whichever candidate comes first
+    chem_opts t = o;
+    t.block_size = best_block; t.chunk_steps = chunks[0]; t.tail_steps = best_tail;
+    t.tail_cap = best_cap; t.pool_order = o0;
+    for (int w = 0; w < 2 * reps + 2 && rc == CHEM_OK; ++w) {
+      float el = 0;
+      rc = time_one(t, &el);
+    }
+  }
+  for (int c : chunks)
+    if (rc == CHEM_OK) rc = consider(best_block, c, best_tail, best_cap, o0);
+  if (rc == CHEM_OK && best_ms < kTuneGridMs) {
+    // cheap calls: every (block, chunk) pair (coordinate descent can stop
+    // in a local optimum: a block that loses at one chunk may win at another)
+    const int b0 = best_block;  // its chunks were just timed
+    for (int b : blocks)
+      for (int c : chunks)
+        if (rc == CHEM_OK && b != b0) rc = consider(b, c, best_tail, best_cap, o0);
+  } else {
+    for (int b : blocks)
+      if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail, best_cap, o0);
+    const int b0 = best_block;
+    for (int c : chunks)
+      if (rc == CHEM_OK && c != best_chunk) rc = consider(b0, c, best_tail, best_cap, o0);
+  }
+  if (tune_tail) {
+    const int b0 = best_block, c0 = best_chunk, t0 = best_tail;
+    for (int tl : tails)
+      if (rc == CHEM_OK && tl != t0) rc = consider(b0, c0, tl, best_cap, o0);
+  }
+  if (tune_cap) {
+    const int b0 = best_block, c0 = best_chunk, t0 = best_tail, k0 = best_cap;
+    for (int tl : pair_tails)
+      for (int cap : caps)
+        if (rc == CHEM_OK && !(tl == t0 && cap == k0)) rc = consider(b0, c0, tl, cap, o0);
+  }
+  if (o.pool_order == 0 && o.fixed_steps == 0) {
+    // the two pool orders at the best launch so far
+    if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_DEAL);
+    if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_RANGE);
+  }
+  {
+    // the hand-off, the cap and the order move the balance between
+    // compaction and the tail (the first sweeps ran at the default hand-off,
+    // where a long tail list may go to the per-lane resumption), so block
+    // and chunk are swept once more at the final choice: the whole plane
+    // for cheap calls, else chunk, block, chunk
+    const int t0 = best_tail, k0 = best_cap, ob0 = best_order;
+    if (best_ms < kTuneGridMs) {
+      const int b1 = best_block, c1 = best_chunk;
+      for (int b : blocks)
+        for (int c : chunks)
+          if (rc == CHEM_OK && !(b == b1 && c == c1)) rc = consider(b, c, t0, k0, ob0);
+    } else {
+      const int b1 = best_block, c1 = best_chunk;
+      for (int c : chunks)
+        if (rc == CHEM_OK && c != c1) rc = consider(b1, c, t0, k0, ob0);
+      const int c2 = best_chunk, b2 = best_block;
+      for (int b : blocks)
+        if (rc == CHEM_OK && b != b2) rc = consider(b, c2, t0, k0, ob0);
+      const int b3 = best_block, c3 = best_chunk;
+      for (int c : chunks)
+        if (rc == CHEM_OK && c != c3) rc = consider(b3, c, t0, k0, ob0);
+    }
+  }
+  if (rc == CHEM_OK && seen.size() > 1) {
+    // confirmation round over the (up to) eight fastest distinct launches
+    std::stable_sort(seen.begin(), seen.end(),
+                     [](const Seen& x, const Seen& y) { return x.ms < y.ms; });
+    std::vector<Seen> top;
+    for (const Seen& v : seen) {
+      bool dup = false;
+      for (const Seen& w : top)
+        dup = dup || (w.b == v.b && w.c == v.c && w.tl == v.tl && w.cap == v.cap && w.ord == v.ord);
+      if (!dup) top.push_back(v);
+      if (top.size() == 8) break;
+    }
+    std::vector<std::vector<float>> ms(top.size());
+    for (int r = 0; r < 3 * reps + 1 && rc == CHEM_OK; ++r)
+      for (size_t k = 0; k < top.size() && rc == CHEM_OK; ++k) {
+        chem_opts t = o;
+        t.block_size = top[k].b; t.chunk_steps = top[k].c; t.tail_steps = top[k].tl;
+        t.tail_cap = top[k].cap; t.pool_order = top[k].ord;
+        float el = 0;
+        rc = time_one(t, &el);
+        ms[k].push_back(el);
+      }
+    if (rc == CHEM_OK) {
+      best_ms = 1e300;
+      for (size_t k = 0; k < top.size(); ++k) {
+        std::sort(ms[k].begin(), ms[k].end());
+        const double med = ms[k][ms[k].size() / 2];
+        if (med < best_ms) {
+          best_ms = med; best_block = top[k].b; best_chunk = top[k].c; best_tail = top[k].tl;
+          best_cap = top[k].cap; best_order = top[k].ord;
+        }
+      }
+    }
+  }
+  if (rc != CHEM_OK) return rc;
+  *best = o;
+  best->block_size = best_block; best->chunk_steps = best_chunk; best->tail_steps = best_tail;
+  best->tail_cap = best_cap; best->pool_order = best_order;
+  *best_ms_out = best_ms;
   return CHEM_OK;
 }
 
@@ -1672,180 +1857,21 @@ int chem_autotune(chem_mech m, const chem_box* boxes, int32_t n_boxes, const che
     if ((e = hipEventElapsedTime(el, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
     return CHEM_OK;
   };
-  // median time of `reps` calls of one configuration (after one untimed call)
-  auto trial = [&](const chem_opts& t, double* med) -> int {
-    std::vector<float> ms;
-    for (int r = 0; r <= reps; ++r) {
-      float el = 0;
-      const int trc = time_one(t, &el);
-      if (trc != CHEM_OK) return trc;
-      if (r > 0) ms.push_back(el);
-    }
-    std::sort(ms.begin(), ms.end());
-    *med = ms[ms.size() / 2];
-    return CHEM_OK;
-  };
-  // Coordinate descent: chunk at the default block, block at the best
-  // chunk, chunk again at the best block, then the hand-off point for the
-  // best pair, then hand-off point and cooperative cap together (an early
-  // hand-off only pays when the cap lets the cooperative kernel take the
-  // longer list), then the two pool orders, then block and chunk once more
-  // at the final hand-off, cap and order.  Each sweep keeps the incumbent
-  // unless a candidate is faster.  Finally the fastest few launches seen
-  // are timed again, round-robin and with more calls each, so that one
-  // noisy trial (a clock ramp, other work on the device) does not decide.
-  const int blocks[] = {64, 128, 192, 256, 384, 512};
-  const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
-  const int tails[] = {4, 8, 16, 32, 64, 128, 256, 512, -1};
-  const int pair_tails[] = {4, 8, 16, 32, 64};
-  // below this many ms per call the (block, chunk) plane is swept whole
-  constexpr double kTuneGridMs = 50.0;
-  struct Seen { int b, c, tl, cap, ord; double ms; };
-  std::vector<Seen> seen;
-  const int caps[] = {kDefaultTailCap, 128, 256, -1};
-  double best_ms = 1e300;
-  int best_block = kDefaultBlock, best_chunk = kDefaultChunk;
-  int best_tail = o.tail_steps != 0 ? o.tail_steps : kDefaultTail;
-  int best_cap = o.tail_cap != 0 ? o.tail_cap : kDefaultTailCap;
-  int best_order = o.pool_order != 0 ? o.pool_order : -1;
-  const bool tune_tail = o.tail_steps == 0 && o.fixed_steps == 0 && o.scheme == SCHEME_LSRK;
-  const bool tune_cap = tune_tail && o.tail_cap == 0;
-  auto consider = [&](int b, int c, int tl, int cap, int ord) -> int {
-    if (m->entry->lds_per_lane() * b > 65536) return CHEM_OK;
-    if (o.scheme == SCHEME_ROS4 && b > 256) return CHEM_OK;
-    chem_opts t = o;
-    t.block_size = b;
-    t.chunk_steps = c;
-    t.tail_steps = tl;
-    t.tail_cap = cap;
-    t.pool_order = ord;
-    double med = 0;
-    const int trc = trial(t, &med);
-    if (trc != CHEM_OK) return trc;
-    seen.push_back({b, c, tl, cap, ord, med});
-    if (med < best_ms) {
-      best_ms = med; best_block = b; best_chunk = c; best_tail = tl; best_cap = cap;
-      best_order = ord;
-    }
-    return CHEM_OK;
-  };
-  rc = CHEM_OK;
-  const int o0 = best_order;
-  {
-    // untimed calls first: the first launches after start-up run slow
-    // (clocks ramping), which would penalise whichever candidate comes first
-    chem_opts t = o;
-    t.block_size = best_block; t.chunk_steps = chunks[0]; t.tail_steps = best_tail;
-    t.tail_cap = best_cap; t.pool_order = o0;
-    for (int w = 0; w < 2 * reps + 2 && rc == CHEM_OK; ++w) {
-      float el = 0;
-      rc = time_one(t, &el);
-    }
-  }
-  for (int c : chunks)
-    if (rc == CHEM_OK) rc = consider(best_block, c, best_tail, best_cap, o0);
-  if (rc == CHEM_OK && best_ms < kTuneGridMs) {
-    // cheap calls: every (block, chunk) pair (coordinate descent can stop
-    // in a local optimum: a block that loses at one chunk may win at another)
-    const int b0 = best_block;  // its chunks were just timed
-    for (int b : blocks)
-      for (int c : chunks)
-        if (rc == CHEM_OK && b != b0) rc = consider(b, c, best_tail, best_cap, o0);
-  } else {
-    for (int b : blocks)
-      if (rc == CHEM_OK && b != best_block) rc = consider(b, best_chunk, best_tail, best_cap, o0);
-    const int b0 = best_block;
-    for (int c : chunks)
-      if (rc == CHEM_OK && c != best_chunk) rc = consider(b0, c, best_tail, best_cap, o0);
-  }
-  if (tune_tail) {
-    const int b0 = best_block, c0 = best_chunk, t0 = best_tail;
-    for (int tl : tails)
-      if (rc == CHEM_OK && tl != t0) rc = consider(b0, c0, tl, best_cap, o0);
-  }
-  if (tune_cap) {
-    const int b0 = best_block, c0 = best_chunk, t0 = best_tail, k0 = best_cap;
-    for (int tl : pair_tails)
-      for (int cap : caps)
-        if (rc == CHEM_OK && !(tl == t0 && cap == k0)) rc = consider(b0, c0, tl, cap, o0);
-  }
-  if (o.pool_order == 0 && o.fixed_steps == 0) {
-    // the two pool orders at the best launch so far
-    if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_DEAL);
-    if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_RANGE);
-  }
-  {
-    // the hand-off, the cap and the order move the balance between
-    // compaction and the tail (the first sweeps ran at the default hand-off,
-    // where a long tail list may go to the per-lane resumption), so block
-    // and chunk are swept once more at the final choice: the whole plane
-    // for cheap calls, else chunk, block, chunk
-    const int t0 = best_tail, k0 = best_cap, ob0 = best_order;
-    if (best_ms < kTuneGridMs) {
-      const int b1 = best_block, c1 = best_chunk;
-      for (int b : blocks)
-        for (int c : chunks)
-          if (rc == CHEM_OK && !(b == b1 && c == c1)) rc = consider(b, c, t0, k0, ob0);
-    } else {
-      const int b1 = best_block, c1 = best_chunk;
-      for (int c : chunks)
-        if (rc == CHEM_OK && c != c1) rc = consider(b1, c, t0, k0, ob0);
-      const int c2 = best_chunk, b2 = best_block;
-      for (int b : blocks)
-        if (rc == CHEM_OK && b != b2) rc = consider(b, c2, t0, k0, ob0);
-      const int b3 = best_block, c3 = best_chunk;
-      for (int c : chunks)
-        if (rc == CHEM_OK && c != c3) rc = consider(b3, c, t0, k0, ob0);
-    }
-  }
-  if (rc == CHEM_OK && seen.size() > 1) {
-    // confirmation round over the (up to) eight fastest distinct launches
-    std::stable_sort(seen.begin(), seen.end(),
-                     [](const Seen& x, const Seen& y) { return x.ms < y.ms; });
-    std::vector<Seen> top;
-    for (const Seen& v : seen) {
-      bool dup = false;
-      for (const Seen& w : top)
-        dup = dup || (w.b == v.b && w.c == v.c && w.tl == v.tl && w.cap == v.cap && w.ord == v.ord);
-      if (!dup) top.push_back(v);
-      if (top.size() == 8) break;
-    }
-    std::vector<std::vector<float>> ms(top.size());
-    for (int r = 0; r < 3 * reps + 1 && rc == CHEM_OK; ++r)
-      for (size_t k = 0; k < top.size() && rc == CHEM_OK; ++k) {
-        chem_opts t = o;
-        t.block_size = top[k].b; t.chunk_steps = top[k].c; t.tail_steps = top[k].tl;
-        t.tail_cap = top[k].cap; t.pool_order = top[k].ord;
-        float el = 0;
-        rc = time_one(t, &el);
-        ms[k].push_back(el);
-      }
-    if (rc == CHEM_OK) {
-      best_ms = 1e300;
-      for (size_t k = 0; k < top.size(); ++k) {
-        std::sort(ms[k].begin(), ms[k].end());
-        const double med = ms[k][ms[k].size() / 2];
-        if (med < best_ms) {
-          best_ms = med; best_block = top[k].b; best_chunk = top[k].c; best_tail = top[k].tl;
-          best_cap = top[k].cap; best_order = top[k].ord;
-        }
-      }
-    }
-  }
+  chem_opts found{};
+  double best_ms = 0.0;
+  rc = tune_search(m, o, reps, time_one, &found, &best_ms);
   if ((e = restore()) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "restore");
   if ((e = hipStreamSynchronize(s)) != hipSuccess && rc == CHEM_OK) rc = hip_fail(e, "autotune sync");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   cleanup();
   if (rc != CHEM_OK) return rc;
-  m->tuned[tkey] = {best_block, best_chunk, best_tail, best_cap, best_order};
-  if (best) {
-    *best = o; best->block_size = best_block; best->chunk_steps = best_chunk;
-    best->tail_steps = best_tail; best->tail_cap = best_cap; best->pool_order = best_order;
-  }
+  m->tuned[tkey] = {found.block_size, found.chunk_steps, found.tail_steps, found.tail_cap,
+                    found.pool_order};
+  if (best) *best = found;
   if (cache_path) {
-    cache.push_back(TuneEntry{key, best_block, best_chunk, best_tail, best_cap, best_order,
-                              best_ms});
+    cache.push_back(TuneEntry{key, found.block_size, found.chunk_steps, found.tail_steps,
+                              found.tail_cap, found.pool_order, best_ms});
     rc = write_cache(cache_path, cache);
   }
   return rc;

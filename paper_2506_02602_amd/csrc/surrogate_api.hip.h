@@ -24,21 +24,15 @@ struct chem_surr_s {
   float* part = nullptr;
   float* fwd_tmp = nullptr;               // surrogate_forward's standardised chunk
   double* sse = nullptr;
-  // inference fallback lists: cells failing the trust test after the network
-  // (fb_list) and cells outside the training hull found before it (hull_list,
-  // integrated on a side stream while the network runs), with the hull flags
-  // (all of them allocated by surrogate_reserve; surrogate_infer allocates nothing)
+  // the fallback list: cells outside the training hull, found by a pass
+  // ahead of the network (flagged in fb_flag so the network skips them),
+  // then the cells failing the trust test after it, appended by the
+  // inference kernel; one pool of the FP64 integrator takes the whole list
+  // (allocated by surrogate_reserve; surrogate_infer allocates nothing)
   int32_t* fb_list = nullptr;
   unsigned* fb_count = nullptr;
+  int8_t* fb_flag = nullptr;
   int64_t reserved = 0;
-  bool side_ready = false;
-  int32_t* hull_list = nullptr;
-  unsigned* hull_count = nullptr;
-  int8_t* hull_flag = nullptr;
-  unsigned long long* side_next = nullptr;  // the side stream's pool counter
-  TailStore side_tail;                      // and tail records
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -246,13 +240,8 @@ void surrogate_free(chem_surr s) {
   surr_free_batch(s);
   for (void* p : {(void*)s->theta, (void*)s->m, (void*)s->v, (void*)s->grad, (void*)s->wbf,
                   (void*)s->norm, (void*)s->wpack, (void*)s->bpack, (void*)s->Xn, (void*)s->Yn,
-                  (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count, (void*)s->hull_list,
-                  (void*)s->hull_count, (void*)s->hull_flag, (void*)s->side_next,
-                  s->side_tail.mem})
+                  (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count, (void*)s->fb_flag})
     if (p) (void)hipFree(p);
-  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
-  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
-  if (s->side) (void)hipStreamDestroy(s->side);
   delete s;
 }
 
@@ -444,31 +433,17 @@ int surrogate_train(chem_surr s, const float* X, const float* Y, int64_t n, int3
 
 int surrogate_reserve(chem_surr s, int64_t max_cells) {
   if (!s || max_cells < 0) return fail(CHEM_EINVAL, "surrogate_reserve: bad argument");
-  hipError_t e;
-  if (!s->side_ready) {
-    if ((e = dalloc(&s->hull_count, 1)) != hipSuccess) return hip_fail(e, "hipMalloc(hull count)");
-    if ((e = dalloc(&s->side_next, 1)) != hipSuccess) return hip_fail(e, "hipMalloc(pool counter)");
-    if ((e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming)) != hipSuccess)
-      return hip_fail(e, "hipEventCreate");
-    if ((e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking)) != hipSuccess)
-      return hip_fail(e, "hipStreamCreate(side)");
-    s->side_ready = true;
-  }
   if (max_cells <= s->reserved && s->fb_list) return CHEM_OK;
-  // growing: calls still queued may use the old lists
+  hipError_t e;
+  // growing: calls still queued may use the old list
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(surrogate)");
-  for (void* p : {(void*)s->fb_list, (void*)s->hull_list, (void*)s->hull_flag, s->side_tail.mem})
+  for (void* p : {(void*)s->fb_list, (void*)s->fb_flag})
     if (p) (void)hipFree(p);
-  s->fb_list = nullptr; s->hull_list = nullptr; s->hull_flag = nullptr;
-  s->side_tail = TailStore{};
+  s->fb_list = nullptr; s->fb_flag = nullptr;
   s->reserved = 0;
   const int64_t cap = std::max<int64_t>(max_cells, 1);
   if ((e = dalloc(&s->fb_list, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(fallback list)");
-  if ((e = dalloc(&s->hull_list, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(hull list)");
-  if ((e = dalloc(&s->hull_flag, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(hull flags)");
-  int rc = alloc_tail(s->side_tail, cap);
-  if (rc) return rc;
+  if ((e = dalloc(&s->fb_flag, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(hull flags)");
   s->reserved = max_cells;
   return CHEM_OK;
 }
@@ -489,21 +464,19 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (fallback) {
-    // the hull cells run on the side stream with the surrogate's lists and
-    // tail records, the other failures on `stream` with the mechanism's
-    // workspace: both reservations must cover n_cells
-    if (!s->side_ready || n_cells > s->reserved) {
+    // the fallback list is the surrogate's, the integrator's workspace the
+    // mechanism's: both reservations must cover n_cells
+    if (!s->fb_list || n_cells > s->reserved) {
       char msg[200];
       snprintf(msg, sizeof msg, "surrogate_infer: %lld cells but the surrogate is reserved for "
                "%lld (call surrogate_reserve first)", (long long)n_cells,
-               (long long)(s->side_ready ? s->reserved : 0));
+               (long long)(s->fb_list ? s->reserved : 0));
       return fail(CHEM_ECAPACITY, msg);
     }
     rc = check_capacity(m, n_cells, "surrogate_infer fallback");
     if (rc) return rc;
   }
   hipLaunchKernelGGL(surr::zero_u32, dim3(1), dim3(1), 0, st, s->fb_count);
-  if (fallback) hipLaunchKernelGGL(surr::zero_u32, dim3(1), dim3(1), 0, st, s->hull_count);
   if (n_cells > 0) {
     surr::InferArgs a{};
     a.state = state; a.ld = ld; a.n = n_cells; a.dt = dt;
@@ -513,54 +486,125 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
     a.fb_count = s->fb_count;
     a.trust_code = trust_code;
     a.out_std = out_std;
-    auto fallback_args = [&](const int32_t* list, const unsigned* count) {
-      PoolArgs pa{};
-      pa.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts, list};
-      pa.boxes = nullptr;
-      pa.n_boxes = 1;
-      pa.total = n_cells;
-      pa.total_dev = count;
-      pa.c = make_control(opts);
-      pa.fixed_steps = opts ? opts->fixed_steps : 0;
-      pa.scheme = opts ? opts->scheme : SCHEME_LSRK;
-      return pa;
-    };
     if (fallback) {
-      // cells outside the hull go to the FP64 integrator on the side stream
-      // while the network runs on the others (disjoint cells of one state)
-      e = m->entry->launch_surr_hull(a, s->hull_flag, s->hull_list, s->hull_count, st);
+      // cells outside the hull are listed first and skipped by the network
+      e = m->entry->launch_surr_hull(a, s->fb_flag, s->fb_list, s->fb_count, st);
       if (e != hipSuccess) return hip_fail(e, "launch surr_hull");
-      a.skip = s->hull_flag;
-      if ((e = hipEventRecord(s->ev_fork, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-      if ((e = hipStreamWaitEvent(s->side, s->ev_fork, 0)) != hipSuccess)
-        return hip_fail(e, "hipStreamWaitEvent");
-      PoolArgs ph = fallback_args(s->hull_list, s->hull_count);
-      // with kernel timing on, this run (the fallback's larger part) is the
-      // one timed
-      rc = run_pool_with(m, ph, opts, s->side, s->side_next, s->side_tail, nullptr, true);
-      if (rc) return rc;
-      if ((e = hipEventRecord(s->ev_join, s->side)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      a.skip = s->fb_flag;
     }
     e = m->entry->launch_surr_infer(a, m->n_cu, st);
     if (e != hipSuccess) return hip_fail(e, "launch surr_infer");
     if (fallback) {
-      PoolArgs pa = fallback_args(s->fb_list, s->fb_count);
-      rc = run_pool_with(m, pa, opts, st, m->d_next, m->tail, &m->order, false);
+      // one FP64 pool over the whole list, its size read on the device
+      PoolArgs pa{};
+      pa.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts, s->fb_list};
+      pa.boxes = nullptr;
+      pa.n_boxes = 1;
+      pa.total = n_cells;
+      pa.total_dev = s->fb_count;
+      pa.c = make_control(opts);
+      pa.fixed_steps = opts ? opts->fixed_steps : 0;
+      pa.scheme = opts ? opts->scheme : SCHEME_LSRK;
+      rc = run_pool_with(m, pa, opts, st, m->d_next, m->tail, &m->order, true);
       if (rc) return rc;
-      if ((e = hipStreamWaitEvent(st, s->ev_join, 0)) != hipSuccess)
-        return hip_fail(e, "hipStreamWaitEvent");
     }
   }
   if (n_fallback_host) {
-    unsigned cnt[2] = {0, 0};
-    e = hipMemcpyAsync(&cnt[0], s->fb_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && fallback && n_cells > 0)
-      e = hipMemcpyAsync(&cnt[1], s->hull_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    unsigned cnt = 0;
+    e = hipMemcpyAsync(&cnt, s->fb_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "surrogate_infer count copy");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "surrogate_infer sync");
-    *n_fallback_host = (int64_t)cnt[0] + cnt[1];
+    *n_fallback_host = (int64_t)cnt;
   }
   return CHEM_OK;
+}
+
+int surrogate_autotune(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t n_cells,
+                       double dt, const double trust[4], const chem_opts* base, int32_t reps,
+                       const char* cache_path, void* stream, chem_opts* best) {
+  if (!s || !m || !trust || !best) return fail(CHEM_EINVAL, "surrogate_autotune: null argument");
+  if (m->entry != s->mech->entry)
+    return fail(CHEM_EINVAL, "surrogate_autotune: surrogate built for another mechanism");
+  if (n_cells <= 0 || ld < n_cells || !state)
+    return fail(CHEM_EINVAL, "surrogate_autotune: need 0 < n_cells <= ld and a state");
+  int rc = check_opts(base);
+  if (rc) return rc;
+  if (reps < 1) reps = 3;
+  hipStream_t st = (hipStream_t)stream;
+  char key[180];
+  snprintf(key, sizeof key, "%016llx:%d:%s%s:surrogate", (unsigned long long)m->entry->hash,
+           size_bucket(n_cells), arch_name(m->device).c_str(),
+           (base && base->scheme == SCHEME_RKF45)  ? ":rkf45"
+           : (base && base->scheme == SCHEME_ROS4) ? ":ros4"
+                                                   : "");
+  const chem_opts o = base ? *base : chem_opts{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<TuneEntry> cache;
+  if (cache_path) {
+    cache = read_cache(cache_path);
+    for (const auto& en : cache)
+      if (en.key == key) {
+        *best = o; best->block_size = en.block; best->chunk_steps = en.chunk;
+        best->tail_steps = en.tail; best->tail_cap = en.cap; best->pool_order = en.order;
+        return CHEM_OK;
+      }
+  }
+  // the trials are surrogate_infer calls: both reservations must cover them
+  if (!m->fixed_ready || n_cells > m->reserved) {
+    rc = chem_workspace_reserve(m, std::max<int64_t>(n_cells, m->reserved));
+    if (rc) return rc;
+  }
+  if (!s->fb_list || n_cells > s->reserved) {
+    rc = surrogate_reserve(s, std::max<int64_t>(n_cells, s->reserved));
+    if (rc) return rc;
+  }
+  // a snapshot of the caller's state, restored before every trial and at
+  // the end
+  const size_t bytes = sizeof(double) * (size_t)ld * (size_t)(m->entry->ns + 3);
+  double* snap = nullptr;
+  hipError_t e = hipMalloc(&snap, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(surrogate_autotune snapshot)");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(snap);
+  };
+  if ((e = hipMemcpyAsync(snap, state, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+      (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    cleanup();
+    return hip_fail(e, "surrogate_autotune set-up");
+  }
+  auto time_one = [&](const chem_opts& t, float* el) -> int {
+    if ((e = hipMemcpyAsync(state, snap, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+      return hip_fail(e, "restore");
+    if ((e = hipEventRecord(e0, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    const int trc = surrogate_infer(s, m, state, ld, n_cells, dt, trust, 1, &t, stream, nullptr,
+                                    nullptr, nullptr, nullptr, nullptr);
+    if (trc != CHEM_OK) return trc;
+    if ((e = hipEventRecord(e1, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "trial");
+    *el = 0;
+    if ((e = hipEventElapsedTime(el, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    return CHEM_OK;
+  };
+  chem_opts found{};
+  double best_ms = 0.0;
+  rc = tune_search(m, o, reps, time_one, &found, &best_ms);
+  if ((e = hipMemcpyAsync(state, snap, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess &&
+      rc == CHEM_OK)
+    rc = hip_fail(e, "restore");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess && rc == CHEM_OK)
+    rc = hip_fail(e, "surrogate_autotune sync");
+  cleanup();
+  if (rc != CHEM_OK) return rc;
+  *best = found;
+  if (cache_path) {
+    cache.push_back(TuneEntry{key, found.block_size, found.chunk_steps, found.tail_steps,
+                              found.tail_cap, found.pool_order, best_ms});
+    rc = write_cache(cache_path, cache);
+  }
+  return rc;
 }
 
 int surrogate_save(chem_surr s, const char* path) {

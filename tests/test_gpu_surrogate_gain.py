@@ -96,3 +96,54 @@ def test_out_of_hull_cells_fall_back_to_fp64(trained):
     fb = tc != 0
     assert n_fb == int(fb.sum()) and n_fb >= int(out.sum()) * 0.9
     assert torch.equal(work[:, fb], ref[:, fb])         # the FP64 path decided those cells
+
+
+def test_fallback_launch_tuned_on_the_surrogate_step(trained, tmp_path):
+    """surrogate_autotune: the launch of the FP64 fallback is searched on
+    whole surrogate steps over the field; the field is restored, the result
+    is cached under its own key (a second call is a hit that tunes nothing),
+    and surrogate_infer with the tuned launch sends the same cells to the
+    fallback and finishes them within the parity budget of the default
+    launch's result."""
+    import json
+    import torch
+    from gpu_common import check_flagged
+    from paper_2506_02602_amd import chemgpu as cg, surrogate as sg
+    m, s, trust, _ = trained
+    field, out = sg.inference_field(m, shape=(64, 64, 64), n_traj=128, n_records=200, seed=25,
+                                    out_frac=0.1)
+    n = field.shape[1]
+    keep = field.clone()
+    cache = str(tmp_path / "tune.json")
+    base = cg.make_opts(rtol=1e-8, atol=1e-10)
+    tuned = cg.surrogate_autotune(s, m, field, 1e-7, trust, base, reps=1, cache_path=cache)
+    torch.cuda.synchronize()
+    assert torch.equal(field, keep)
+    entries = json.load(open(cache))["entries"]
+    assert len(entries) == 1 and entries[0]["key"].endswith(":surrogate")
+    assert tuned.block_size > 0 and tuned.chunk_steps != 0 and tuned.tail_steps != 0
+    before = open(cache).read()
+    again = cg.surrogate_autotune(s, m, field, 1e-7, trust, base, reps=1, cache_path=cache)
+    assert open(cache).read() == before
+    assert (again.block_size, again.chunk_steps, again.tail_steps, again.tail_cap,
+            again.pool_order) == (tuned.block_size, tuned.chunk_steps, tuned.tail_steps,
+                                  tuned.tail_cap, tuned.pool_order)
+    print(f"[gain] tuned fallback launch: block {tuned.block_size} chunk {tuned.chunk_steps} "
+          f"tail {tuned.tail_steps} cap {tuned.tail_cap} order {tuned.pool_order}", flush=True)
+    results = []
+    for opts in (base, tuned):
+        work = field.clone()
+        tc = torch.zeros(n, dtype=torch.int32, device="cuda")
+        st = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        cg.surrogate_infer(s, m, work, 1e-7, trust, fallback=True, opts=opts, trust_code=tc,
+                           status=st)
+        torch.cuda.synchronize()
+        results.append((work.cpu().numpy(), tc.cpu().numpy(), st.cpu().numpy()))
+    (w0, c0, s0), (w1, c1, s1) = results
+    assert np.array_equal(c0, c1)
+    fb = c0 != 0
+    assert fb.sum() >= int(out.sum()) * 0.9
+    assert np.array_equal(s0[fb], s1[fb]) and (s1[fb] == 0).all()
+    assert np.array_equal(w0[:, ~fb], w1[:, ~fb])       # trusted cells: the network's result
+    check_flagged(np.ascontiguousarray(w1[:, fb]), np.ascontiguousarray(w0[:, fb]), m.n_species,
+                  "front_hot", label="tuned fallback launch vs default")
