@@ -367,8 +367,8 @@ int surrogate_grad(chem_surr s, const float *Xn, const float *Yn, int32_t B, flo
 
 /*
  * Allocate what surrogate_infer with fallback needs for up to max_cells
- * cells: the fallback list and the out-of-hull flags (5 B per cell; the
- * fallback's integration uses the mechanism's workspace).  Growing it
+ * cells: the fallback list (4 B per cell; the fallback's integration uses
+ * the mechanism's workspace).  Growing it
  * first waits for the whole device.  CHEM_EINVAL for a null handle or
  * max_cells < 0.
  */
@@ -382,12 +382,14 @@ int surrogate_reserve(chem_surr s, int64_t max_cells);
  * allows Y + dY down to -pos_tol, the write clips it to 0).  Untrusted cells keep their
  * state and, if `fallback` is non-zero, are integrated from it by the FP64
  * LSRK path (opts as for chem_integrate) in the same stream, with no host
- * round trip: cells outside the training hull are listed by a pass ahead of
- * the network (which skips them), the network appends the cells failing
- * the rest of the test, and one pool of the persistent kernel takes the
- * device-side list.  Optional
+ * round trip: the inference kernel appends the untrusted cells to a
+ * device-side list that one pool of the persistent kernel then takes.
+ * With fallback, a cell outside the training hull is decided by that
+ * criterion alone (trust code CHEM_TRUST_HULL, the others not evaluated),
+ * and a 64-cell tile holding only such cells skips the network.  Optional
  * device outputs: trust_code int32[n] (CHEM_TRUST_* bits), out_std
- * float[n][N+1] (raw network outputs), status / counts (as chem_integrate,
+ * float[n][N+1] (raw network outputs; not written for a skipped tile),
+ * status / counts (as chem_integrate,
  * written for fallback cells only).  n_fallback_host (may be NULL) receives
  * the number of untrusted cells and then the call synchronises `stream`.
  * Allocates nothing: with fallback, n_cells must be within both the

@@ -556,7 +556,6 @@ struct MechEntry {
   int (*max_blocks_per_cu)(int block, int scheme);
   size_t (*lds_per_lane)();
   hipError_t (*launch_surr_infer)(const surr::InferArgs&, int grid, hipStream_t);
-  hipError_t (*launch_surr_hull)(const surr::InferArgs&, int8_t*, int32_t*, unsigned*, hipStream_t);
   hipError_t (*launch_make_pairs)(const double*, const double*, long, long, double, const double*,
                                   float*, float*, hipStream_t);
 };
@@ -685,7 +684,7 @@ size_t lds_per_lane() {
                        &launch_direct<M>, &launch_persistent<M>, \
                        &launch_coop<M>, &launch_cons_to_prim<M>, &launch_prim_to_cons<M>, \
                        &max_blocks_per_cu<M>, &lds_per_lane<M>, \
-                       &launch_surr_infer<M>, &launch_surr_hull<M>, &launch_make_pairs<M>},
+                       &launch_surr_infer<M>, &launch_make_pairs<M>},
 const MechEntry g_registry[] = {CHEM_FOR_EACH_MECH(CHEM_ENTRY)};
 #undef CHEM_ENTRY
 

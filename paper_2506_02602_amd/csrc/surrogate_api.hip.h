@@ -24,14 +24,11 @@ struct chem_surr_s {
   float* part = nullptr;
   float* fwd_tmp = nullptr;               // surrogate_forward's standardised chunk
   double* sse = nullptr;
-  // the fallback list: cells outside the training hull, found by a pass
-  // ahead of the network (flagged in fb_flag so the network skips them),
-  // then the cells failing the trust test after it, appended by the
+  // the fallback list: the cells failing the trust test, appended by the
   // inference kernel; one pool of the FP64 integrator takes the whole list
   // (allocated by surrogate_reserve; surrogate_infer allocates nothing)
   int32_t* fb_list = nullptr;
   unsigned* fb_count = nullptr;
-  int8_t* fb_flag = nullptr;
   int64_t reserved = 0;
 };
 
@@ -240,7 +237,7 @@ void surrogate_free(chem_surr s) {
   surr_free_batch(s);
   for (void* p : {(void*)s->theta, (void*)s->m, (void*)s->v, (void*)s->grad, (void*)s->wbf,
                   (void*)s->norm, (void*)s->wpack, (void*)s->bpack, (void*)s->Xn, (void*)s->Yn,
-                  (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count, (void*)s->fb_flag})
+                  (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count})
     if (p) (void)hipFree(p);
   delete s;
 }
@@ -437,13 +434,11 @@ int surrogate_reserve(chem_surr s, int64_t max_cells) {
   hipError_t e;
   // growing: calls still queued may use the old list
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(surrogate)");
-  for (void* p : {(void*)s->fb_list, (void*)s->fb_flag})
-    if (p) (void)hipFree(p);
-  s->fb_list = nullptr; s->fb_flag = nullptr;
+  if (s->fb_list) (void)hipFree(s->fb_list);
+  s->fb_list = nullptr;
   s->reserved = 0;
   const int64_t cap = std::max<int64_t>(max_cells, 1);
   if ((e = dalloc(&s->fb_list, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(fallback list)");
-  if ((e = dalloc(&s->fb_flag, cap)) != hipSuccess) return hip_fail(e, "hipMalloc(hull flags)");
   s->reserved = max_cells;
   return CHEM_OK;
 }
@@ -486,12 +481,6 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
     a.fb_count = s->fb_count;
     a.trust_code = trust_code;
     a.out_std = out_std;
-    if (fallback) {
-      // cells outside the hull are listed first and skipped by the network
-      e = m->entry->launch_surr_hull(a, s->fb_flag, s->fb_list, s->fb_count, st);
-      if (e != hipSuccess) return hip_fail(e, "launch surr_hull");
-      a.skip = s->fb_flag;
-    }
     e = m->entry->launch_surr_infer(a, m->n_cu, st);
     if (e != hipSuccess) return hip_fail(e, "launch surr_infer");
     if (fallback) {

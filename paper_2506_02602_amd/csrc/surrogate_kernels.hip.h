@@ -305,7 +305,6 @@ struct InferArgs {
   double hull_margin, elem_tol, pos_tol, energy_tol;
   int32_t* fb_list; unsigned* fb_count;
   int32_t* trust_code; float* out_std;
-  const int8_t* skip;           // NULL, or 1 for cells the hull pass already sent to FP64
 };
 
 enum { TRUST_HULL = 1, TRUST_ELEM = 2, TRUST_POS = 4, TRUST_ENERGY = 8, TRUST_NONFINITE = 16 };
@@ -347,6 +346,19 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Append this wave's cells with `fall` set to the fallback list (when there
+// is one): one atomic per wave, positions in lane order.
+__device__ __forceinline__ void append_fallback(const InferArgs& a, bool fall, int lane, long cell) {
+  if (!a.fb_list) return;
+  const unsigned long long ball = __ballot(fall);
+  if (!ball) return;
+  const int leader = __ffsll((long long)ball) - 1;
+  unsigned base_idx = 0;
+  if (lane == leader) base_idx = atomicAdd(a.fb_count, (unsigned)__popcll(ball));
+  base_idx = __shfl(base_idx, leader);
+  if (fall) a.fb_list[base_idx + __popcll(ball & ((1ull << lane) - 1ull))] = (int32_t)cell;
+}
+
 // Fused inference: FP64 features -> BF16 MFMA MLP (weights in LDS, shared by
 // the block; hidden activations never leave registers) -> FP64 trust test ->
 // either the new state or an entry in the fallback list for the FP64
@@ -379,11 +391,12 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
   const float* zmin = a.norm + 2 * NI + 2 * NO;
   const float* zmax = zmin + NI;
 
+  const double ln_dt = log(a.dt);
   const long ntiles = (a.n + 63) / 64;
   for (long tile = (long)blockIdx.x * S::WAVES + wave; tile < ntiles;
        tile += (long)gridDim.x * S::WAVES) {
     const long cell = tile * 64 + lane;
-    const bool valid = cell < a.n && !(a.skip && a.skip[cell]);
+    const bool valid = cell < a.n;
     int code = 0;
     // ---- stage 0: this lane's cell features (FP64), standardised, BF16 to LDS
     {
@@ -402,7 +415,7 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
         const double rho = a.state[(NS + 1) * a.ld + cell];
         f[0] = T;
         f[1] = log(rho * 8.31446261815324e7 * T * sy);
-        f[2] = log(a.dt);
+        f[2] = ln_dt;
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
           const double z = sd_in[k] > 0.f ? (f[k] - (double)mu_in[k]) / (double)sd_in[k] : 0.0;
@@ -423,6 +436,15 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
         }
         *reinterpret_cast<v8s*>(stage + lane * S::CELL_B + 16 * q) = v;
       }
+    }
+    // with a fallback, a cell outside the hull is decided by that criterion
+    // alone (code TRUST_HULL); a tile of such cells skips the network
+    const bool decided = a.fb_list && (code & TRUST_HULL);
+    if (!__any(valid && !decided)) {
+      if (valid && a.trust_code) a.trust_code[cell] = code;
+      append_fallback(a, valid, lane, cell);
+      wave_sync();
+      continue;
     }
     wave_sync();
     // ---- stage 1: the MLP on this wave's 64 cells, in two halves of 32
@@ -498,7 +520,10 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
     wave_sync();
     // ---- stage 2: de-standardise and trust-test this lane's cell (FP64)
     bool fall = false;
-    if (valid) {
+    if (valid && decided) {
+      if (a.trust_code) a.trust_code[cell] = code;
+      fall = true;
+    } else if (valid) {
       double inc[NO];
       bool fin = true;
 #pragma unroll
@@ -545,66 +570,8 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
         fall = true;
       }
     }
-    if (a.fb_list) {
-      const unsigned long long ball = __ballot(fall);
-      if (ball) {
-        const int cnt = __popcll(ball);
-        const int leader = __ffsll((long long)ball) - 1;
-        unsigned base_idx = 0;
-        if (lane == leader) base_idx = atomicAdd(a.fb_count, (unsigned)cnt);
-        base_idx = __shfl(base_idx, leader);
-        if (fall) a.fb_list[base_idx + __popcll(ball & ((1ull << lane) - 1ull))] = (int32_t)cell;
-      }
-    }
+    append_fallback(a, fall, lane, cell);
     wave_sync();
-  }
-}
-
-// The trust test's first criterion alone, ahead of the network: a cell whose
-// standardised features leave the training hull (with margin), or are not
-// finite, is flagged and queued for the FP64 integrator at once (ballot +
-// one atomic per wave), so that its integration can overlap the inference
-// of the other cells.  Its trust code is TRUST_HULL.
-template <class M>
-__global__ void surr_hull(InferArgs a, int8_t* flag, int32_t* list, unsigned* count) {
-  constexpr int NS = M::NS, NI = NS + 3;
-  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  bool out = false;
-  if (cell < a.n) {
-    const float* mu_in = a.norm;
-    const float* sd_in = a.norm + NI;
-    const float* zmin = a.norm + 2 * NI + 2 * (NS + 1);
-    const float* zmax = zmin + NI;
-    double f[NI];
-    const double T = a.state[cell];
-    double sy = 0.0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const double y = a.state[(k + 1) * a.ld + cell];
-      f[3 + k] = y;
-      sy += y * (1.0 / M::W[k]);
-    }
-    const double rho = a.state[(NS + 1) * a.ld + cell];
-    f[0] = T;
-    f[1] = log(rho * 8.31446261815324e7 * T * sy);
-    f[2] = log(a.dt);
-#pragma unroll
-    for (int k = 0; k < NI; ++k) {
-      const double z = sd_in[k] > 0.f ? (f[k] - (double)mu_in[k]) / (double)sd_in[k] : 0.0;
-      if (!(z >= (double)zmin[k] - a.hull_margin && z <= (double)zmax[k] + a.hull_margin))
-        out = true;
-    }
-    flag[cell] = out ? 1 : 0;
-    if (out && a.trust_code) a.trust_code[cell] = TRUST_HULL;
-  }
-  const unsigned long long ball = __ballot(out);
-  if (ball) {
-    const int leader = __ffsll((long long)ball) - 1;
-    unsigned base_idx = 0;
-    if (lane == leader) base_idx = atomicAdd(count, (unsigned)__popcll(ball));
-    base_idx = __shfl(base_idx, leader);
-    if (out) list[base_idx + __popcll(ball & ((1ull << lane) - 1ull))] = (int32_t)cell;
   }
 }
 
@@ -647,15 +614,6 @@ hipError_t launch_surr_infer(const surr::InferArgs& a, int grid, hipStream_t s) 
   const long need = (a.n + S::THREADS - 1) / S::THREADS;
   grid = (int)(need < grid ? (need > 0 ? need : 1) : grid);
   hipLaunchKernelGGL(surr::surr_infer<M>, dim3(grid), dim3(S::THREADS), S::BYTES, s, a);
-  return hipGetLastError();
-}
-
-template <class M>
-hipError_t launch_surr_hull(const surr::InferArgs& a, int8_t* flag, int32_t* list, unsigned* count,
-                            hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(surr::surr_hull<M>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a,
-                     flag, list, count);
   return hipGetLastError();
 }
 

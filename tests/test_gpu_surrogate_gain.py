@@ -96,6 +96,8 @@ def test_out_of_hull_cells_fall_back_to_fp64(trained):
     fb = tc != 0
     assert n_fb == int(fb.sum()) and n_fb >= int(out.sum()) * 0.9
     assert torch.equal(work[:, fb], ref[:, fb])         # the FP64 path decided those cells
+    hull = (tc & cg.TRUST_HULL) != 0                    # decided by the hull alone
+    assert int(hull.sum()) > 0 and bool((tc[hull] == cg.TRUST_HULL).all())
 
 
 def test_fallback_launch_tuned_on_the_surrogate_step(trained, tmp_path):
