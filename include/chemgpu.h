@@ -28,7 +28,7 @@
  * call on more cells than the reservation holds returns CHEM_ECAPACITY and
  * enqueues nothing.  Only the set-up calls allocate: chem_workspace_reserve,
  * surrogate_create/reserve/train/grad/forward, chem_autotune,
- * surrogate_autotune and chem_graph_capture_batched.
+ * surrogate_autotune, chem_graph_capture_batched and surrogate_graph_capture.
  */
 #ifndef CHEMGPU_H
 #define CHEMGPU_H
@@ -420,6 +420,25 @@ int surrogate_infer(chem_surr s, chem_mech m, double *state, int64_t ld, int64_t
 int surrogate_autotune(chem_surr s, chem_mech m, double *state, int64_t ld, int64_t n_cells,
                        double dt, const double trust[4], const chem_opts *base, int32_t reps,
                        const char *cache_path, void *stream, chem_opts *best);
+
+/*
+ * Capture one surrogate step with fallback (surrogate_infer with
+ * fallback = 1 on this block, dt, trust and opts; no trust codes, outputs,
+ * status or counts) into a HIP graph launched with chem_graph_launch and
+ * freed with chem_graph_destroy: the inference kernel, then the FP64 pool
+ * over the device-side list, whose length the kernels read when they run
+ * (no memset nodes, no host round trip).  The graph owns its fallback list
+ * and its pool's counter, tail records and order, so its launches may
+ * follow eager calls on the same handles on one stream; two launches of one
+ * graph must not overlap.  It uses the surrogate's weights and the
+ * mechanism's tables as they are when launched.  A set-up call: allocates
+ * (about 44 B per cell) and synchronises `stream` before capturing on a
+ * private stream.  CHEM_EINVAL for null arguments, n_cells <= 0 or
+ * ld < n_cells.
+ */
+int surrogate_graph_capture(chem_surr s, chem_mech m, double *state, int64_t ld, int64_t n_cells,
+                            double dt, const double trust[4], const chem_opts *opts, void *stream,
+                            chem_graph *out);
 
 /* Save / load parameters and normaliser (binary; tied to the mechanism hash). */
 int surrogate_save(chem_surr s, const char *path);

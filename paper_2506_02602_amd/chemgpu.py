@@ -242,6 +242,9 @@ _lib.surrogate_infer.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_double, C
                                  C.c_int32, C.POINTER(chem_opts), _P, _P, _P, _P, _P,
                                  C.POINTER(C.c_int64)]
 _lib.surrogate_reserve.argtypes = [_P, C.c_int64]
+_lib.surrogate_graph_capture.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_double,
+                                         C.POINTER(C.c_double), C.POINTER(chem_opts), _P,
+                                         C.POINTER(_P)]
 _lib.surrogate_autotune.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_double,
                                     C.POINTER(C.c_double), C.POINTER(chem_opts), C.c_int32,
                                     C.c_char_p, _P, C.POINTER(chem_opts)]
@@ -395,6 +398,20 @@ def surrogate_autotune(s: Surrogate, mech: Mechanism, state, dt, trust, base=Non
     return best
 
 
+def surrogate_graph_capture(s: Surrogate, mech: Mechanism, state, dt, trust, opts=None,
+                            stream=None, n_cells=None) -> Graph:
+    """One surrogate step with fallback on `state`, captured (``chem_graph``)."""
+    ld = state.shape[1]
+    n = ld if n_cells is None else int(n_cells)
+    tr = (C.c_double * 4)(*[float(x) for x in trust])
+    o = opts if opts is not None else make_opts()
+    h = _P()
+    _check(_lib.surrogate_graph_capture(s.handle, mech.handle, state.data_ptr(), ld, n, float(dt),
+                                        tr, C.byref(o), _stream(stream), C.byref(h)),
+           "surrogate_graph_capture")
+    return Graph(mech, [state, s], handle=h)
+
+
 def surrogate_save(s: Surrogate, path: str) -> None:
     _check(_lib.surrogate_save(s.handle, path.encode()), "surrogate_save")
 
@@ -429,9 +446,14 @@ def chem_integrate_batched(mech: Mechanism, boxes, opts: chem_opts | None = None
 
 
 class Graph:
-    """A captured batched call (``chem_graph``)."""
+    """A captured batched call or surrogate step (``chem_graph``)."""
 
-    def __init__(self, mech: Mechanism, boxes, opts: chem_opts | None = None, stream=None):
+    def __init__(self, mech: Mechanism, boxes, opts: chem_opts | None = None, stream=None,
+                 handle=None):
+        if handle is not None:
+            self.handle = handle
+            self._keep = boxes
+            return
         arr = make_boxes(boxes)
         o = opts if opts is not None else make_opts()
         h = _P()
@@ -531,4 +553,5 @@ def exported_symbols():
             "surrogate_grad", "surrogate_infer", "surrogate_save", "surrogate_load",
             "surrogate_free", "chem_eval_exp", "chem_eval_math", "chem_react_conserved",
             "chem_set_kernel_timing", "chem_kernel_times", "surrogate_reserve",
-            "chem_integrate_noalloc", "chem_tail_stats", "surrogate_autotune"]
+            "chem_integrate_noalloc", "chem_tail_stats", "surrogate_autotune",
+            "surrogate_graph_capture"]

@@ -818,6 +818,8 @@ struct chem_graph_s {
   hipGraphExec_t exec = nullptr;
   BoxDesc* d_boxes = nullptr;
   unsigned long long* d_next = nullptr;
+  int32_t* fb_list = nullptr;    // a captured surrogate step's fallback list
+  unsigned* fb_count = nullptr;  // and its length
 };
 
 namespace {
@@ -1777,6 +1779,8 @@ void chem_graph_destroy(chem_graph g) {
   if (g->d_next) (void)hipFree(g->d_next);
   if (g->tail.mem) (void)hipFree(g->tail.mem);
   if (g->order.mem) (void)hipFree(g->order.mem);
+  if (g->fb_list) (void)hipFree(g->fb_list);
+  if (g->fb_count) (void)hipFree(g->fb_count);
   delete g;
 }
 

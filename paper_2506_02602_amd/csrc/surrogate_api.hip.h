@@ -175,6 +175,49 @@ int surr_pack(chem_surr s, hipStream_t st) {
   return CHEM_OK;
 }
 
+// Where one surrogate step keeps its fallback list and the fallback pool's
+// counter, tail records and order: the surrogate's and mechanism's own for
+// surrogate_infer, a graph's own for a captured step.
+struct StepBufs {
+  int32_t* fb_list;
+  unsigned* fb_count;
+  unsigned long long* next;
+  TailStore* tail;
+  OrderStore* order;
+};
+
+// Enqueue one surrogate step on `st`: zero the list, the fused inference
+// (appending untrusted cells when `fallback`), then one FP64 pool over the
+// list, its size read on the device.
+int enqueue_step(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t n_cells, double dt,
+                 const double trust[4], bool fallback, const chem_opts* opts, hipStream_t st,
+                 int32_t* trust_code, float* out_std, int32_t* status, int32_t* counts,
+                 const StepBufs& b, bool timed) {
+  hipLaunchKernelGGL(surr::zero_u32, dim3(1), dim3(1), 0, st, b.fb_count);
+  if (n_cells <= 0) return CHEM_OK;
+  surr::InferArgs a{};
+  a.state = state; a.ld = ld; a.n = n_cells; a.dt = dt;
+  a.wpack = s->wpack; a.bpack = s->bpack; a.norm = s->norm;
+  a.hull_margin = trust[0]; a.elem_tol = trust[1]; a.pos_tol = trust[2]; a.energy_tol = trust[3];
+  a.fb_list = fallback ? b.fb_list : nullptr;
+  a.fb_count = b.fb_count;
+  a.trust_code = trust_code;
+  a.out_std = out_std;
+  hipError_t e = m->entry->launch_surr_infer(a, m->n_cu, st);
+  if (e != hipSuccess) return hip_fail(e, "launch surr_infer");
+  if (!fallback) return CHEM_OK;
+  PoolArgs pa{};
+  pa.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts, b.fb_list};
+  pa.boxes = nullptr;
+  pa.n_boxes = 1;
+  pa.total = n_cells;
+  pa.total_dev = b.fb_count;
+  pa.c = make_control(opts);
+  pa.fixed_steps = opts ? opts->fixed_steps : 0;
+  pa.scheme = opts ? opts->scheme : SCHEME_LSRK;
+  return run_pool_with(m, pa, opts, st, b.next, *b.tail, b.order, timed);
+}
+
 }  // namespace
 
 extern "C" {
@@ -471,33 +514,10 @@ int surrogate_infer(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t
     rc = check_capacity(m, n_cells, "surrogate_infer fallback");
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(surr::zero_u32, dim3(1), dim3(1), 0, st, s->fb_count);
-  if (n_cells > 0) {
-    surr::InferArgs a{};
-    a.state = state; a.ld = ld; a.n = n_cells; a.dt = dt;
-    a.wpack = s->wpack; a.bpack = s->bpack; a.norm = s->norm;
-    a.hull_margin = trust[0]; a.elem_tol = trust[1]; a.pos_tol = trust[2]; a.energy_tol = trust[3];
-    a.fb_list = fallback ? s->fb_list : nullptr;
-    a.fb_count = s->fb_count;
-    a.trust_code = trust_code;
-    a.out_std = out_std;
-    e = m->entry->launch_surr_infer(a, m->n_cu, st);
-    if (e != hipSuccess) return hip_fail(e, "launch surr_infer");
-    if (fallback) {
-      // one FP64 pool over the whole list, its size read on the device
-      PoolArgs pa{};
-      pa.one = BoxDesc{state, ld, n_cells, 0, dt, 1, 0, status, counts, s->fb_list};
-      pa.boxes = nullptr;
-      pa.n_boxes = 1;
-      pa.total = n_cells;
-      pa.total_dev = s->fb_count;
-      pa.c = make_control(opts);
-      pa.fixed_steps = opts ? opts->fixed_steps : 0;
-      pa.scheme = opts ? opts->scheme : SCHEME_LSRK;
-      rc = run_pool_with(m, pa, opts, st, m->d_next, m->tail, &m->order, true);
-      if (rc) return rc;
-    }
-  }
+  StepBufs b{s->fb_list, s->fb_count, m->d_next, &m->tail, &m->order};
+  rc = enqueue_step(s, m, state, ld, n_cells, dt, trust, fallback != 0, opts, st, trust_code,
+                    out_std, status, counts, b, true);
+  if (rc) return rc;
   if (n_fallback_host) {
     unsigned cnt = 0;
     e = hipMemcpyAsync(&cnt, s->fb_count, sizeof(unsigned), hipMemcpyDeviceToHost, st);
@@ -594,6 +614,69 @@ int surrogate_autotune(chem_surr s, chem_mech m, double* state, int64_t ld, int6
     rc = write_cache(cache_path, cache);
   }
   return rc;
+}
+
+int surrogate_graph_capture(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t n_cells,
+                            double dt, const double trust[4], const chem_opts* opts, void* stream,
+                            chem_graph* out) {
+  if (!s || !m || !trust || !out) return fail(CHEM_EINVAL, "surrogate_graph_capture: null argument");
+  *out = nullptr;
+  if (m->entry != s->mech->entry)
+    return fail(CHEM_EINVAL, "surrogate_graph_capture: surrogate built for another mechanism");
+  if (n_cells <= 0 || ld < n_cells || !state)
+    return fail(CHEM_EINVAL, "surrogate_graph_capture: need 0 < n_cells <= ld and a state");
+  if (n_cells > 0x7fffffff) return fail(CHEM_EINVAL, "more than 2^31-1 cells");
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (!s->packed) return fail(CHEM_EINVAL, "surrogate_graph_capture: weights not packed");
+  chem_graph g = new (std::nothrow) chem_graph_s();
+  if (!g) return fail(CHEM_ENOMEM, "surrogate_graph_capture: host allocation");
+  auto bail = [&](hipError_t e, const char* what) {
+    chem_graph_destroy(g);
+    return hip_fail(e, what);
+  };
+  // the graph's own list, pool counter, tail records and order, so that its
+  // launches and eager calls on the same handles do not share them
+  hipError_t e;
+  if ((e = dalloc(&g->fb_list, n_cells)) != hipSuccess) return bail(e, "hipMalloc(graph fallback list)");
+  if ((e = dalloc(&g->fb_count, 1)) != hipSuccess) return bail(e, "hipMalloc(graph list length)");
+  if ((e = hipMalloc(&g->d_next, sizeof(unsigned long long))) != hipSuccess)
+    return bail(e, "hipMalloc(graph pool counter)");
+  if ((rc = alloc_tail(g->tail, n_cells)) != CHEM_OK) { chem_graph_destroy(g); return rc; }
+  if ((rc = alloc_order(g->order, n_cells)) != CHEM_OK) { chem_graph_destroy(g); return rc; }
+  if (stream && (e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess)
+    return bail(e, "hipStreamSynchronize");
+  hipStream_t cs;
+  if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
+    return bail(e, "hipStreamCreate(capture)");
+  // one empty inference launch outside the capture sets the kernel's LDS
+  // attribute, which is a set-up call
+  {
+    surr::InferArgs a0{};
+    a0.n = 0;
+    a0.dt = dt;
+    a0.wpack = s->wpack; a0.bpack = s->bpack; a0.norm = s->norm;
+    if ((e = m->entry->launch_surr_infer(a0, 1, cs)) != hipSuccess ||
+        (e = hipStreamSynchronize(cs)) != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return bail(e, "surrogate_graph_capture set-up");
+    }
+  }
+  if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return bail(e, "hipStreamBeginCapture");
+  }
+  StepBufs b{g->fb_list, g->fb_count, g->d_next, &g->tail, &g->order};
+  rc = enqueue_step(s, m, state, ld, n_cells, dt, trust, true, opts, cs, nullptr, nullptr,
+                    nullptr, nullptr, b, false);
+  e = hipStreamEndCapture(cs, &g->graph);
+  (void)hipStreamDestroy(cs);
+  if (rc) { chem_graph_destroy(g); return rc; }
+  if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
+  if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return bail(e, "hipGraphInstantiate");
+  *out = g;
+  return CHEM_OK;
 }
 
 int surrogate_save(chem_surr s, const char* path) {

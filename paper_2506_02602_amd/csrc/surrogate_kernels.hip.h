@@ -375,6 +375,7 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
   const unsigned short* sW3 = sW2 + S::W2;
   const unsigned short* sW4 = sW3 + S::W2;
   float* sB = reinterpret_cast<float*>(smem + S::WTOT * 2);
+  if (a.n <= 0) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   unsigned char* stage = smem + S::F_OFF + wave * S::STAGE;
   {

@@ -149,3 +149,35 @@ def test_fallback_launch_tuned_on_the_surrogate_step(trained, tmp_path):
     assert np.array_equal(w0[:, ~fb], w1[:, ~fb])       # trusted cells: the network's result
     check_flagged(np.ascontiguousarray(w1[:, fb]), np.ascontiguousarray(w0[:, fb]), m.n_species,
                   "front_hot", label="tuned fallback launch vs default")
+
+
+def test_surrogate_step_captured_in_a_graph(trained):
+    """surrogate_graph_capture: the inference and the FP64 pool over the
+    device-side fallback list replay from one graph.  Every replay (with
+    eager surrogate calls and host synchronisations between replays) gives
+    bitwise the eager step's result, fallback cells included."""
+    import torch
+    from paper_2506_02602_amd import chemgpu as cg, surrogate as sg
+    m, s, trust, _ = trained
+    field, out = sg.inference_field(m, shape=(64, 64, 64), n_traj=128, n_records=200, seed=26,
+                                    out_frac=0.1)
+    opts = cg.make_opts(rtol=1e-8, atol=1e-10)
+    ref = field.clone()
+    tc = torch.zeros(field.shape[1], dtype=torch.int32, device="cuda")
+    n_fb = cg.surrogate_infer(s, m, ref, 1e-7, trust, fallback=True, opts=opts, trust_code=tc,
+                              want_count=True)
+    assert n_fb >= int(out.sum()) * 0.9
+    work = field.clone()
+    g = cg.surrogate_graph_capture(s, m, work, 1e-7, trust, opts)
+    stream = torch.cuda.current_stream()
+    for rep in range(3):
+        work.copy_(field)
+        g.launch(stream)
+        torch.cuda.synchronize()
+        assert torch.equal(work, ref), f"replay {rep}"
+        # eager work on the same handles between replays
+        other = field.clone()
+        cg.surrogate_infer(s, m, other, 1e-7, trust, fallback=True, opts=opts)
+        torch.cuda.synchronize()
+        assert torch.equal(other, ref)
+    g.close()
