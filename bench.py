@@ -129,6 +129,30 @@ def traffic(workload, kernel):
     return rec[1].get(kernel)
 
 
+# Operations per launch of the dominant kernels by hardware counter, from
+# rocprofv3 --pmc runs of this bench: FP64 = 64 lanes x (2 FMA + ADD + MUL +
+# TRANS) per wave instruction of SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 (so
+# masked lanes count too); BF16 MFMA = 512 x SQ_INSTS_VALU_MFMA_MOPS_BF16.
+# Keyed like TRAFFIC; any kernel change nulls it.
+COUNTER_FLOPS = {}
+
+
+def with_counters(roof, workload):
+    """The roofline record with the measured HBM traffic and the executed
+    (counter) operation rate beside the algorithmic one, where figures taken
+    on the current kernels exist; null otherwise."""
+    roof["traffic"] = traffic(workload, roof["kernel"])
+    rec = COUNTER_FLOPS.get(workload)
+    ops = rec[1].get(roof["kernel"]) if rec and rec[0] == kernel_digest() else None
+    if ops is None:
+        roof["counter_achieved"] = roof["counter_frac"] = None
+    else:
+        ach = ops / (roof["launch_ms"] * 1e-3) / 1e12
+        roof["counter_achieved"] = ach
+        roof["counter_frac"] = ach / roof["peak"]
+    return roof
+
+
 WORKLOADS = {
     "surrogate256": "256^3 = 16,777,216 cells: 90% states of held-out stoichiometric H2/O2/N2 "
                     "ignition trajectories in smooth 3-D blobs, 10% reacting-front states (cold "
@@ -388,7 +412,10 @@ def measure_boxes(args, workload, hboxes=None, path=None, steps=None):
         chemgpu.chem_integrate_batched(mech, tboxes, base)
     kt, tstats = timed_kernels(chemgpu, mech, one, max(3, min(K, 10)))
     roof = dominant_fp64(kt, total_steps, tstats["cooperative_steps"], flops_per_step)
-    roof["traffic"] = traffic(workload, roof["kernel"]) if args.scheme == "lsrk" else None
+    if args.scheme == "lsrk":
+        with_counters(roof, workload)
+    else:
+        roof["traffic"] = roof["counter_achieved"] = roof["counter_frac"] = None
     achieved = total_steps * flops_per_step / (kern_ms * 1e-3) / 1e12
     nv = mech.n_species + 1
     out = {
@@ -558,7 +585,7 @@ def surrogate_field(args):
     per_cell = plain_counts.sum(axis=0)
     roof_plain = dominant_fp64(kt_plain, int(per_cell.sum()), tail_plain["cooperative_steps"],
                                flops_per_step)
-    roof_plain["traffic"] = traffic("surrogate256_plain", roof_plain["kernel"])
+    with_counters(roof_plain, "surrogate256_plain")
     plain_ach = int(per_cell.sum()) * flops_per_step / (k_plain * 1e-3) / 1e12
 
     # surrogate + fallback: the step captured in one graph (as the plain
@@ -589,12 +616,13 @@ def surrogate_field(args):
     fb_steps = fcn.view(2, n).cpu().numpy().sum(axis=0)
     roof_fb = dominant_fp64(kt_fb, int(fb_steps[hull].sum()), tail_fb["cooperative_steps"],
                             flops_per_step)
-    roof_fb["traffic"] = traffic("surrogate256_fallback", roof_fb["kernel"])
+    with_counters(roof_fb, "surrogate256_fallback")
     inf_ach = SURROGATE_FLOPS_PER_CELL * n / (k_inf * 1e-3) / 1e12
     roof_inf = {"bound": "mfma", "kernel": "surr_infer", "achieved": inf_ach,
                 "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": inf_ach / PEAK_BF16_MFMA_TFLOPS, "launch_ms": k_inf,
-                "cells_per_launch": n, "traffic": traffic("surrogate256_inference", "surr_infer")}
+                "cells_per_launch": n}
+    with_counters(roof_inf, "surrogate256_inference")
     # the surrogate step's dominant kernel: the longer of the FP64 fallback's
     # dominant kernel and the network
     dom = roof_fb if roof_fb["launch_ms"] >= k_inf else roof_inf
