@@ -543,19 +543,40 @@ def gen_aux(m: dict) -> str:
         aw = m["element_weights"][e]
         coefs.append("{" + ", ".join(lit(s["comp"][e] * aw / s["W"]) for s in sp) + "}")
     L.append("  static constexpr double ELEM[NE][NS] = {" + ", ".join(coefs) + "};")
+    # e/(R T) = sum_k Y_k/W_k (h_k/RT - 1), c_v/R = sum_k Y_k/W_k (cp_k/R - 1)
+    # from the shared powers of T (one coefficient per multiply-add, as in
+    # the RHS's thermo), with the NASA-7 range chosen per wave like there
     L.append("  __device__ __forceinline__ static void energy_cv(double T, const double* Y, "
              "double& e, double& cv) {")
-    L.append("    const double invT = 1.0 / T;")
+    L.append("    const double invT = rcp_nr(T);")
+    L.append("    const double T2 = T * T, T3 = T2 * T, T4 = T3 * T;")
     L.append("    double se = 0.0, sc = 0.0;")
+
+    def block(idx, rng, se="se", sc="sc"):
+        out = []
+        for k in idx:
+            a = sp[k][rng]
+            hm1 = _powsum([a[0] - 1.0, a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5])
+            cpm1 = _powsum([a[0] - 1.0] + list(a[1:5]))
+            out.append(f"      {{ const double yw = Y[{k}] * {lit(1.0 / sp[k]['W'])};")
+            out.append(f"        {se} += yw * ({hm1} + {lit(a[5])} * invT);")
+            out.append(f"        {sc} += yw * ({cpm1}); }}")
+        return out
+    groups: dict = {}
     for k, s in enumerate(sp):
-        iw = lit(1.0 / s["W"])
-        for rng, head in (("lo", f"    if (T < {lit(s['Tmid'])}) {{"), ("hi", "    } else {")):
-            a = s[rng]
-            hm1 = _horner([a[0] - 1.0, a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5], "T")
-            cpm1 = _horner([a[0] - 1.0] + list(a[1:5]), "T")
-            L.append(head)
-            L.append(f"      se += Y[{k}] * {iw} * ({hm1} + {lit(a[5])} * invT);")
-            L.append(f"      sc += Y[{k}] * {iw} * ({cpm1});")
+        groups.setdefault(s["Tmid"], []).append(k)
+    for gi, (tm, idx) in enumerate(groups.items()):
+        L.append(f"    const bool lo{gi} = T < {lit(tm)};")
+        L.append(f"    if (__all(lo{gi})) {{")
+        L += block(idx, "lo")
+        L.append(f"    }} else if (!__any(lo{gi})) {{")
+        L += block(idx, "hi")
+        L.append("    } else {")
+        L.append("      double sel = 0.0, scl = 0.0, seh = 0.0, sch = 0.0;")
+        L += block(idx, "lo", "sel", "scl")
+        L += block(idx, "hi", "seh", "sch")
+        L.append(f"      se += lo{gi} ? sel : seh;")
+        L.append(f"      sc += lo{gi} ? scl : sch;")
         L.append("    }")
     L.append(f"    e = {lit(R_CGS)} * T * se;")
     L.append(f"    cv = {lit(R_CGS)} * sc;")

@@ -12,6 +12,7 @@ struct chem_surr_s {
   bool norm_set = false;
   unsigned short* wpack = nullptr;        // inference layout
   float* bpack = nullptr;
+  double* isd = nullptr;                  // 1 / input scale, FP64 (inference)
   bool packed = false;
   long adam_t = 0;
   // training data (standardised) and per-batch buffers
@@ -168,7 +169,7 @@ hipError_t surr_backward_batch(chem_surr s, int B, hipStream_t st) {
 int surr_pack(chem_surr s, hipStream_t st) {
   const int kc1 = (s->ni + 31) / 32, ot4 = (s->no + 15) / 16;
   hipLaunchKernelGGL(surr::pack_weights, dim3(256), dim3(256), 0, st, s->theta, s->ni, s->no, kc1,
-                     ot4, s->wpack, s->bpack);
+                     ot4, s->wpack, s->bpack, s->norm + s->ni, s->isd);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "launch pack_weights");
   s->packed = true;
@@ -197,7 +198,7 @@ int enqueue_step(chem_surr s, chem_mech m, double* state, int64_t ld, int64_t n_
   if (n_cells <= 0) return CHEM_OK;
   surr::InferArgs a{};
   a.state = state; a.ld = ld; a.n = n_cells; a.dt = dt;
-  a.wpack = s->wpack; a.bpack = s->bpack; a.norm = s->norm;
+  a.wpack = s->wpack; a.bpack = s->bpack; a.norm = s->norm; a.isd = s->isd;
   a.hull_margin = trust[0]; a.elem_tol = trust[1]; a.pos_tol = trust[2]; a.energy_tol = trust[3];
   a.fb_list = fallback ? b.fb_list : nullptr;
   a.fb_count = b.fb_count;
@@ -244,6 +245,7 @@ int surrogate_create(chem_mech mech, int32_t hidden, int32_t depth, uint64_t see
   A(dalloc(&s->norm, 4L * s->ni + 2L * s->no));
   A(dalloc(&s->wpack, surr::packed_weight_elems(kc1, ot4)));
   A(dalloc(&s->bpack, 3 * H + ot4 * 16));
+  A(dalloc(&s->isd, s->ni));
   A(dalloc(&s->sse, 1));
   A(dalloc(&s->fb_count, 1));
   if (e != hipSuccess) { surrogate_free(s); return hip_fail(e, "hipMalloc(surrogate)"); }
@@ -279,7 +281,8 @@ void surrogate_free(chem_surr s) {
   (void)hipDeviceSynchronize();  // teardown: nothing to report an error to
   surr_free_batch(s);
   for (void* p : {(void*)s->theta, (void*)s->m, (void*)s->v, (void*)s->grad, (void*)s->wbf,
-                  (void*)s->norm, (void*)s->wpack, (void*)s->bpack, (void*)s->Xn, (void*)s->Yn,
+                  (void*)s->norm, (void*)s->wpack, (void*)s->bpack, (void*)s->isd,
+                  (void*)s->Xn, (void*)s->Yn,
                   (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count})
     if (p) (void)hipFree(p);
   delete s;
@@ -655,7 +658,7 @@ int surrogate_graph_capture(chem_surr s, chem_mech m, double* state, int64_t ld,
     surr::InferArgs a0{};
     a0.n = 0;
     a0.dt = dt;
-    a0.wpack = s->wpack; a0.bpack = s->bpack; a0.norm = s->norm;
+    a0.wpack = s->wpack; a0.bpack = s->bpack; a0.norm = s->norm; a0.isd = s->isd;
     if ((e = m->entry->launch_surr_infer(a0, 1, cs)) != hipSuccess ||
         (e = hipStreamSynchronize(cs)) != hipSuccess) {
       (void)hipStreamDestroy(cs);

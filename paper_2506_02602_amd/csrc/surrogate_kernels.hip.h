@@ -265,9 +265,13 @@ __host__ __device__ constexpr long packed_weight_elems(int kc1, int ot4) {
 }
 
 // theta (FP32 master, natural layout) -> BF16 packed weights (padded rows,
-// padding zero) + FP32 biases
+// padding zero) + FP32 biases; and the reciprocals of the input scales in
+// FP64 (0 for a constant input), so that the inference standardises with a
+// multiply
 __global__ void pack_weights(const float* theta, int ni, int no, int kc1, int ot4,
-                             unsigned short* wp, float* bp) {
+                             unsigned short* wp, float* bp, const float* sd_in, double* isd) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < ni)
+    isd[threadIdx.x] = sd_in[threadIdx.x] > 0.f ? 1.0 / (double)sd_in[threadIdx.x] : 0.0;
   const int l1 = w1_ld(kc1);
   const long w1 = (long)HID * l1, w2 = (long)HID * kWLd, w4 = (long)ot4 * 16 * kWLd;
   const long oW1 = 0, ob1 = (long)HID * ni, oW2 = ob1 + HID, ob2 = oW2 + (long)HID * HID;
@@ -302,6 +306,7 @@ struct InferArgs {
   double* state; long ld; long n; double dt;
   const unsigned short* wpack; const float* bpack;
   const float* norm;            // mu_in[ni] sd_in[ni] mu_out[no] sd_out[no] zmin[ni] zmax[ni]
+  const double* isd;            // 1 / sd_in (0 where sd_in is 0), FP64
   double hull_margin, elem_tol, pos_tol, energy_tol;
   int32_t* fb_list; unsigned* fb_count;
   int32_t* trust_code; float* out_std;
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(InferShape<M>::THREADS) void surr_infer(InferArgs a
         f[2] = ln_dt;
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
-          const double z = sd_in[k] > 0.f ? (f[k] - (double)mu_in[k]) / (double)sd_in[k] : 0.0;
+          const double z = sd_in[k] > 0.f ? (f[k] - (double)mu_in[k]) * a.isd[k] : 0.0;
           if (!(z >= (double)zmin[k] - a.hull_margin && z <= (double)zmax[k] + a.hull_margin))
             code |= TRUST_HULL;
           f[k] = z;
