@@ -537,6 +537,7 @@ __global__ void prim_to_cons(const double* __restrict__ work, const int8_t* __re
 }  // namespace
 
 #include "surrogate_kernels.hip.h"
+#include "surrogate_train.hip.h"
 
 namespace {
 
@@ -558,6 +559,10 @@ struct MechEntry {
   hipError_t (*launch_surr_infer)(const surr::InferArgs&, int grid, hipStream_t);
   hipError_t (*launch_make_pairs)(const double*, const double*, long, long, double, const double*,
                                   float*, float*, hipStream_t);
+  hipError_t (*launch_train)(const surr::TrainArgs&, int phase, hipStream_t);
+  long train_wtpack_elems;  // the transposed packed weights of the training step
+  int train_w4t_ld;
+  long train_wt4, train_wt2;
 };
 
 // Kernels are instantiated for launch bounds 256 (blocks of 64..256 threads)
@@ -684,7 +689,9 @@ size_t lds_per_lane() {
                        &launch_direct<M>, &launch_persistent<M>, \
                        &launch_coop<M>, &launch_cons_to_prim<M>, &launch_prim_to_cons<M>, \
                        &max_blocks_per_cu<M>, &lds_per_lane<M>, \
-                       &launch_surr_infer<M>, &launch_make_pairs<M>},
+                       &launch_surr_infer<M>, &launch_make_pairs<M>, &launch_train<M>, \
+                       TrainSizes<M>::wtpack_elems, TrainSizes<M>::w4t_ld, TrainSizes<M>::wt4, \
+                       TrainSizes<M>::wt2},
 const MechEntry g_registry[] = {CHEM_FOR_EACH_MECH(CHEM_ENTRY)};
 #undef CHEM_ENTRY
 

@@ -19,10 +19,14 @@ struct chem_surr_s {
   float *Xn = nullptr, *Yn = nullptr;
   long ncap = 0;
   int bcap = 0;
-  unsigned short *X0 = nullptr, *H1 = nullptr, *H2 = nullptr, *H3 = nullptr, *dout = nullptr;
-  unsigned short *dZb1 = nullptr, *dZb2 = nullptr, *dZb3 = nullptr;
-  float *Z1 = nullptr, *Z2 = nullptr, *Z3 = nullptr, *out = nullptr, *Yb = nullptr, *dZ = nullptr;
-  float* part = nullptr;
+  // the generic forward's batch (surrogate_forward)
+  unsigned short *X0 = nullptr, *H1 = nullptr, *H2 = nullptr, *H3 = nullptr;
+  float *Z1 = nullptr, *Z2 = nullptr, *Z3 = nullptr, *out = nullptr, *Yb = nullptr;
+  // the training step's batch (rows padded to a multiple of 32 samples)
+  int tcap = 0;
+  unsigned short *Xfm = nullptr, *Hfm = nullptr, *dZfm = nullptr, *doutfm = nullptr;
+  float* Zd = nullptr;
+  unsigned short* wtpack = nullptr;       // transposed packed weights (backward)
   float* fwd_tmp = nullptr;               // surrogate_forward's standardised chunk
   double* sse = nullptr;
   // the fallback list: the cells failing the trust test, appended by the
@@ -34,8 +38,6 @@ struct chem_surr_s {
 };
 
 namespace {
-
-constexpr int kSplits = 16;
 
 uint64_t splitmix64(uint64_t& x) {
   uint64_t z = (x += 0x9E3779B97F4A7C15ull);
@@ -53,14 +55,39 @@ hipError_t dalloc(T** p, long count) {
 }
 
 void surr_free_batch(chem_surr s) {
-  for (void* p : {(void*)s->X0, (void*)s->H1, (void*)s->H2, (void*)s->H3, (void*)s->dout,
-                  (void*)s->dZb1, (void*)s->dZb2, (void*)s->dZb3, (void*)s->Z1, (void*)s->Z2,
-                  (void*)s->Z3, (void*)s->out, (void*)s->Yb, (void*)s->dZ, (void*)s->part,
-                  (void*)s->fwd_tmp})
+  for (void* p : {(void*)s->X0, (void*)s->H1, (void*)s->H2, (void*)s->H3, (void*)s->Z1,
+                  (void*)s->Z2, (void*)s->Z3, (void*)s->out, (void*)s->Yb, (void*)s->fwd_tmp,
+                  (void*)s->Xfm, (void*)s->Hfm, (void*)s->dZfm, (void*)s->doutfm, (void*)s->Zd})
     if (p) (void)hipFree(p);
-  s->X0 = s->H1 = s->H2 = s->H3 = s->dout = s->dZb1 = s->dZb2 = s->dZb3 = nullptr;
-  s->Z1 = s->Z2 = s->Z3 = s->out = s->Yb = s->dZ = s->part = s->fwd_tmp = nullptr;
+  s->X0 = s->H1 = s->H2 = s->H3 = nullptr;
+  s->Z1 = s->Z2 = s->Z3 = s->out = s->Yb = s->fwd_tmp = nullptr;
+  s->Xfm = s->Hfm = s->dZfm = s->doutfm = nullptr;
+  s->Zd = nullptr;
   s->bcap = 0;
+  s->tcap = 0;
+}
+
+// The training step's buffers for batches of up to B samples.
+int surr_ensure_train(chem_surr s, int B) {
+  const int Bp = (B + 31) / 32 * 32;
+  if (Bp <= s->tcap) return CHEM_OK;
+  for (void* p : {(void*)s->Xfm, (void*)s->Hfm, (void*)s->dZfm, (void*)s->doutfm, (void*)s->Zd})
+    if (p) (void)hipFree(p);
+  s->Xfm = s->Hfm = s->dZfm = s->doutfm = nullptr;
+  s->Zd = nullptr;
+  s->tcap = 0;
+  const long H = surr::HID;
+  const int ni16 = (s->ni + 15) / 16 * 16, no16 = (s->no + 15) / 16 * 16;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+  A(dalloc(&s->Xfm, (long)ni16 * Bp));
+  A(dalloc(&s->Hfm, 3 * H * Bp));
+  A(dalloc(&s->dZfm, 3 * H * Bp));
+  A(dalloc(&s->doutfm, (long)no16 * Bp));
+  A(dalloc(&s->Zd, 3 * H * Bp));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(surrogate training batch)");
+  s->tcap = Bp;
+  return CHEM_OK;
 }
 
 int surr_ensure_batch(chem_surr s, int B) {
@@ -71,12 +98,8 @@ int surr_ensure_batch(chem_surr s, int B) {
   auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
   A(dalloc(&s->X0, (long)B * s->ni));
   A(dalloc(&s->H1, (long)B * H)); A(dalloc(&s->H2, (long)B * H)); A(dalloc(&s->H3, (long)B * H));
-  A(dalloc(&s->dout, (long)B * s->no));
-  A(dalloc(&s->dZb1, (long)B * H)); A(dalloc(&s->dZb2, (long)B * H)); A(dalloc(&s->dZb3, (long)B * H));
   A(dalloc(&s->Z1, (long)B * H)); A(dalloc(&s->Z2, (long)B * H)); A(dalloc(&s->Z3, (long)B * H));
   A(dalloc(&s->out, (long)B * s->no)); A(dalloc(&s->Yb, (long)B * s->no));
-  A(dalloc(&s->dZ, (long)B * H));
-  A(dalloc(&s->part, (long)kSplits * H * std::max<long>(H, std::max(s->ni, s->no))));
   A(dalloc(&s->fwd_tmp, (long)B * s->ni));
   if (e != hipSuccess) { surr_free_batch(s); return hip_fail(e, "hipMalloc(surrogate batch)"); }
   s->bcap = B;
@@ -121,55 +144,42 @@ hipError_t surr_forward_batch(chem_surr s, int B, hipStream_t st) {
   return gemm<surr::EPI_BIAS>(g, 1, st);
 }
 
-// Backward pass of the MSE loss; writes the full gradient into s->grad.
-hipError_t surr_backward_batch(chem_surr s, int B, hipStream_t st) {
-  const int H = surr::HID, ni = s->ni, no = s->no;
-  hipError_t e;
-  hipLaunchKernelGGL(surr::mse_grad, dim3(64), dim3(256), 0, st, s->out, s->Yb, (long)B * no,
-                     2.0f / ((float)B * (float)no), s->dout, s->sse);
-  // output layer
-  {
-    surr::GemmArgs g = gargs(s->dout, 1, no, s->H3, H, 1, no, H, B, s->part, H, 1);
-    g.cz = (long)no * H;
-    if ((e = gemm<surr::EPI_STORE>(g, kSplits, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(surr::reduce_splits, dim3((no * H + 255) / 256), dim3(256), 0, st, s->part,
-                       kSplits, (long)no * H, (long)no * H, s->grad + s->oW4);
-    hipLaunchKernelGGL(surr::colsum_bf16, dim3(no), dim3(256), 0, st, s->dout, (long)B, no,
-                       s->grad + s->ob4);
-  }
-  // dZ3 = (dout W4) * silu'(Z3)
-  {
-    surr::GemmArgs g = gargs(s->dout, no, 1, s->wbf + s->oW4, H, 1, B, H, no, s->dZ, H, 1);
-    g.Cb = s->dZb3; g.sbm = H; g.sbc = 1; g.Z = s->Z3; g.szm = H; g.szn = 1;
-    if ((e = gemm<surr::EPI_DSILU>(g, 1, st)) != hipSuccess) return e;
-  }
-  unsigned short* dZb[3] = {s->dZb1, s->dZb2, s->dZb3};
-  const unsigned short* Hprev[3] = {s->X0, s->H1, s->H2};
-  const float* Zs[3] = {s->Z1, s->Z2, s->Z3};
-  const long oW[3] = {s->oW1, s->oW2, s->oW3}, ob[3] = {s->ob1, s->ob2, s->ob3};
-  for (int l = 2; l >= 0; --l) {
-    const int K = l == 0 ? ni : H;   // width of this layer's input
-    // dW_l = dZ_l^T H_{l-1}
-    surr::GemmArgs g = gargs(dZb[l], 1, H, Hprev[l], K, 1, H, K, B, s->part, K, 1);
-    g.cz = (long)H * K;
-    if ((e = gemm<surr::EPI_STORE>(g, kSplits, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(surr::reduce_splits, dim3((H * K + 255) / 256), dim3(256), 0, st, s->part,
-                       kSplits, (long)H * K, (long)H * K, s->grad + oW[l]);
-    hipLaunchKernelGGL(surr::colsum_bf16, dim3(H), dim3(256), 0, st, dZb[l], (long)B, H,
-                       s->grad + ob[l]);
-    if (l == 0) break;
-    // dZ_{l-1} = (dZ_l W_l) * silu'(Z_{l-1})
-    surr::GemmArgs d = gargs(dZb[l], H, 1, s->wbf + oW[l], H, 1, B, H, H, s->dZ, H, 1);
-    d.Cb = dZb[l - 1]; d.sbm = H; d.sbc = 1; d.Z = Zs[l - 1]; d.szm = H; d.szn = 1;
-    if ((e = gemm<surr::EPI_DSILU>(d, 1, st)) != hipSuccess) return e;
-  }
-  return hipGetLastError();
+// The arguments of the training step's kernels for a batch of B samples:
+// rows (pa ((first + s) mod n) + pb) mod n of Xn / Yn.
+surr::TrainArgs train_args(chem_surr s, const float* Xn, const float* Yn, long n, long first,
+                           unsigned long long pa, unsigned long long pb, int B) {
+  surr::TrainArgs a{};
+  a.Xn = Xn; a.Yn = Yn; a.n = n; a.first = first; a.pa = pa; a.pb = pb;
+  a.B = B; a.Bp = (B + 31) / 32 * 32;
+  a.wpack = s->wpack; a.bpack = s->bpack; a.wtpack = s->wtpack;
+  a.Xfm = s->Xfm; a.Hfm = s->Hfm; a.Zd = s->Zd; a.dZfm = s->dZfm; a.doutfm = s->doutfm;
+  a.sse = s->sse;
+  a.scale = 2.0f / ((float)B * (float)s->no);
+  a.theta = s->theta; a.m = s->m; a.v = s->v; a.grad = s->grad; a.wbf = s->wbf;
+  a.wpack_w = s->wpack; a.bpack_w = s->bpack; a.wtpack_w = s->wtpack;
+  a.oW[0] = s->oW1; a.oW[1] = s->oW2; a.oW[2] = s->oW3; a.oW[3] = s->oW4;
+  a.ob[0] = s->ob1; a.ob[1] = s->ob2; a.ob[2] = s->ob3; a.ob[3] = s->ob4;
+  return a;
+}
+
+// One training step's kernels: forward + loss, backward, weight gradients
+// (and, with a.adam, the Adam update of every parameter).
+hipError_t train_step(chem_surr s, const surr::TrainArgs& a, hipStream_t st) {
+  const MechEntry* en = s->mech->entry;
+  hipError_t e = en->launch_train(a, 0, st);
+  if (e == hipSuccess) e = en->launch_train(a, 1, st);
+  if (e == hipSuccess) e = en->launch_train(a, 2, st);
+  return e;
 }
 
 int surr_pack(chem_surr s, hipStream_t st) {
   const int kc1 = (s->ni + 31) / 32, ot4 = (s->no + 15) / 16;
   hipLaunchKernelGGL(surr::pack_weights, dim3(256), dim3(256), 0, st, s->theta, s->ni, s->no, kc1,
                      ot4, s->wpack, s->bpack, s->norm + s->ni, s->isd);
+  const MechEntry* en = s->mech->entry;
+  hipLaunchKernelGGL(surr::pack_transposed, dim3(256), dim3(256), 0, st, s->theta, s->ni, s->no,
+                     s->oW2, s->oW3, s->oW4, en->train_w4t_ld, en->train_wt4, en->train_wt2,
+                     s->wtpack);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "launch pack_weights");
   s->packed = true;
@@ -246,6 +256,7 @@ int surrogate_create(chem_mech mech, int32_t hidden, int32_t depth, uint64_t see
   A(dalloc(&s->wpack, surr::packed_weight_elems(kc1, ot4)));
   A(dalloc(&s->bpack, 3 * H + ot4 * 16));
   A(dalloc(&s->isd, s->ni));
+  A(dalloc(&s->wtpack, mech->entry->train_wtpack_elems));
   A(dalloc(&s->sse, 1));
   A(dalloc(&s->fb_count, 1));
   if (e != hipSuccess) { surrogate_free(s); return hip_fail(e, "hipMalloc(surrogate)"); }
@@ -282,6 +293,7 @@ void surrogate_free(chem_surr s) {
   surr_free_batch(s);
   for (void* p : {(void*)s->theta, (void*)s->m, (void*)s->v, (void*)s->grad, (void*)s->wbf,
                   (void*)s->norm, (void*)s->wpack, (void*)s->bpack, (void*)s->isd,
+                  (void*)s->wtpack,
                   (void*)s->Xn, (void*)s->Yn,
                   (void*)s->sse, (void*)s->fb_list, (void*)s->fb_count})
     if (p) (void)hipFree(p);
@@ -340,15 +352,14 @@ int surrogate_make_pairs(chem_mech m, const double* before, const double* after,
 int surrogate_grad(chem_surr s, const float* Xn, const float* Yn, int32_t B, float* grad_out,
                    float* loss_host, void* stream) {
   if (!s || !Xn || !Yn || B <= 0) return fail(CHEM_EINVAL, "surrogate_grad: bad argument");
-  int rc = surr_ensure_batch(s, B);
+  int rc = surr_ensure_train(s, B);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMemsetAsync(s->sse, 0, sizeof(double), st);
   if (e != hipSuccess) return hip_fail(e, "surrogate_grad clear");
-  hipLaunchKernelGGL(surr::gather_batch, dim3((B + 255) / 256), dim3(256), 0, st, Xn, Yn, (long)B,
-                     s->ni, s->no, 0L, B, 1ull, 0ull, s->X0, s->Yb);
-  e = surr_forward_batch(s, B, st);
-  if (e == hipSuccess) e = surr_backward_batch(s, B, st);
+  surr::TrainArgs a = train_args(s, Xn, Yn, B, 0, 1ull, 0ull, B);
+  a.adam = 0;
+  e = train_step(s, a, st);
   if (e == hipSuccess && grad_out)
     e = hipMemcpyAsync(grad_out, s->grad, sizeof(float) * s->P, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "surrogate_grad");
@@ -426,7 +437,7 @@ int surrogate_train(chem_surr s, const float* X, const float* Y, int64_t n, int3
     hipLaunchKernelGGL(surr::col_minmax, dim3(s->ni), dim3(256), 0, st, s->Xn, (long)n, s->ni, zmin, zmax);
     s->norm_set = true;
   }
-  int rc = surr_ensure_batch(s, batch);
+  int rc = surr_ensure_train(s, batch);
   if (rc) return rc;
   const long steps = n / batch;
   const long total = steps * (long)epochs;
@@ -443,22 +454,18 @@ int surrogate_train(chem_surr s, const float* X, const float* Y, int64_t n, int3
     }
     if ((e = hipMemsetAsync(s->sse, 0, sizeof(double), st)) != hipSuccess)
       return hip_fail(e, "surrogate_train clear");
+    surr::TrainArgs a = train_args(s, s->Xn, s->Yn, n, 0, pa, pb, batch);
+    a.adam = 1;
+    // the decay rates are the FP32 values the moment updates use; the bias
+    // corrections 1 - beta^t are taken with those same values
+    a.b1 = 0.9f; a.b2 = 0.999f; a.eps = 1e-8f;
     for (long k = 0; k < steps; ++k, ++t) {
-      hipLaunchKernelGGL(surr::gather_batch, dim3((batch + 255) / 256), dim3(256), 0, st, s->Xn, s->Yn,
-                         (long)n, s->ni, s->no, k * batch, batch, pa, pb, s->X0, s->Yb);
-      e = surr_forward_batch(s, batch, st);
-      if (e == hipSuccess) e = surr_backward_batch(s, batch, st);
-      if (e != hipSuccess) return hip_fail(e, "surrogate_train step");
       s->adam_t += 1;
-      const double lr_t = lr * 0.5 * (1.0 + cos(3.14159265358979323846 * (double)t / (double)total));
-      // the decay rates are the FP32 values the moment updates use; the bias
-      // corrections 1 - beta^t are taken with those same values
-      const float b1 = 0.9f, b2 = 0.999f;
-      const float c1 = (float)(1.0 - pow((double)b1, (double)s->adam_t));
-      const float c2 = (float)(1.0 - pow((double)b2, (double)s->adam_t));
-      hipLaunchKernelGGL(surr::adam_update, dim3((unsigned)((s->P + 255) / 256)), dim3(256), 0, st,
-                         s->theta, s->m, s->v, s->grad, s->P, (float)lr_t, b1, b2, c1, c2, 1e-8f,
-                         s->wbf);
+      a.first = k * batch;
+      a.lr = (float)(lr * 0.5 * (1.0 + cos(3.14159265358979323846 * (double)t / (double)total)));
+      a.c1 = (float)(1.0 - pow((double)a.b1, (double)s->adam_t));
+      a.c2 = (float)(1.0 - pow((double)a.b2, (double)s->adam_t));
+      if ((e = train_step(s, a, st)) != hipSuccess) return hip_fail(e, "surrogate_train step");
     }
     if (loss_host) {
       double sse = 0;

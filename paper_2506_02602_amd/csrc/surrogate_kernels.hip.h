@@ -40,16 +40,13 @@ __device__ __forceinline__ float silu_fast(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 
-__device__ __forceinline__ float dsilu_f(float z) {
-  const float s = 1.0f / (1.0f + expf(-z));
-  return s * (1.0f + z * (1.0f - s));
-}
 
-// ----------------------------------------------------------- training GEMM
-// C[M x N] = A[M x K] B[K x N] with BF16 operands addressed by strides; one
-// wave per 16x16 output tile; blockIdx.z splits K (partial sums written to
-// C + z * cz, reduced by a separate kernel).
-enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_DSILU = 3 };
+// ------------------------------------------- the generic forward's GEMM
+// C[M x N] = A[M x K] B[K x N] + bias with BF16 operands addressed by
+// strides, one wave per 16x16 output tile; with EPI_BIAS_SILU also the BF16
+// SiLU of the result (surrogate_forward on raw inputs; the training step
+// has kernels of its own).
+enum { EPI_BIAS_SILU = 1, EPI_BIAS = 2 };
 
 struct GemmArgs {
   const unsigned short* A; long sam, sak;
@@ -58,7 +55,6 @@ struct GemmArgs {
   float* C; long scm, scn, cz;
   unsigned short* Cb; long sbm, sbc;   // BF16 copy of the epilogue result (optional)
   const float* bias;
-  const float* Z; long szm, szn;       // saved pre-activations for EPI_DSILU
   int kper;                            // K range per split (multiple of 32)
 };
 
@@ -90,36 +86,9 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
     if (cm >= g.M || cn >= g.N) continue;
     float v = acc[i];
     if (EPI == EPI_BIAS_SILU || EPI == EPI_BIAS) v += g.bias[cn];
-    if (EPI == EPI_DSILU) v *= dsilu_f(g.Z[cm * g.szm + cn * g.szn]);
     g.C[blockIdx.z * g.cz + cm * g.scm + cn * g.scn] = v;
     if (EPI == EPI_BIAS_SILU) g.Cb[cm * g.sbm + cn * g.sbc] = f2bf(silu_f(v));
-    if (EPI == EPI_DSILU) g.Cb[cm * g.sbm + cn * g.sbc] = f2bf(v);
   }
-}
-
-// sum of `splits` partial [rows x cols] blocks into dst (row-major)
-__global__ void reduce_splits(const float* part, int splits, long stride, long count, float* dst) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  float s = 0.f;
-  for (int k = 0; k < splits; ++k) s += part[k * stride + i];
-  dst[i] = s;
-}
-
-// column sums of a BF16 [rows x cols] matrix (bias gradients); one block per column
-__global__ __launch_bounds__(256) void colsum_bf16(const unsigned short* x, long rows, int cols,
-                                                   float* dst) {
-  __shared__ float red[256];
-  const int c = blockIdx.x;
-  float s = 0.f;
-  for (long r = threadIdx.x; r < rows; r += blockDim.x) s += bf2f(x[r * cols + c]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) dst[c] = red[0];
 }
 
 // batch gather through the epoch's permutation src = (pa * i + pb) mod n
@@ -132,42 +101,6 @@ __global__ void gather_batch(const float* Xn, const float* Yn, long n, int ni, i
   const long src = (long)((pa * (idx % (unsigned long long)n) + pb) % (unsigned long long)n);
   for (int k = 0; k < ni; ++k) X0[(long)rr * ni + k] = f2bf(Xn[src * ni + k]);
   for (int o = 0; o < no; ++o) Yb[(long)rr * no + o] = Yn[src * no + o];
-}
-
-// dL/dout = 2 (out - y) / (B no) as BF16, and the batch's squared error
-__global__ __launch_bounds__(256) void mse_grad(const float* out, const float* y, long count,
-                                                float scale, unsigned short* dout, double* sse) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (long)gridDim.x * blockDim.x) {
-    const float d = out[i] - y[i];
-    dout[i] = f2bf(scale * d);
-    s += (double)d * d;
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicAdd(sse, red[0]);
-}
-
-// Adam on FP32 master weights, then the BF16 copy used by the GEMMs
-__global__ void adam_update(float* theta, float* m, float* v, const float* grad, long P, float lr,
-                            float b1, float b2, float c1, float c2, float eps,
-                            unsigned short* wbf) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  const float g = grad[i];
-  const float mi = b1 * m[i] + (1.f - b1) * g;
-  const float vi = b2 * v[i] + (1.f - b2) * g * g;
-  m[i] = mi;
-  v[i] = vi;
-  const float th = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  theta[i] = th;
-  wbf[i] = f2bf(th);
 }
 
 __global__ void cast_bf16(const float* x, long n, unsigned short* y) {
@@ -247,7 +180,7 @@ __device__ __forceinline__ unsigned short d2bf(double x) {
 // Packed column order of the hidden layers: column c of a packed matrix holds
 // input feature perm(c), so that a layer's MFMA output registers are already
 // the next layer's B operand (no LDS round trip between layers).
-__device__ __forceinline__ int packed_feature(int c) {
+__host__ __device__ constexpr int packed_feature(int c) {
   const int kc = c >> 5, rr = c & 31, gg = rr >> 3, j = rr & 7;
   return 32 * kc + (j < 4 ? 4 * gg + j : 16 + 4 * gg + (j - 4));
 }
