@@ -101,10 +101,18 @@ def parse():
 
 # HBM bytes per launch of the dominant kernels, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE) of this bench, each scaled by what the counter
-# reads for the restore copy of known size in the same run (FETCH_SIZE
-# reports 0.5002 of the copied bytes, WRITE_SIZE 1.000).  Keyed by a digest of
-# the kernel sources the counters were taken on; any change nulls it.
-TRAFFIC = {}
+# reads for the restore copy of known size in the same run (the 256^3 field,
+# 1,572,864 KiB: FETCH_SIZE reports 0.5000 of it, WRITE_SIZE 1.000).  For the
+# per-lane kernel a launch is the flow step's two launches (the persistent
+# kernel and the resumption of the tail list), as for its HIP-event time.
+# Keyed by a digest of the kernel sources the counters were taken on; any
+# change nulls it (profiles/surrogate_mech9_256cubed.md).
+_COUNTED = "e44deffdd291c675"
+TRAFFIC = {
+    "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.5983e9}),
+    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 6.6539e8}),
+    "surrogate256_inference": (_COUNTED, {"surr_infer": 2.9144e9}),
+}
 
 
 def kernel_digest():
@@ -134,7 +142,11 @@ def traffic(workload, kernel):
 # TRANS) per wave instruction of SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 (so
 # masked lanes count too); BF16 MFMA = 512 x SQ_INSTS_VALU_MFMA_MOPS_BF16.
 # Keyed like TRAFFIC; any kernel change nulls it.
-COUNTER_FLOPS = {}
+COUNTER_FLOPS = {
+    "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.6054e11}),
+    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 2.1675e11}),
+    "surrogate256_inference": (_COUNTED, {"surr_infer": 1.3057e12}),
+}
 
 
 def with_counters(roof, workload):
