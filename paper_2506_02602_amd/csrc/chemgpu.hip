@@ -90,22 +90,28 @@ __global__ void eval_math_kernel(int fn, const double* x, double* y, int64_t n) 
 
 __global__ void pool_reset(unsigned long long* next, unsigned int* tail_count,
                            unsigned long long* tail_next, unsigned long long* tail_next2,
-                           unsigned long long* coop_steps) {
-  *next = 0ull;
-  if (tail_count) *tail_count = 0u;
-  if (tail_next) *tail_next = 0ull;
-  if (tail_next2) *tail_next2 = 0ull;
-  if (coop_steps) *coop_steps = 0ull;
+                           unsigned long long* coop_steps, unsigned int* buckets) {
+  if (threadIdx.x == 0) {
+    *next = 0ull;
+    if (tail_count) *tail_count = 0u;
+    if (tail_next) *tail_next = 0ull;
+    if (tail_next2) *tail_next2 = 0ull;
+    if (coop_steps) *coop_steps = 0ull;
+  }
+  if (buckets) buckets[threadIdx.x] = 0u;
 }
 
-// Order of the tail list.  The cooperative kernel's groups claim handed-over
-// cells one after another, so the flow step ends when the group that claimed
-// the longest remaining integration finishes it; claiming the longest first
-// (the longest-processing-time rule of list scheduling) keeps a long cell
-// from starting late.  A cell's remaining work is estimated from its state at
-// the hand-off, in its current step size: rem/h steps for the time rem left
-// in its flow step (all remaining sub-calls); the key buckets that estimate
-// four to an octave, 0 for fewer than two steps, up to kTailBuckets - 1.
+// Order of the tail list.  Handed-over cells are claimed one after another
+// (by the cooperative kernel's groups, or one per lane by the per-lane
+// resumption), so the flow step ends when whoever claimed the longest
+// remaining integration finishes it; claiming the longest first (the
+// longest-processing-time rule of list scheduling) keeps a long cell from
+// starting late, and when the list is resumed one per lane it keeps the
+// launch from draining on long cells claimed last.  A cell's remaining work
+// is estimated from its state at the hand-off, in its current step size:
+// rem/h steps for the time rem left in its flow step (all remaining
+// sub-calls); the key buckets that estimate four to an octave, 0 for fewer
+// than two steps, up to kTailBuckets - 1.
 constexpr int kTailBuckets = 64;
 
 __device__ __forceinline__ int32_t tail_key(double rem, double h) {
@@ -115,35 +121,66 @@ __device__ __forceinline__ int32_t tail_key(double rem, double h) {
   return k >= (double)(kTailBuckets - 1) ? kTailBuckets - 1 : (int32_t)k;
 }
 
-// Which kernel finishes the tail list (one block): when it holds at most
-// tb.cap cells the cooperative kernel takes all of them (split = count) and
-// they are counting-sorted by key into tb.order, largest first; otherwise
-// the per-lane resumption takes all of them (split = 0).  Several lanes per
-// cell only pay while the tail is short next to the chip, and the choice
-// depends only on the list's length, so on the input.  Cells with equal keys
-// keep no particular order: each cell's integration does not depend on when
-// or by which group it runs.
-__global__ __launch_bounds__(1024) void tail_order(TailBuf tb) {
-  __shared__ unsigned int off[kTailBuckets];
+// Counting sort of the tail records by key, largest first, over the whole
+// grid: tail_count adds every block's histogram of its chunk of records to
+// the bucket totals; tail_scatter gives each block a range per bucket (one
+// atomic per bucket and block) and writes the record indices into tb.order.
+// Both read the record count on the device, so a captured launch sequence
+// serves any list length.  tail_scatter also decides which kernel finishes
+// the list: at most tb.cap records go to the cooperative kernel (split =
+// count), more are resumed one per lane (split = 0); several lanes per cell
+// only pay while the list is short next to the chip, and the choice depends
+// only on the list's length, so on the input.  Records with equal keys keep
+// no particular order: a cell's integration does not depend on when or by
+// which lanes it runs.
+constexpr int kSortBlock = 1024;
+constexpr int kSortGridMax = 512;
+
+__device__ __forceinline__ void sort_chunk(unsigned int count, unsigned int& lo, unsigned int& hi) {
+  const unsigned int per = (count + gridDim.x - 1u) / gridDim.x;
+  lo = min(count, blockIdx.x * per);
+  hi = min(count, lo + per);
+}
+
+__global__ __launch_bounds__(kSortBlock) void tail_count(TailBuf tb) {
+  __shared__ unsigned int h[kTailBuckets];
   const unsigned int count = *tb.count;
-  const bool coop = count > 0u && count <= (unsigned int)tb.cap;
-  if (threadIdx.x == 0) *tb.split = coop ? count : 0u;
-  if (!coop) return;
-  for (int k = threadIdx.x; k < kTailBuckets; k += blockDim.x) off[k] = 0u;
+  if (count == 0u) return;
+  for (int k = threadIdx.x; k < kTailBuckets; k += blockDim.x) h[k] = 0u;
   __syncthreads();
-  for (unsigned int r = threadIdx.x; r < count; r += blockDim.x) atomicAdd(&off[tb.key[r]], 1u);
+  unsigned int lo, hi;
+  sort_chunk(count, lo, hi);
+  for (unsigned int r = lo + threadIdx.x; r < hi; r += blockDim.x) atomicAdd(&h[tb.key[r]], 1u);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int run = 0u;
-    for (int k = kTailBuckets - 1; k >= 0; --k) {
-      const unsigned int c = off[k];
-      off[k] = run;
-      run += c;
-    }
+  for (int k = threadIdx.x; k < kTailBuckets; k += blockDim.x)
+    if (h[k]) atomicAdd(&tb.btot[k], h[k]);
+}
+
+__global__ __launch_bounds__(kSortBlock) void tail_scatter(TailBuf tb) {
+  __shared__ unsigned int h[kTailBuckets], base[kTailBuckets];
+  const unsigned int count = *tb.count;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    *tb.split = count > 0u && count <= (unsigned int)tb.cap ? count : 0u;
+  if (count == 0u) return;
+  for (int k = threadIdx.x; k < kTailBuckets; k += blockDim.x) h[k] = 0u;
+  __syncthreads();
+  unsigned int lo, hi;
+  sort_chunk(count, lo, hi);
+  for (unsigned int r = lo + threadIdx.x; r < hi; r += blockDim.x) atomicAdd(&h[tb.key[r]], 1u);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kTailBuckets; k += blockDim.x) {
+    // records in larger buckets come first
+    unsigned int pre = 0u;
+    for (int q = kTailBuckets - 1; q > k; --q) pre += tb.btot[q];
+    base[k] = pre + (h[k] ? atomicAdd(&tb.bcur[k], h[k]) : 0u);
   }
   __syncthreads();
-  for (unsigned int r = threadIdx.x; r < count; r += blockDim.x)
-    tb.order[atomicAdd(&off[tb.key[r]], 1u)] = (int32_t)r;
+  for (int k = threadIdx.x; k < kTailBuckets; k += blockDim.x) h[k] = 0u;
+  __syncthreads();
+  for (unsigned int r = lo + threadIdx.x; r < hi; r += blockDim.x) {
+    const int k = tb.key[r];
+    tb.order[base[k] + atomicAdd(&h[k], 1u)] = (int32_t)r;
+  }
 }
 
 // Pool order.  Blocks claim work items in pool order, so cells that need
@@ -330,16 +367,17 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
       const int64_t g = s_base + (tid - free_from);
       item = -1;
       if (a.resume) {
-        // a cell handed over at tail_steps: its state and hint are in its
-        // rows, its progress in record g
+        // a cell handed over at tail_steps, longest first: its state and
+        // hint are in its rows, its progress in record r
         if (g < total) {
-          item = a.tail.item[g];
+          const int r = a.tail.order[g];
+          item = a.tail.item[r];
           bx = find_box(a, item);
           const BoxDesc& bd = box_ref(a, bx);
           load_cell<M>(bd, cell_index(bd, item), u, rho, h);
-          t = a.tail.t[g];
-          nacc = a.tail.nacc[g]; nrej = a.tail.nrej[g];
-          sub = a.tail.sub[g]; base = a.tail.base[g];
+          t = a.tail.t[r];
+          nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
+          sub = a.tail.sub[r]; base = a.tail.base[r];
         }
       } else if (g < total) {
         item = a.order ? (int64_t)a.order[g] : g;
@@ -617,11 +655,13 @@ hipError_t launch_persistent_s(const PoolArgs& a, int block, int grid, hipStream
 
 template <class M>
 hipError_t launch_persistent(const PoolArgs& a, int block, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(pool_reset, dim3(1), dim3(1), 0, s, a.next,
+  // one lane per key-bucket counter (btot and bcur are adjacent)
+  hipLaunchKernelGGL(pool_reset, dim3(1), dim3(2 * kTailBuckets), 0, s, a.next,
                      a.tail_steps > 0 ? a.tail.count : nullptr,
                      a.tail_steps > 0 ? a.tail.next : nullptr,
                      a.tail_steps > 0 ? a.tail.next2 : nullptr,
-                     a.tail_steps > 0 ? a.tail.coop_steps : nullptr);
+                     a.tail_steps > 0 ? a.tail.coop_steps : nullptr,
+                     a.tail_steps > 0 ? a.tail.btot : nullptr);
   if (a.scheme == SCHEME_ROS4) {
     if constexpr (M::HAS_JAC) {
       if (block > 256) return hipErrorInvalidConfiguration;
@@ -719,9 +759,10 @@ uint64_t fnv1a64(const std::vector<char>& d) {
 struct TailStore {
   void* mem = nullptr;
   int64_t cap = 0;
-  // [next u64][count u32][split u32][next2 u64][coop_steps u64][pad]
+  // [next u64][count u32][split u32][next2 u64][coop_steps u64]
+  // [btot, bcur: kTailBuckets u32 each]
   // [t: cap doubles][item, nacc, nrej, sub, base, key, order: cap int32 each]
-  static constexpr size_t kHead = 32;
+  static constexpr size_t kHead = 32 + 2 * kTailBuckets * sizeof(unsigned int);
   TailBuf view() const {
     TailBuf b{};
     char* p = static_cast<char*>(mem);
@@ -730,6 +771,8 @@ struct TailStore {
     b.split = reinterpret_cast<unsigned int*>(p + 12);
     b.next2 = reinterpret_cast<unsigned long long*>(p + 16);
     b.coop_steps = reinterpret_cast<unsigned long long*>(p + 24);
+    b.btot = reinterpret_cast<unsigned int*>(p + 32);
+    b.bcur = b.btot + kTailBuckets;
     b.t = reinterpret_cast<double*>(p + kHead);
     int32_t* q = reinterpret_cast<int32_t*>(p + kHead + sizeof(double) * cap);
     b.item = q; b.nacc = q + cap; b.nrej = q + 2 * cap; b.sub = q + 3 * cap; b.base = q + 4 * cap;
@@ -989,10 +1032,10 @@ void pick_launch(chem_mech m, int64_t total, const chem_opts* o, int* block, int
 int grid_for(chem_mech m, int block, int64_t total, int scheme);
 
 // The flow step's launches: pool reset + persistent kernel, then, with a
-// hand-off point, tail_order, the cooperative kernel and the per-lane
+// hand-off point, the tail sort, the cooperative kernel and the per-lane
 // resumption of the list (exactly one of the last two does work, chosen by
 // the list's length against a.tail.cap).  Timed calls record m->tev: [0]
-// before the persistent kernel, [1] after it, [2] after tail_order, [3]
+// before the persistent kernel, [1] after it, [2] after the tail sort, [3]
 // after the cooperative kernel, [4] after the resumption.
 hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_t s,
                        const OrderBuf* ob, bool timed = false) {
@@ -1023,8 +1066,14 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
       if ((e = hipEventRecord(tv[k], s)) != hipSuccess) return e;
     return hipSuccess;
   }
-  hipLaunchKernelGGL(tail_order, dim3(1), dim3(1024), 0, s, a.tail);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  {
+    // the records number at most a.total (a cell is handed over once)
+    const int64_t sg = (a.total + 4 * kSortBlock - 1) / (4 * kSortBlock);
+    const unsigned sgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(sg, kSortGridMax));
+    hipLaunchKernelGGL(tail_count, dim3(sgrid), dim3(kSortBlock), 0, s, a.tail);
+    hipLaunchKernelGGL(tail_scatter, dim3(sgrid), dim3(kSortBlock), 0, s, a.tail);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (tv && (e = hipEventRecord(tv[2], s)) != hipSuccess) return e;
   e = m->entry->launch_coop(a, m->n_cu, s);
   if (e != hipSuccess) return e;
@@ -1513,7 +1562,7 @@ int chem_kernel_times(chem_mech m, float* ms, int32_t n) {
   if (!m->timed_last) return fail(CHEM_EINVAL, "chem_kernel_times: no timed call since timing was set");
   hipError_t e = hipEventSynchronize(m->tev[4]);
   if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(kernel timing)");
-  // persistent, tail_order, cooperative, resumption
+  // persistent, tail sort, cooperative, resumption
   for (int k = 0; k < 4; ++k) {
     ms[k] = 0.0f;
     e = hipEventElapsedTime(&ms[k], m->tev[k], m->tev[k + 1]);

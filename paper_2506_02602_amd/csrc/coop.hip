@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
   double* E = smem + C::ND;
   int* I = reinterpret_cast<int*>(smem + C::ND + 64);
   double* scr = smem + C::ND + 64 + C::NI / 2;
-  const unsigned int count = *a.tail.split;  // the records this kernel takes (tail_order)
+  const unsigned int count = *a.tail.split;  // the records this kernel takes (tail_scatter)
   if (count == 0u) return;
   const int tid = threadIdx.x;
   for (int i = tid; i < C::ND; i += blockDim.x) D[i] = C::dtab()[i];

@@ -37,11 +37,13 @@ struct TailBuf {
   int32_t* sub;           // current sub-call
   int32_t* base;          // steps taken before the current sub-call
   int32_t* key;           // bucket of the cell's estimated remaining steps (tail_key)
-  int32_t* order;         // record indices, largest key first (tail_order)
+  int32_t* order;         // record indices, largest key first (tail_count, tail_scatter)
   unsigned int* count;    // records written (zeroed before launch)
   unsigned long long* next;   // records claimed by the cooperative kernel (zeroed)
   unsigned long long* next2;  // records claimed by the per-lane resumption (zeroed)
-  unsigned int* split;    // records the cooperative kernel takes: all or none (tail_order)
+  unsigned int* split;    // records the cooperative kernel takes: all or none (tail_scatter)
+  unsigned int* btot;     // records per key bucket (zeroed before launch)
+  unsigned int* bcur;     // per key bucket: records given a position so far (zeroed)
   unsigned long long* coop_steps;  // steps the cooperative kernel took (zeroed; measurement)
   int cap;                // at most this many records go to the cooperative kernel; more
                           // are resumed one per lane (the count decides, so the choice is
