@@ -371,13 +371,26 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
         // hint are in its rows, its progress in record r
         if (g < total) {
           const int r = a.tail.order[g];
-          item = a.tail.item[r];
-          bx = find_box(a, item);
-          const BoxDesc& bd = box_ref(a, bx);
-          load_cell<M>(bd, cell_index(bd, item), u, rho, h);
-          t = a.tail.t[r];
-          nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
-          sub = a.tail.sub[r]; base = a.tail.base[r];
+          if (a.tail.rec) {
+            using TR = TailRec<M>;
+            const double* rc = a.tail.rec + (int64_t)r * TR::RD;
+#pragma unroll
+            for (int v = 0; v < N1; ++v) u[v] = rc[v];
+            rho = rc[TR::RHO];
+            h = rc[TR::H];
+            t = rc[TR::T];
+            const int* ri = reinterpret_cast<const int*>(rc + TR::INTS);
+            item = ri[0]; nacc = ri[1]; nrej = ri[2]; sub = ri[3]; base = ri[4];
+            bx = find_box(a, item);
+          } else {
+            item = a.tail.item[r];
+            bx = find_box(a, item);
+            const BoxDesc& bd = box_ref(a, bx);
+            load_cell<M>(bd, cell_index(bd, item), u, rho, h);
+            t = a.tail.t[r];
+            nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
+            sub = a.tail.sub[r]; base = a.tail.base[r];
+          }
         }
       } else if (g < total) {
         item = a.order ? (int64_t)a.order[g] : g;
@@ -430,20 +443,32 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
         break;
       }
       if (item >= 0 && a.tail_steps > 0 && nacc + nrej >= a.tail_steps) {
-        // hand the cell to the cooperative kernel: state and hint go to its
-        // own rows, progress to a tail record
-        const int64_t i = cell_index(bd, item);
-        double* s = bd.state;
-#pragma unroll
-        for (int v = 0; v < N1; ++v) s[v * bd.ld + i] = u[v];
-        s[(N1 + 1) * bd.ld + i] = h;
+        // hand the cell over: state, hint and progress to a tail record (or
+        // state and hint to its own rows, progress to the record's fields)
         const unsigned int r = atomicAdd(a.tail.count, 1u);
-        a.tail.item[r] = (int32_t)item;
-        a.tail.t[r] = t;
-        a.tail.nacc[r] = nacc;
-        a.tail.nrej[r] = nrej;
-        a.tail.sub[r] = sub;
-        a.tail.base[r] = base;
+        if (a.tail.rec) {
+          using TR = TailRec<M>;
+          double* rc = a.tail.rec + (int64_t)r * TR::RD;
+#pragma unroll
+          for (int v = 0; v < N1; ++v) rc[v] = u[v];
+          rc[TR::RHO] = rho;
+          rc[TR::H] = h;
+          rc[TR::T] = t;
+          int* ri = reinterpret_cast<int*>(rc + TR::INTS);
+          ri[0] = (int)item; ri[1] = nacc; ri[2] = nrej; ri[3] = sub; ri[4] = base;
+        } else {
+          const int64_t i = cell_index(bd, item);
+          double* s = bd.state;
+#pragma unroll
+          for (int v = 0; v < N1; ++v) s[v * bd.ld + i] = u[v];
+          s[(N1 + 1) * bd.ld + i] = h;
+          a.tail.item[r] = (int32_t)item;
+          a.tail.t[r] = t;
+          a.tail.nacc[r] = nacc;
+          a.tail.nrej[r] = nrej;
+          a.tail.sub[r] = sub;
+          a.tail.base[r] = base;
+        }
         a.tail.key[r] = tail_key((bd.n_sub - sub) * bd.dt - t, h);
         item = -1;
       }
@@ -601,6 +626,7 @@ struct MechEntry {
   long train_wtpack_elems;  // the transposed packed weights of the training step
   int train_w4t_ld;
   long train_wt4, train_wt2;
+  int tail_rd;  // doubles per tail record carrying the state (TailRec)
 };
 
 // Kernels are instantiated for launch bounds 256 (blocks of 64..256 threads)
@@ -731,7 +757,7 @@ size_t lds_per_lane() {
                        &max_blocks_per_cu<M>, &lds_per_lane<M>, \
                        &launch_surr_infer<M>, &launch_make_pairs<M>, &launch_train<M>, \
                        TrainSizes<M>::wtpack_elems, TrainSizes<M>::w4t_ld, TrainSizes<M>::wt4, \
-                       TrainSizes<M>::wt2},
+                       TrainSizes<M>::wt2, TailRec<M>::RD},
 const MechEntry g_registry[] = {CHEM_FOR_EACH_MECH(CHEM_ENTRY)};
 #undef CHEM_ENTRY
 
@@ -759,10 +785,13 @@ uint64_t fnv1a64(const std::vector<char>& d) {
 struct TailStore {
   void* mem = nullptr;
   int64_t cap = 0;
+  int rd = 0;  // doubles per record carrying the state (TailRec<M>::RD), or 0
   // [next u64][count u32][split u32][next2 u64][coop_steps u64]
-  // [btot, bcur: kTailBuckets u32 each]
-  // [t: cap doubles][item, nacc, nrej, sub, base, key, order: cap int32 each]
-  static constexpr size_t kHead = 32 + 2 * kTailBuckets * sizeof(unsigned int);
+  // [btot, bcur: kTailBuckets u32 each][pad to 768 bytes], then
+  // rd > 0: [rec: cap records of rd doubles][key, order: cap int32 each]
+  // rd = 0: [t: cap doubles][item, nacc, nrej, sub, base, key, order: cap int32 each]
+  static constexpr size_t kHead = 768;
+  static_assert(32 + 2 * kTailBuckets * sizeof(unsigned int) <= kHead, "tail head");
   TailBuf view() const {
     TailBuf b{};
     char* p = static_cast<char*>(mem);
@@ -773,14 +802,21 @@ struct TailStore {
     b.coop_steps = reinterpret_cast<unsigned long long*>(p + 24);
     b.btot = reinterpret_cast<unsigned int*>(p + 32);
     b.bcur = b.btot + kTailBuckets;
+    if (rd > 0) {
+      b.rec = reinterpret_cast<double*>(p + kHead);
+      int32_t* q = reinterpret_cast<int32_t*>(p + kHead + sizeof(double) * rd * cap);
+      b.key = q; b.order = q + cap;
+      return b;
+    }
     b.t = reinterpret_cast<double*>(p + kHead);
     int32_t* q = reinterpret_cast<int32_t*>(p + kHead + sizeof(double) * cap);
     b.item = q; b.nacc = q + cap; b.nrej = q + 2 * cap; b.sub = q + 3 * cap; b.base = q + 4 * cap;
     b.key = q + 5 * cap; b.order = q + 6 * cap;
     return b;
   }
-  static constexpr size_t bytes(int64_t cap) {
-    return kHead + (size_t)cap * (sizeof(double) + 7 * sizeof(int32_t));
+  static constexpr size_t bytes(int64_t cap, int rd = 0) {
+    return rd > 0 ? kHead + (size_t)cap * (sizeof(double) * rd + 2 * sizeof(int32_t))
+                  : kHead + (size_t)cap * (sizeof(double) + 7 * sizeof(int32_t));
   }
 };
 
@@ -874,12 +910,16 @@ struct chem_graph_s {
 
 namespace {
 
-int alloc_tail(TailStore& ts, int64_t cap) {
+// Tail records of a workspace or a captured graph: the state travels with
+// each record (rd doubles, the mechanism's TailRec size).
+int alloc_tail(TailStore& ts, int64_t cap, int rd) {
   ts.mem = nullptr;
   ts.cap = 0;
-  hipError_t e = hipMalloc(&ts.mem, TailStore::bytes(cap));
+  ts.rd = 0;
+  hipError_t e = hipMalloc(&ts.mem, TailStore::bytes(cap, rd));
   if (e != hipSuccess) { ts.mem = nullptr; return hip_fail(e, "hipMalloc(tail records)"); }
   ts.cap = cap;
+  ts.rd = rd;
   return CHEM_OK;
 }
 
@@ -1529,7 +1569,8 @@ int chem_workspace_reserve(chem_mech m, int64_t max_cells) {
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize(workspace)");
   free_cell_workspace(m);
   const int64_t cap = std::max<int64_t>(max_cells, 1);
-  if ((rc = alloc_tail(m->tail, cap)) != CHEM_OK || (rc = alloc_order(m->order, cap)) != CHEM_OK) {
+  if ((rc = alloc_tail(m->tail, cap, m->entry->tail_rd)) != CHEM_OK ||
+      (rc = alloc_order(m->order, cap)) != CHEM_OK) {
     free_cell_workspace(m);
     return rc;
   }
@@ -1768,7 +1809,7 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   if (e != hipSuccess) return bail(e, "hipMalloc(graph pool counter)");
   const int tail_steps = pick_tail(m, total, opts);
   if (tail_steps > 0) {
-    rc = alloc_tail(g->tail, total);
+    rc = alloc_tail(g->tail, total, m->entry->tail_rd);
     if (rc) { chem_graph_destroy(g); return rc; }
   }
   const int omode = pick_order(m, total, opts);

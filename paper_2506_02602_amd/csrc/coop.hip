@@ -83,21 +83,34 @@ __global__ __launch_bounds__(256) void lsrk_coop(PoolArgs a) {
       r = __shfl(r, gw * G);  // the group's first lane, within the wave
       if (r >= count) break;
       r = (unsigned int)a.tail.order[r];
-      const int64_t item = a.tail.item[r];
+      using TR = TailRec<M>;
+      const double* rc = a.tail.rec ? a.tail.rec + (int64_t)r * TR::RD : nullptr;
+      const int* ri = rc ? reinterpret_cast<const int*>(rc + TR::INTS) : nullptr;
+      const int64_t item = rc ? ri[0] : a.tail.item[r];
       {
         const BoxDesc& bd = box_ref(a, find_box(a, item));
         i = cell_index(bd, item);
         st = bd.state; ld = bd.ld; nbox = bd.n; dt = bd.dt; n_sub = bd.n_sub;
         status = bd.status; counts = bd.counts;
       }
-      uT = st[i];
-      uk = gl < N ? st[(gl + 1) * ld + i] : 0.0;
-      rho = st[(N + 1) * ld + i];
+      if (rc) {
+        // the state travels with the record; the cell's rows get the result
+        uT = rc[0];
+        uk = gl < N ? rc[gl + 1] : 0.0;
+        rho = rc[TR::RHO];
+        h = rc[TR::H];
+        t = rc[TR::T];
+        nacc = ri[1]; nrej = ri[2]; sub = ri[3]; base = ri[4];
+      } else {
+        uT = st[i];
+        uk = gl < N ? st[(gl + 1) * ld + i] : 0.0;
+        rho = st[(N + 1) * ld + i];
+        h = st[(N + 2) * ld + i];
+        t = a.tail.t[r];
+        nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
+        sub = a.tail.sub[r]; base = a.tail.base[r];
+      }
       inv_rho = 1.0 / rho;
-      h = st[(N + 2) * ld + i];
-      t = a.tail.t[r];
-      nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
-      sub = a.tail.sub[r]; base = a.tail.base[r];
       n0 = nacc + nrej;
       have = true;
     }

@@ -26,10 +26,25 @@ struct BoxDesc {
   const int32_t* index;  // NULL, or the cell index of each of this block's pool items
 };
 
-// Cells handed from the per-lane kernel to the cooperative one, as
-// structure-of-arrays records; the cell's (T, Y) and step hint at time t are
-// in its own state rows.
+// A handed-over cell's record when the state travels with it (TailBuf::rec):
+// doubles T, Y_1..Y_N, rho, h, t, then the ints item, nacc, nrej, sub, base;
+// RD doubles per record, a multiple of 64 bytes, so the claim of a record in
+// key order reads whole cache lines instead of one word from each state row.
+template <class M>
+struct TailRec {
+  static constexpr int N1 = M::NS + 1;
+  static constexpr int RHO = N1, H = N1 + 1, T = N1 + 2, INTS = N1 + 3;
+  static constexpr int RD = (N1 + 6 + 7) / 8 * 8;
+};
+
+// Cells handed from the per-lane kernel to the cooperative one or to its
+// own resumption.  With rec set, each record carries the cell's state and
+// progress (TailRec) and the cell's rows are written only when it finishes;
+// without (the fixed scratch of the allocation-free call), the cell's (T, Y)
+// and step hint at time t go to its own state rows and its progress to the
+// structure-of-arrays fields below.
 struct TailBuf {
+  double* rec;            // NULL, or cap records of TailRec<M>::RD doubles
   int32_t* item;          // pool index
   double* t;              // time reached within the current sub-call
   int32_t* nacc;

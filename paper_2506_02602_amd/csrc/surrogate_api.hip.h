@@ -652,7 +652,7 @@ int surrogate_graph_capture(chem_surr s, chem_mech m, double* state, int64_t ld,
   if ((e = dalloc(&g->fb_count, 1)) != hipSuccess) return bail(e, "hipMalloc(graph list length)");
   if ((e = hipMalloc(&g->d_next, sizeof(unsigned long long))) != hipSuccess)
     return bail(e, "hipMalloc(graph pool counter)");
-  if ((rc = alloc_tail(g->tail, n_cells)) != CHEM_OK) { chem_graph_destroy(g); return rc; }
+  if ((rc = alloc_tail(g->tail, n_cells, m->entry->tail_rd)) != CHEM_OK) { chem_graph_destroy(g); return rc; }
   if ((rc = alloc_order(g->order, n_cells)) != CHEM_OK) { chem_graph_destroy(g); return rc; }
   if (stream && (e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess)
     return bail(e, "hipStreamSynchronize");
