@@ -128,9 +128,11 @@ void chem_mech_free(chem_mech m);
  * max_cells cells (all boxes of a batched call together): the work-pool
  * counter, a ring of 4 box tables of 4096 entries (device memory plus a
  * pinned host staging copy), the tail records through which the per-lane
- * kernel hands long-running cells to the cooperative kernel (36 B per cell),
- * the pool order (8 B per cell) and chem_react_conserved's primitive work
- * state ((N+3) doubles + 1 byte per cell): 141 B per cell for 9 species.
+ * kernel hands long-running cells to the cooperative kernel or its own
+ * resumption (the cell's state and progress, N+7 doubles rounded up to a
+ * multiple of 64 bytes, plus 8 B of sort key and order per cell), the pool
+ * order (8 B per cell) and chem_react_conserved's primitive work state
+ * ((N+3) doubles + 1 byte per cell): 241 B per cell for 9 species.
  * This is the only call that allocates for chem_integrate,
  * chem_integrate_batched and chem_react_conserved; past the reservation they
  * return CHEM_ECAPACITY.  A reservation never shrinks; growing one first
@@ -432,9 +434,9 @@ int surrogate_autotune(chem_surr s, chem_mech m, double *state, int64_t ld, int6
  * follow eager calls on the same handles on one stream; two launches of one
  * graph must not overlap.  It uses the surrogate's weights and the
  * mechanism's tables as they are when launched.  A set-up call: allocates
- * (about 44 B per cell) and synchronises `stream` before capturing on a
- * private stream.  CHEM_EINVAL for null arguments, n_cells <= 0 or
- * ld < n_cells.
+ * (about 148 B per cell for 9 species) and synchronises `stream` before
+ * capturing on a private stream.  CHEM_EINVAL for null arguments,
+ * n_cells <= 0 or ld < n_cells.
  */
 int surrogate_graph_capture(chem_surr s, chem_mech m, double *state, int64_t ld, int64_t n_cells,
                             double dt, const double trust[4], const chem_opts *opts, void *stream,
