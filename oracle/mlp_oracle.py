@@ -5,9 +5,10 @@ chemistry only as future work (Sec. 7) and gives no design, so this follows
 the design the build states for it (12 -> 128 -> 128 -> 128 -> 10 MLP with
 SiLU hidden layers, BF16 GEMM operands with wider accumulation, FP32 master
 weights trained by Adam on an MSE loss over standardised increments, and a
-per-cell trust test).  Parity of this file's arithmetic with the paper is
-therefore unpinned; it is pinned instead to finite differences, to torch's
-bfloat16 conversion and to closed forms of Adam's first step.
+per-cell trust test).  No passage of the paper fixes this arithmetic, so its
+pins are mathematical ones: finite differences of the loss for the backward
+pass, torch's bfloat16 conversion for the rounding points, and closed forms
+of Adam's first step.
 
 Parameter vector layout (FP32 master weights, flat):
     W1 [H, I], b1 [H], W2 [H, H], b2 [H], W3 [H, H], b3 [H], W4 [O, H], b4 [O]
