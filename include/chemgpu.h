@@ -84,7 +84,8 @@ typedef struct {
                             mechanisms of at most 15 species (CHEM_EUNSUPPORTED otherwise)
                             and run with block_size <= 256 (CHEM_EINVAL otherwise) */
     int32_t tail_cap;    /* most handed-over cells per CU that the cooperative kernel takes
-                            (see tail_steps): 0 = tuned default, else 64; < 0 = no limit */
+                            (see tail_steps): 0 = the tuned value (64 when none is tuned),
+                            > 0 = that many, < 0 = no limit */
     int32_t pool_order;  /* 1: before the step, cells expected to take many steps (a step
                             hint below dt/8 over the flow step, or without a usable hint
                             T >= 1000 K) are dealt round-robin over the first work claim of

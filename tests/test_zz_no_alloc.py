@@ -1,8 +1,11 @@
 """chem_integrate_noalloc: the flow step on the library's fixed scratch
 array, for callers that cannot allocate.  Through the C ABI it must give
-bitwise the results of chem_integrate (state, status, counts) on two calls in
-a row, the second on fewer cells, allocate no device memory, and refuse more
-than 1,048,576 cells with CHEM_ECAPACITY."""
+bitwise the results of chem_integrate (state, status, counts) on calls in a
+row -- the second on fewer cells, the third with the tail list resumed one
+cell per lane instead of by the cooperative kernel (the scratch keeps a
+handed-over cell's state in its rows, the workspace in its tail record) --
+allocate no device memory, and refuse more than 1,048,576 cells with
+CHEM_ECAPACITY."""
 import numpy as np
 import pytest
 
@@ -21,11 +24,15 @@ def test_noalloc_matches_chem_integrate_twice(mech9_path):
     small[0, :500] += 1200.0
     o = cg.make_opts(rtol=wl.RTOL, atol=wl.ATOL, block_size=256, chunk_steps=2, tail_steps=4,
                      tail_cap=-1, pool_order=1)
+    # a cap of one cell per CU sends the tail list to the per-lane resumption
+    # (state in tail records for chem_integrate, in the cells' rows here)
+    o_res = cg.make_opts(rtol=wl.RTOL, atol=wl.ATOL, block_size=256, chunk_steps=2, tail_steps=4,
+                         tail_cap=1, pool_order=1)
     ref_m = cg.chem_mech_load(mech9_path)
     m = cg.Mechanism(mech9_path, auto_reserve=False)      # no workspace at all
     try:
         outs = []
-        for k, s0 in enumerate((big, small)):
+        for k, (s0, o) in enumerate(((big, o), (small, o), (big, o_res))):
             n = s0.shape[1]
             res = []
             for which in ("plain", "noalloc"):
@@ -46,8 +53,8 @@ def test_noalloc_matches_chem_integrate_twice(mech9_path):
                 assert np.array_equal(a, b), f"call {k}"
             assert (res[1][1] == 0).all()
             outs.append(res[1])
-            print(f"[noalloc] call {k}: {n} cells bitwise equal to chem_integrate, "
-                  f"{int(res[1][2].sum())} steps", flush=True)
+            print(f"[noalloc] call {k}: {n} cells bitwise equal to chem_integrate "
+                  f"(tail cap {o.tail_cap}), {int(res[1][2].sum())} steps", flush=True)
         # more than the scratch array holds: refused before any work
         over = torch.zeros((m.n_species + 3, cg.NOALLOC_MAX_CELLS + 1), dtype=torch.float64,
                            device="cuda")
