@@ -297,6 +297,40 @@ def test_long_tail_list_without_cap(gmech9, omech9, mech9_path):
                   budget="front_hot", tail_steps=1, tail_cap=-1)
 
 
+def test_tail_list_at_the_cap(chemgpu, gmech9, omech9, mech9_path):
+    """The finisher of the tail list is chosen by its length alone: with a
+    cap of one cell per CU, a list of exactly as many cells as CUs goes to
+    the cooperative kernel (checked against the oracle) and one cell more to
+    the per-lane resumption (bitwise the result of never handing over)."""
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    s0, hot = wl.front_2d(mech9_path, nx=1024, ny=1024, seed=37)
+    hs = np.ascontiguousarray(s0[:, hot])
+    # cells still stepping after one step are handed over with tail_steps=1
+    _, _, cn = run_gpu(gmech9, hs, wl.DT_FLOW, tail_steps=-1)
+    long = np.flatnonzero(cn.sum(axis=0) >= 2)
+    assert long.size > n_cu + 1
+    for extra in (0, 1):
+        sel = np.ascontiguousarray(hs[:, long[:n_cu + extra]])
+        ref, rst, rcn = run_gpu(gmech9, sel, wl.DT_FLOW, tail_steps=-1)
+        chemgpu.chem_set_kernel_timing(gmech9, True)
+        try:
+            g, gst, gcn = run_gpu(gmech9, sel, wl.DT_FLOW, tail_steps=1, tail_cap=1)
+            stats = chemgpu.chem_tail_stats(gmech9)
+        finally:
+            chemgpu.chem_set_kernel_timing(gmech9, False)
+        print(f"[tail cap] {n_cu + extra} cells: {stats}", flush=True)
+        assert stats["handed_over"] == n_cu + extra
+        assert (gst == 0).all()
+        if extra == 0:
+            assert stats["cooperative"] == n_cu and stats["cooperative_steps"] > 0
+            assert_parity(gmech9, omech9, sel, wl.DT_FLOW, label="tail list at the cap",
+                          budget="front_hot", tail_steps=1, tail_cap=1)
+        else:
+            assert stats["cooperative"] == 0 and stats["cooperative_steps"] == 0
+            assert np.array_equal(g, ref) and np.array_equal(gst, rst) and np.array_equal(gcn, rcn)
+
+
 def test_tail_mech32(gmech32, omech32, mech32_path):
     """32 species / 150 reactions through the cooperative kernel (a full wave
     per cell, three reaction rounds per lane)."""
