@@ -67,12 +67,12 @@ __global__ __launch_bounds__(LB) void lsrk_direct(PoolArgs a) {
 
 // -------------------------------------------------------- persistent kernel
 // Per-lane slot in LDS used to pack active cells: u[N1], t, h, rho (doubles)
-// then item, nacc, nrej, sub, base (ints).
+// then item, nacc, nrej, sub, base, box (ints).
 template <class M>
 struct Slots {
   static constexpr int N1 = M::NS + 1;
   static constexpr int ND = N1 + 3;
-  static constexpr int NI = 5;
+  static constexpr int NI = 6;  // item, nacc, nrej, sub, base, box
   static size_t bytes(int block) { return (size_t)block * (ND * sizeof(double) + NI * sizeof(int)); }
 };
 
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   const int B = blockDim.x;
   const int tid = threadIdx.x;
   double* sd = smem;                                       // [ND][B]
-  int* si = reinterpret_cast<int*>(smem + (size_t)ND * B);  // [5][B]
+  int* si = reinterpret_cast<int*>(smem + (size_t)ND * B);  // [6][B]
   __shared__ int s_active;
   __shared__ long long s_base;
   __shared__ int s_take;
@@ -497,6 +497,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
       si[2 * B + rank] = nrej;
       si[3 * B + rank] = sub;
       si[4 * B + rank] = base;
+      si[5 * B + rank] = bx;
     }
     if (tid == 0) {
       int take = 0;
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
       nrej = si[2 * B + tid];
       sub = si[3 * B + tid];
       base = si[4 * B + tid];
-      bx = find_box(a, item);
+      bx = si[5 * B + tid];  // the box travels with the cell: no search
     } else {
       item = -1;
     }
