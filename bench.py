@@ -110,9 +110,9 @@ def parse():
 # profiles/hbm_counters_lsrk_mech9_front1024_stress.md).
 _COUNTED = "bfe4b9178e50344c"
 TRAFFIC = {
-    "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.5510e+09}),
-    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 6.8003e+08}),
-    "surrogate256_inference": (_COUNTED, {"surr_infer": 2.9143e+09}),
+    "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.5521e+09}),
+    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 6.7125e+08}),
+    "surrogate256_inference": (_COUNTED, {"surr_infer": 2.9136e+09}),
     "front": (_COUNTED, {"lsrk_coop": 1.0698e+07}),
     "stress9": (_COUNTED, {"lsrk_persistent": 3.1977e+09}),
 }
@@ -147,7 +147,7 @@ def traffic(workload, kernel):
 # Keyed like TRAFFIC; any kernel change nulls it.
 COUNTER_FLOPS = {
     "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.4838e+11}),
-    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 2.0272e+11}),
+    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 1.9993e+11}),
     "surrogate256_inference": (_COUNTED, {"surr_infer": 1.3057e+12}),
     "front": (_COUNTED, {"lsrk_coop": 2.4615e+10}),
     "stress9": (_COUNTED, {"lsrk_persistent": 1.1583e+12}),
