@@ -1297,9 +1297,10 @@ int tune_search(chem_mech m, const chem_opts& o, int reps, const TimeOne& time_o
   // hand-off only pays when the cap lets the cooperative kernel take the
   // longer list), then the two pool orders, then block and chunk once more
   // at the final hand-off, cap and order.  Each sweep keeps the incumbent
-  // unless a candidate is faster.  Finally the fastest few launches seen
-  // are timed again, round-robin and with more calls each, so that one
-  // noisy trial (a clock ramp, other work on the device) does not decide.
+  // unless a candidate is faster.  Then the fastest few launches seen are
+  // timed again, round-robin and with more calls each, so that one noisy
+  // trial (a clock ramp, other work on the device) does not decide, and the
+  // winner is refined against its one-step neighbours the same way.
   const int blocks[] = {64, 128, 192, 256, 384, 512};
   const int chunks[] = {1, 2, 4, 8, 16, 32, 64};
   const int tails[] = {4, 8, 16, 32, 64, 128, 256, 512, -1};
@@ -1436,6 +1437,68 @@ int tune_search(chem_mech m, const chem_opts& o, int reps, const TimeOne& time_o
           best_cap = top[k].cap; best_order = top[k].ord;
         }
       }
+    }
+  }
+  if (rc == CHEM_OK && seen.size() > 1) {
+    // neighbour refinement: the sweeps change one setting at a time, so a
+    // launch that wins only with two settings changed together can be
+    // missed; the confirmed launch is timed round-robin (as above) against
+    // its neighbours -- the adjacent block, chunk and hand-off values, the
+    // other caps and pool orders -- and replaced by a faster one, at most
+    // kRefineMoves times
+    constexpr int kRefineMoves = 3;
+    auto at = [](const int* arr, int n, int v) {
+      for (int i = 0; i < n; ++i)
+        if (arr[i] == v) return i;
+      return -1;
+    };
+    constexpr int NB = sizeof(blocks) / sizeof(int), NC = sizeof(chunks) / sizeof(int),
+                  NT = sizeof(tails) / sizeof(int), NK = sizeof(caps) / sizeof(int);
+    const int orders[] = {-1, ORDER_DEAL, ORDER_RANGE};
+    for (int move = 0; move < kRefineMoves && rc == CHEM_OK; ++move) {
+      const Seen cur{best_block, best_chunk, best_tail, best_cap, best_order, best_ms};
+      std::vector<Seen> cand{cur};
+      auto add = [&](int b, int c, int tl, int cap, int ord) {
+        if (m->entry->lds_per_lane() * b > 65536) return;
+        if (o.scheme == SCHEME_ROS4 && b > 256) return;
+        for (const Seen& w : cand)
+          if (w.b == b && w.c == c && w.tl == tl && w.cap == cap && w.ord == ord) return;
+        cand.push_back({b, c, tl, cap, ord, 0.0});
+      };
+      const int ib = at(blocks, NB, cur.b), ic = at(chunks, NC, cur.c), it = at(tails, NT, cur.tl);
+      for (int d : {-1, 1}) {
+        if (ib >= 0 && ib + d >= 0 && ib + d < NB) add(blocks[ib + d], cur.c, cur.tl, cur.cap, cur.ord);
+        if (ic >= 0 && ic + d >= 0 && ic + d < NC) add(cur.b, chunks[ic + d], cur.tl, cur.cap, cur.ord);
+        if (tune_tail && it >= 0 && it + d >= 0 && it + d < NT)
+          add(cur.b, cur.c, tails[it + d], cur.cap, cur.ord);
+      }
+      if (tune_cap)
+        for (int k = 0; k < NK; ++k) add(cur.b, cur.c, cur.tl, caps[k], cur.ord);
+      if (o.pool_order == 0 && o.fixed_steps == 0)
+        for (int ord : orders) add(cur.b, cur.c, cur.tl, cur.cap, ord);
+      if (cand.size() < 2) break;
+      std::vector<std::vector<float>> ms(cand.size());
+      for (int r = 0; r < 3 * reps + 1 && rc == CHEM_OK; ++r)
+        for (size_t k = 0; k < cand.size() && rc == CHEM_OK; ++k) {
+          chem_opts t = o;
+          t.block_size = cand[k].b; t.chunk_steps = cand[k].c; t.tail_steps = cand[k].tl;
+          t.tail_cap = cand[k].cap; t.pool_order = cand[k].ord;
+          float el = 0;
+          rc = time_one(t, &el);
+          ms[k].push_back(el);
+        }
+      if (rc != CHEM_OK) break;
+      size_t win = 0;
+      double win_ms = 1e300;
+      for (size_t k = 0; k < cand.size(); ++k) {
+        std::sort(ms[k].begin(), ms[k].end());
+        const double med = ms[k][ms[k].size() / 2];
+        if (med < win_ms) { win_ms = med; win = k; }
+      }
+      best_ms = win_ms;
+      if (win == 0) break;
+      best_block = cand[win].b; best_chunk = cand[win].c; best_tail = cand[win].tl;
+      best_cap = cand[win].cap; best_order = cand[win].ord;
     }
   }
   if (rc != CHEM_OK) return rc;
