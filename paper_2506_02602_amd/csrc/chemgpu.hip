@@ -121,6 +121,24 @@ __device__ __forceinline__ int32_t tail_key(double rem, double h) {
   return k >= (double)(kTailBuckets - 1) ? kTailBuckets - 1 : (int32_t)k;
 }
 
+// Wave priorities for the resumption launch.  When the longest handed-over
+// cell's estimate (the top bucket of the key histogram btot) exceeds the
+// per-lane share of all the estimated steps, the launch ends with its
+// longest cells stepping while most lanes are idle; a wave whose cells have
+// more steps left then issues first on its SIMD (s_setprio) and the others
+// fill its stalls.  Returns the top level's threshold, half the longest
+// estimate, or 0 (off) when the work per lane exceeds the longest cell and
+// the launch is bound by throughput, where priorities only cost issue slots.
+// Scheduling only: no result depends on it.
+__device__ __forceinline__ float resume_priority(const unsigned int* btot, float lanes) {
+  int k = kTailBuckets - 1;
+  while (k > 0 && btot[k] == 0u) --k;
+  float sum = 0.f;
+  for (int j = 0; j <= k; ++j) sum += (float)btot[j] * exp2f(((float)j + 0.5f) * 0.25f);
+  const float top = exp2f((float)(k + 1) * 0.25f);
+  return top >= sum / lanes ? 0.5f * top : 0.f;
+}
+
 // Counting sort of the tail records by key, largest first, over the whole
 // grid: tail_count adds every block's histogram of its chunk of records to
 // the bucket totals; tail_scatter gives each block a range per bucket (one
@@ -353,6 +371,7 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
     const unsigned int cnt = *a.tail.count;
     total = *a.tail.split < cnt ? (int64_t)cnt : 0;
   }
+  const float prio = a.resume ? resume_priority(a.tail.btot, (float)gridDim.x * (float)B) : 0.f;
 
   // claim the first B items
   if (tid == 0) {
@@ -416,6 +435,19 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
           h = initial_h(h, bd.dt);
         }
       }
+    }
+    // ---- priority levels at 1/1, 1/2, 1/4 of the threshold, from the
+    // wave's largest estimate of remaining steps
+    if (prio > 0.f) {
+      float est = 0.f;
+      if (item >= 0) {
+        const BoxDesc& bd = box_ref(a, bx);
+        est = (float)((bd.n_sub - sub) * bd.dt - t) * __builtin_amdgcn_rcpf((float)h);
+      }
+      if (__any(est >= prio)) __builtin_amdgcn_s_setprio(3);
+      else if (__any(est >= 0.5f * prio)) __builtin_amdgcn_s_setprio(2);
+      else if (__any(est >= 0.25f * prio)) __builtin_amdgcn_s_setprio(1);
+      else __builtin_amdgcn_s_setprio(0);
     }
     // ---- run one chunk
     if (item >= 0) {
