@@ -264,14 +264,29 @@ def test_tail_cells_match_oracle(gmech9, omech9, mech9_path, tail):
                   budget="front_hot", tail_steps=tail)
 
 
-@pytest.mark.parametrize("cap", [0, 1])
-def test_long_tail_list_resumes_per_lane(chemgpu, gmech9, mech9_path, cap):
+@pytest.mark.parametrize("tiles,cap", [(2, 0), (2, 1), (48, 0)])
+def test_long_tail_list_resumes_per_lane(chemgpu, gmech9, mech9_path, tiles, cap):
     """More handed-over cells than the cooperative kernel takes (default 64
     per CU, or 1): the list is resumed one cell per lane, bitwise the result
-    of never handing over, and the cooperative kernel takes no step."""
+    of never handing over, and the cooperative kernel takes no step.  Two
+    copies of the front's hot band (~42,000 cells) leave the longest cell
+    far above the work per lane, so the resumption runs with wave
+    priorities; 48 copies (~1 M cells) put the work per lane above the
+    longest cell, where it runs without them."""
+    import torch
     s0, hot = wl.front_2d(mech9_path, nx=1024, ny=1024, seed=37)
-    s1 = np.ascontiguousarray(np.tile(s0[:, hot], (1, 2)))       # ~42,000 stiff cells
+    s1 = np.ascontiguousarray(np.tile(s0[:, hot], (1, tiles)))
     ref, rst, rcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=-1)
+    # the two regimes, in actual steps after the hand-off over the lanes of
+    # two waves per SIMD
+    left = np.maximum(rcn.sum(axis=0).astype(np.int64) - 1, 0)
+    lanes = torch.cuda.get_device_properties(0).multi_processor_count * 4 * 2 * 64
+    print(f"[resume] {s1.shape[1]} cells: longest {left.max()} steps left, "
+          f"{left.sum() / lanes:.1f} per lane", flush=True)
+    if tiles == 2:
+        assert left.max() > 4 * left.sum() / lanes
+    else:
+        assert left.sum() / lanes > left.max()
     chemgpu.chem_set_kernel_timing(gmech9, True)
     try:
         g, gst, gcn = run_gpu(gmech9, s1, wl.DT_FLOW, tail_steps=1, tail_cap=cap)
