@@ -93,9 +93,14 @@ typedef struct {
                             chip; 2: cells below the mechanism's NASA-7 range switch (the
                             T_mid most species share) come first, the others after them,
                             so that few waves hold cells of both ranges (such a wave
-                            evaluates both sets of polynomials); < 0: pool order as laid
-                            out; 0: tuned default, else off; > 2: CHEM_EINVAL.  Changes no
-                            result (cells are independent); uses 8 bytes of workspace per
+                            evaluates both sets of polynomials); 3: as 2, and with a
+                            hand-off point (tail_steps) the first launch takes only the
+                            cells above the switch: the others are stepped by the
+                            per-lane resumption after its tail list, where they fill
+                            the lanes its longest cells leave idle (without a hand-off
+                            point, as 2); < 0: pool order as laid out; 0: tuned
+                            default, else off; > 3: CHEM_EINVAL.  Changes no result
+                            (cells are independent); uses 8 bytes of workspace per
                             cell */
 } chem_opts;
 
@@ -279,7 +284,7 @@ void chem_graph_destroy(chem_graph g);
  * chunk again at the best block; then, if base->tail_steps is 0, tail_steps in {4, 8, 16, 32, 64,
  * 128, 256, 512, never} for the best pair, and, if base->tail_cap is 0 too,
  * the pairs of tail_steps in {4, 8, 16, 32, 64} and tail_cap in {64, 128,
- * 256, no limit}, then, if base->pool_order is 0, each of the two pool orders,
+ * 256, no limit}, then, if base->pool_order is 0, each of the three pool orders,
  * then block and chunk once more at the final hand-off, cap and order (the
  * whole plane when calls take under 50 ms, else chunk, block, chunk).  Each candidate is timed with HIP
  * events on `stream` (median of `reps` launches after one untimed launch);

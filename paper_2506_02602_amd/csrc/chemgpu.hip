@@ -227,12 +227,14 @@ constexpr double kHeavyT = 1000.0;
 
 constexpr int ORDER_DEAL = 1;    // heavy cells dealt over the first claims
 constexpr int ORDER_RANGE = 2;   // cells below the NASA-7 range switch first
+constexpr int ORDER_RANGE_DEFER = 3;  // as ORDER_RANGE; cells below the switch wait for the resumption
 
 struct OrderBuf {
   int32_t* rank;          // per item: rank among class 0 (>= 0) or -(rank among class 1) - 1
   int32_t* order;         // pool position -> item
   unsigned int* counts;   // [0] class 0, [1] class 1 (zeroed before order_rank)
   int mode;               // ORDER_DEAL (class 0 = heavy) or ORDER_RANGE (class 0 = T < t_split)
+  int defer;              // with ORDER_RANGE: class 0 is claimed after the resumption's records
   double t_split;
 };
 
@@ -366,10 +368,19 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
   int nacc = 0, nrej = 0, sub = 0, base = 0;
   int bx = 0;
   int64_t total = a.total_dev ? (int64_t)*a.total_dev : a.total;
+  // with deferred cells: dH of them, at positions [0, dH) of defer_order
+  const int64_t pool_n = a.pool_dev ? (int64_t)*a.pool_dev : total;
+  const int64_t dH = a.defer ? min((int64_t)*a.defer_h, pool_n) : 0;
+  int64_t nrec = 0, off = 0;
   if (a.resume) {
-    // resume the tail records when the cooperative kernel does not take them
+    // resume the tail records when the cooperative kernel does not take
+    // them, then step the deferred cells
     const unsigned int cnt = *a.tail.count;
-    total = *a.tail.split < cnt ? (int64_t)cnt : 0;
+    nrec = *a.tail.split < cnt ? (int64_t)cnt : 0;
+    total = nrec + dH;
+  } else if (a.defer) {
+    off = dH;
+    total = pool_n - dH;
   }
   const float prio = a.resume ? resume_priority(a.tail.btot, (float)gridDim.x * (float)B) : 0.f;
 
@@ -385,10 +396,11 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
     if (tid >= free_from) {
       const int64_t g = s_base + (tid - free_from);
       item = -1;
+      bool fresh = false;
       if (a.resume) {
         // a cell handed over at tail_steps, longest first: its state and
         // hint are in its rows, its progress in record r
-        if (g < total) {
+        if (g < nrec) {
           const int r = a.tail.order[g];
           if (a.tail.rec) {
             using TR = TailRec<M>;
@@ -410,12 +422,17 @@ __global__ __launch_bounds__(LB) void lsrk_persistent(PoolArgs a) {
             nacc = a.tail.nacc[r]; nrej = a.tail.nrej[r];
             sub = a.tail.sub[r]; base = a.tail.base[r];
           }
+        } else if (g < total) {
+          // a deferred cell, not stepped yet
+          item = a.defer_order[g - nrec];
+          fresh = true;
+          if (item < 0 || item >= pool_n) item = -1;
         }
       } else if (g < total) {
-        item = a.order ? (int64_t)a.order[g] : g;
-        if (item < 0 || item >= total) item = -1;
+        item = a.order ? (int64_t)a.order[off + g] : off + g;
+        if (item < 0 || item >= pool_n) item = -1;
       }
-      if (item >= 0 && !a.resume) {
+      if (item >= 0 && (!a.resume || fresh)) {
         bx = find_box(a, item);
         const BoxDesc& bd = box_ref(a, bx);
         const int64_t i = cell_index(bd, item);
@@ -1023,8 +1040,8 @@ int check_opts(const chem_opts* o) {
   if (o->scheme != SCHEME_LSRK && o->scheme != SCHEME_RKF45 && o->scheme != SCHEME_ROS4)
     return fail(CHEM_EINVAL,
                 "chem_opts.scheme must be 0 (LSRK4(3)5), 1 (RKF45) or 2 (Rosenbrock)");
-  if (o->pool_order > 2)
-    return fail(CHEM_EINVAL, "chem_opts.pool_order must be <= 0 (off or tuned), 1 or 2");
+  if (o->pool_order > 3)
+    return fail(CHEM_EINVAL, "chem_opts.pool_order must be <= 0 (off or tuned), 1, 2 or 3");
   if (o->block_size != 0 && (o->block_size % 64 != 0 || o->block_size > 512 || o->block_size < 64))
     return fail(CHEM_EINVAL, "chem_opts.block_size must be a multiple of 64 in [64, 512]");
   return CHEM_OK;
@@ -1077,7 +1094,7 @@ int pick_order(chem_mech m, int64_t total, const chem_opts* o) {
     auto it = m->tuned.find(tuned_key(total, o));
     v = it != m->tuned.end() ? it->second.order : 0;
   }
-  return v == ORDER_DEAL || v == ORDER_RANGE ? v : 0;
+  return v == ORDER_DEAL || v == ORDER_RANGE || v == ORDER_RANGE_DEFER ? v : 0;
 }
 
 int pick_cap(chem_mech m, int64_t total, const chem_opts* o) {
@@ -1114,6 +1131,7 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
                        const OrderBuf* ob, bool timed = false) {
   hipError_t e;
   a.order = nullptr;
+  a.defer = 0;
   hipEvent_t* tv = timed ? m->tev : nullptr;
   if (ob && a.total > 0 && !a.resume) {
     // the pool order (for a pool whose size is counted on the device, the
@@ -1128,6 +1146,11 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
                        *ob);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     a.order = ob->order;
+    if (ob->defer && a.tail_steps > 0) {
+      a.defer = 1;
+      a.defer_h = ob->counts;
+      a.defer_order = ob->order;
+    }
   }
   if (tv && (e = hipEventRecord(tv[0], s)) != hipSuccess) return e;
   e = m->entry->launch_persistent(a, block, grid, s);
@@ -1152,6 +1175,7 @@ hipError_t launch_step(chem_mech m, PoolArgs& a, int block, int grid, hipStream_
   if (e != hipSuccess) return e;
   if (tv && (e = hipEventRecord(tv[3], s)) != hipSuccess) return e;
   PoolArgs r = a;
+  r.pool_dev = a.total_dev;
   r.resume = 1;
   r.tail_steps = 0;
   r.next = a.tail.next2;
@@ -1190,7 +1214,8 @@ int run_pool_with(chem_mech m, PoolArgs& a, const chem_opts* o, hipStream_t s,
     if (!order->mem || a.total > order->cap)
       return fail(CHEM_ECAPACITY, "more cells than the reserved pool order");
     ob = order->view();
-    ob.mode = omode;
+    ob.mode = omode == ORDER_RANGE_DEFER ? ORDER_RANGE : omode;
+    ob.defer = omode == ORDER_RANGE_DEFER;
     ob.t_split = m->entry->t_split;
   }
   timed = timed && m->timing;
@@ -1409,9 +1434,11 @@ int tune_search(chem_mech m, const chem_opts& o, int reps, const TimeOne& time_o
         if (rc == CHEM_OK && !(tl == t0 && cap == k0)) rc = consider(b0, c0, tl, cap, o0);
   }
   if (o.pool_order == 0 && o.fixed_steps == 0) {
-    // the two pool orders at the best launch so far
+    // the three pool orders at the best launch so far
     if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_DEAL);
     if (rc == CHEM_OK) rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_RANGE);
+    if (rc == CHEM_OK && best_tail > 0)
+      rc = consider(best_block, best_chunk, best_tail, best_cap, ORDER_RANGE_DEFER);
   }
   {
     // the hand-off, the cap and the order move the balance between
@@ -1486,7 +1513,7 @@ int tune_search(chem_mech m, const chem_opts& o, int reps, const TimeOne& time_o
     };
     constexpr int NB = sizeof(blocks) / sizeof(int), NC = sizeof(chunks) / sizeof(int),
                   NT = sizeof(tails) / sizeof(int), NK = sizeof(caps) / sizeof(int);
-    const int orders[] = {-1, ORDER_DEAL, ORDER_RANGE};
+    const int orders[] = {-1, ORDER_DEAL, ORDER_RANGE, ORDER_RANGE_DEFER};
     for (int move = 0; move < kRefineMoves && rc == CHEM_OK; ++move) {
       const Seen cur{best_block, best_chunk, best_tail, best_cap, best_order, best_ms};
       std::vector<Seen> cand{cur};
@@ -1942,7 +1969,8 @@ int chem_graph_capture_batched(chem_mech m, const chem_box* boxes, int32_t n_box
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) { (void)hipStreamDestroy(cs); return bail(e, "hipStreamBeginCapture"); }
   OrderBuf ob = ordered ? g->order.view() : OrderBuf{};
-  ob.mode = omode;
+  ob.mode = omode == ORDER_RANGE_DEFER ? ORDER_RANGE : omode;
+  ob.defer = omode == ORDER_RANGE_DEFER;
   ob.t_split = m->entry->t_split;
   hipError_t le = launch_step(m, a, block, grid, cs, ordered ? &ob : nullptr);
   e = hipStreamEndCapture(cs, &g->graph);

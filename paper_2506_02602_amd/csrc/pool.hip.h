@@ -80,6 +80,14 @@ struct PoolArgs {
   int resume;                  // 1: the work items are tail records, resumed one per lane
   int scheme;                  // SCHEME_LSRK, SCHEME_RKF45 or SCHEME_ROS4
   const int32_t* order;        // NULL, or pool position -> work item (order_place)
+  // Deferred cells (pool order 3): the first launch claims only positions
+  // [*defer_h, pool size) of defer_order (the cells above the NASA-7 range
+  // switch); the resumption claims its tail records and then positions
+  // [0, *defer_h) as fresh cells, which it steps to the end.
+  int defer;
+  const unsigned int* defer_h;
+  const int32_t* defer_order;
+  const unsigned int* pool_dev;  // the resumption: the first launch's total_dev
 };
 
 __device__ __forceinline__ int find_box(const PoolArgs& a, int64_t g) {

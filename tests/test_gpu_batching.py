@@ -212,16 +212,17 @@ def test_full_amr_hierarchy_sampled(cg, gm9, omech9, mech9_path, launch):
                   f"full AMR ({launch} launch), sampled")
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("block,chunk,tail", [(512, 8, 32), (256, 2, 16), (128, 1, -1)])
 def test_pool_order_changes_no_result(cg, gm9, mech9_path, block, chunk, tail, mode):
-    """Dealing the hot cells over the first claims (pool_order 1) or grouping
-    the cells by NASA-7 range (pool_order 2) moves cells between blocks and
-    in time, never their arithmetic: state, status and counts are bitwise
-    those of the laid-out order, on the first call (order from temperature)
-    and on a second call (order from the step hints the first one wrote).
-    The field is larger than one round of claims, so the order is really
-    dealt."""
+    """Dealing the hot cells over the first claims (pool_order 1), grouping
+    the cells by NASA-7 range (pool_order 2) or, with a hand-off point,
+    leaving the cells below the range switch to the end of the resumption
+    (pool_order 3) moves cells between blocks and launches and in time,
+    never their arithmetic: state, status and counts are bitwise those of
+    the laid-out order, on the first call (order from temperature) and on a
+    second call (order from the step hints the first one wrote).  The field
+    is larger than one round of claims, so the order is really dealt."""
     import torch
     from gpu_common import run_gpu
     s0, hot = wl.front_2d(mech9_path, nx=512, ny=512, seed=61)
@@ -249,6 +250,13 @@ def test_range_order_on_scattered_temperatures(cg, gm9, mech9_path):
     off = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=-1, **kw)
     on = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=2, **kw)
     assert all(np.array_equal(x, y) for x, y in zip(off, on))
+    # the cells below the switch left to the end of the resumption, which
+    # takes the whole tail list with a cap of one cell per CU (against the
+    # laid-out order with the same cap: the cooperative kernel, which takes
+    # shorter lists, sums in another order)
+    off1 = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=-1, tail_cap=1, **kw)
+    on3 = run_gpu(gm9, s0, wl.DT_FLOW, pool_order=3, tail_cap=1, **kw)
+    assert all(np.array_equal(x, y) for x, y in zip(off1, on3))
     st = torch.from_numpy(s0.copy()).cuda()
     g = cg.chem_graph_capture_batched(gm9, [dict(state=st, dt=wl.DT_FLOW)],
                                       cg.make_opts(pool_order=2, **kw))
@@ -259,7 +267,7 @@ def test_range_order_on_scattered_temperatures(cg, gm9, mech9_path):
         assert np.array_equal(st.cpu().numpy(), off[0]), f"replay {rep}"
     g.close()
     with pytest.raises(cg.ChemError) as e:
-        cg.chem_integrate(gm9, st, wl.DT_FLOW, cg.make_opts(pool_order=3))
+        cg.chem_integrate(gm9, st, wl.DT_FLOW, cg.make_opts(pool_order=4))
     assert e.value.code == -1
 
 

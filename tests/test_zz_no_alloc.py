@@ -3,7 +3,9 @@ array, for callers that cannot allocate.  Through the C ABI it must give
 bitwise the results of chem_integrate (state, status, counts) on calls in a
 row -- the second on fewer cells, the third with the tail list resumed one
 cell per lane instead of by the cooperative kernel (the scratch keeps a
-handed-over cell's state in its rows, the workspace in its tail record) --
+handed-over cell's state in its rows, the workspace in its tail record),
+the fourth with the cells below the NASA-7 range switch stepped after the
+resumed ones --
 allocate no device memory, and refuse more than 1,048,576 cells with
 CHEM_ECAPACITY."""
 import numpy as np
@@ -28,11 +30,15 @@ def test_noalloc_matches_chem_integrate_twice(mech9_path):
     # (state in tail records for chem_integrate, in the cells' rows here)
     o_res = cg.make_opts(rtol=wl.RTOL, atol=wl.ATOL, block_size=256, chunk_steps=2, tail_steps=4,
                          tail_cap=1, pool_order=1)
+    # and with the cells below the NASA-7 range switch left to the end of
+    # the resumption
+    o_def = cg.make_opts(rtol=wl.RTOL, atol=wl.ATOL, block_size=256, chunk_steps=2, tail_steps=4,
+                         tail_cap=1, pool_order=3)
     ref_m = cg.chem_mech_load(mech9_path)
     m = cg.Mechanism(mech9_path, auto_reserve=False)      # no workspace at all
     try:
         outs = []
-        for k, (s0, o) in enumerate(((big, o), (small, o), (big, o_res))):
+        for k, (s0, o) in enumerate(((big, o), (small, o), (big, o_res), (big, o_def))):
             n = s0.shape[1]
             res = []
             for which in ("plain", "noalloc"):
