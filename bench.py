@@ -108,13 +108,13 @@ def parse():
 # Keyed by a digest of the kernel sources the counters were taken on; any
 # change nulls it (profiles/surrogate_mech9_256cubed.md,
 # profiles/hbm_counters_lsrk_mech9_front1024_stress.md).
-_COUNTED = "6d3b32fd4338eab7"
+_COUNTED = "6d92838f03263d5b"
 TRAFFIC = {
-    "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.7121e+09}),
-    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 6.8690e+08}),
-    "surrogate256_inference": (_COUNTED, {"surr_infer": 2.9115e+09}),
-    "front": (_COUNTED, {"lsrk_coop": 1.0715e+07}),
-    "stress9": (_COUNTED, {"lsrk_persistent": 3.1980e+09}),
+    "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.7069e+09}),
+    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 6.8932e+08}),
+    "surrogate256_inference": (_COUNTED, {"surr_infer": 2.9144e+09}),
+    "front": (_COUNTED, {"lsrk_coop": 1.0697e+07}),
+    "stress9": (_COUNTED, {"lsrk_persistent": 3.1985e+09}),
 }
 
 
@@ -146,11 +146,11 @@ def traffic(workload, kernel):
 # masked lanes count too); BF16 MFMA = 512 x SQ_INSTS_VALU_MFMA_MOPS_BF16.
 # Keyed like TRAFFIC; any kernel change nulls it.
 COUNTER_FLOPS = {
-    "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.4548e+11}),
-    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 1.9917e+11}),
+    "surrogate256_plain": (_COUNTED, {"lsrk_persistent": 3.4513e+11}),
+    "surrogate256_fallback": (_COUNTED, {"lsrk_persistent": 1.9865e+11}),
     "surrogate256_inference": (_COUNTED, {"surr_infer": 1.3057e+12}),
-    "front": (_COUNTED, {"lsrk_coop": 2.4613e+10}),
-    "stress9": (_COUNTED, {"lsrk_persistent": 1.1584e+12}),
+    "front": (_COUNTED, {"lsrk_coop": 2.4618e+10}),
+    "stress9": (_COUNTED, {"lsrk_persistent": 1.1582e+12}),
 }
 
 
