@@ -77,7 +77,9 @@ def parse():
                          "(0 = default, < 0 = no limit)")
     ap.add_argument("--pool-order", type=int, default=0,
                     help="deal cells expected to be slow over the first claims (1), group "
-                         "by NASA-7 range (2), keep the pool order (-1), or the tuned choice (0)")
+                         "by NASA-7 range (2), group by range and step the cells below the "
+                         "switch after the resumed ones (3), keep the pool order (-1), or the "
+                         "tuned choice (0)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--workload", default="surrogate256",
